@@ -1,0 +1,329 @@
+"""Seeded synthetic inputs for the rollout, the perception pass and the tests.
+
+This module draws random scenes and agent sets and holds default parameter
+values.  It contains none of the planner's arithmetic: no force law, no
+integration, no cost, no back-projection.  Both the HIP path and the FP64 oracle
+consume what it returns, so it is the only code they share.
+
+Every generator takes a seed and returns FP32 arrays (the precision the HIP path
+computes in); the oracle widens them to FP64 exactly.
+
+Workloads (the paper's scenes exist only as figures, so these stand in for them):
+  config1  1,000 points uniform in a 0.2 m cube centred at (0.5, 0, 0); 8 agents,
+           100 steps; start (0,0,0), goal (1,0,0).
+  config2  10 spheres (r 2-10 cm) and 10 boxes (edges 4-20 cm) in the unit cube,
+           50,000 surface points (allocated by area) with 5 mm Gaussian noise,
+           each object translating at 0.2 m/s; 64 agents, 500 steps.
+  config3  640x480 z-depth image of 20 random boxes on a plane, seen from 1 m
+           above; the rollout uses 256 agents, 1,000 steps on its voxel centres.
+  config4  5 noisy spheres, 20,000 static points; 128 agents with jittered gains,
+           400 steps, C1 taper (for gradients).
+  config5  512 config2-style scenes with uneven N_O / N_a / N_k and Poisson
+           arrival times at 1 kHz.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional
+
+import numpy as np
+
+F32 = np.float32
+
+# ---------------------------------------------------------------------------
+# default parameters (the paper prints no values; the readings are in the design doc)
+MASS = 1.0
+K_A = 400.0
+D_A = 2.0 * math.sqrt(2.0 * K_A * MASS)  # critical damping of the half-kick dynamics
+K_F = 0.01
+R_D = 0.10
+R_OBS = 0.005        # half of the 1 cm voxel
+EPS = 1e-3
+A_MAX = 10.0
+ALPHA = 0.9
+DT = 1e-3
+TAPER_BAND = 0.1     # fraction of r_d over which the C1 taper falls to zero
+
+
+@dataclasses.dataclass
+class Params:
+    dt: float = DT
+    inv_mass: float = 1.0 / MASS
+    eps: float = EPS
+    r_cost: float = R_D
+    w: tuple = (1.0, 1.0, 1.0, 1.0)   # goal, obs, path, smooth
+    a_max: float = A_MAX
+    alpha: float = ALPHA
+    n_steps: int = 100
+    cutoff: int = 0                   # 0 = hard (Alg. 1), 1 = C1 taper
+    taper_band: float = TAPER_BAND
+
+
+@dataclasses.dataclass
+class Agents:
+    k_a: np.ndarray
+    d_a: np.ndarray
+    k_f: np.ndarray
+    r_d: np.ndarray
+    r_a: np.ndarray
+    omega: np.ndarray  # [N_a, 3]
+
+    @property
+    def n(self) -> int:
+        return int(self.k_a.shape[0])
+
+    def subset(self, idx) -> "Agents":
+        idx = np.asarray(idx)
+        return Agents(*(np.ascontiguousarray(getattr(self, f.name)[idx]) for f in dataclasses.fields(self)))
+
+
+@dataclasses.dataclass
+class Scene:
+    x: np.ndarray
+    y: np.ndarray
+    z: np.ndarray
+    r_obs: float = R_OBS
+    seg_begin: Optional[np.ndarray] = None   # int32 [n_seg + 1] or None (static)
+    seg_vel: Optional[np.ndarray] = None     # float32 [n_seg, 3]
+
+    @property
+    def n(self) -> int:
+        return int(self.x.shape[0])
+
+    @property
+    def n_seg(self) -> int:
+        return 0 if self.seg_begin is None else int(self.seg_begin.shape[0] - 1)
+
+
+@dataclasses.dataclass
+class Query:
+    p0: np.ndarray
+    v0: np.ndarray
+    goal: np.ndarray
+    incumbent: int = -1
+
+
+@dataclasses.dataclass
+class Problem:
+    scene: Scene
+    agents: Agents
+    query: Query
+    params: Params
+    name: str = ""
+
+
+@dataclasses.dataclass
+class DepthFrame:
+    depth: np.ndarray     # float32 [h, w], z-depth in metres
+    K: np.ndarray         # float32 [4] fx, fy, cx, cy
+    T_wc: np.ndarray      # float32 [3, 4] camera-to-world rotation | translation
+    box_lo: np.ndarray    # float32 [3] workspace box (voxel grid origin)
+    dims: np.ndarray      # int32 [3] voxel grid dimensions
+    voxel: float = 2 * R_OBS
+
+
+# ---------------------------------------------------------------------------
+def unit_vectors(rng: np.random.Generator, n: int) -> np.ndarray:
+    """n directions uniform on the unit sphere (normalised Gaussian samples)."""
+    v = rng.standard_normal((n, 3))
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    return v
+
+
+def default_agents(rng: np.random.Generator, n: int, jitter: float = 0.0) -> Agents:
+    """Homogeneous circular-field agents; rotation vectors uniform on S^2.
+
+    jitter > 0 multiplies k_a, d_a, k_f by independent U[1 - jitter, 1 + jitter]."""
+    omega = unit_vectors(rng, n)
+    k_a = np.full(n, K_A)
+    d_a = np.full(n, D_A)
+    k_f = np.full(n, K_F)
+    if jitter > 0:
+        k_a = k_a * rng.uniform(1 - jitter, 1 + jitter, n)
+        d_a = d_a * rng.uniform(1 - jitter, 1 + jitter, n)
+        k_f = k_f * rng.uniform(1 - jitter, 1 + jitter, n)
+    return Agents(k_a.astype(F32), d_a.astype(F32), k_f.astype(F32), np.full(n, R_D, F32), np.zeros(n, F32),
+                  omega.astype(F32))
+
+
+def _query(p0, goal, v0=(0.0, 0.0, 0.0)) -> Query:
+    return Query(np.asarray(p0, F32), np.asarray(v0, F32), np.asarray(goal, F32), -1)
+
+
+def _sphere_surface(rng, n, c, r):
+    return np.asarray(c) + r * unit_vectors(rng, n)
+
+
+def _box_surface(rng, n, c, e):
+    """n points uniform on the surface of an axis-aligned box with edges e."""
+    e = np.asarray(e, float)
+    areas = np.array([e[1] * e[2], e[1] * e[2], e[0] * e[2], e[0] * e[2], e[0] * e[1], e[0] * e[1]])
+    face = rng.choice(6, size=n, p=areas / areas.sum())
+    u = rng.uniform(-0.5, 0.5, (n, 3)) * e
+    ax = face // 2
+    sign = np.where(face % 2 == 0, -0.5, 0.5)
+    u[np.arange(n), ax] = sign * e[ax]
+    return np.asarray(c) + u
+
+
+def _allocate(n_total, weights):
+    """Split n_total into integer counts proportional to weights (largest remainder)."""
+    w = np.asarray(weights, float)
+    raw = n_total * w / w.sum()
+    cnt = np.floor(raw).astype(int)
+    rem = n_total - cnt.sum()
+    order = np.argsort(-(raw - cnt), kind="stable")
+    cnt[order[:rem]] += 1
+    return cnt
+
+
+def objects_scene(rng, n_points, n_spheres=10, n_boxes=10, lo=0.15, hi=0.85, sphere_r=(0.02, 0.10),
+                  box_e=(0.04, 0.20), noise=0.005, speed=0.2) -> Scene:
+    """Surface samples of random spheres and boxes; one constant velocity per object.
+
+    Points are stored grouped by object, so the objects are the segments of the
+    scene's segment table."""
+    objs = []
+    for _ in range(n_spheres):
+        c = rng.uniform(lo, hi, 3)
+        r = rng.uniform(*sphere_r)
+        objs.append(("s", c, r, 4 * math.pi * r * r))
+    for _ in range(n_boxes):
+        c = rng.uniform(lo, hi, 3)
+        e = rng.uniform(box_e[0], box_e[1], 3)
+        objs.append(("b", c, e, 2 * (e[0] * e[1] + e[1] * e[2] + e[0] * e[2])))
+    counts = _allocate(n_points, [o[3] for o in objs])
+    pts, begin, vel = [], [0], []
+    for (kind, c, g, _), m in zip(objs, counts):
+        p = _sphere_surface(rng, m, c, g) if kind == "s" else _box_surface(rng, m, c, g)
+        p = p + rng.normal(0.0, noise, p.shape) if noise > 0 else p
+        pts.append(p)
+        begin.append(begin[-1] + m)
+        vel.append(speed * unit_vectors(rng, 1)[0])
+    P = np.concatenate(pts).astype(F32) if pts else np.zeros((0, 3), F32)
+    seg_begin = np.asarray(begin, np.int32)
+    seg_vel = np.asarray(vel, F32).reshape(-1, 3)
+    if speed == 0:
+        seg_begin, seg_vel = None, None
+    return Scene(np.ascontiguousarray(P[:, 0]), np.ascontiguousarray(P[:, 1]), np.ascontiguousarray(P[:, 2]),
+                 R_OBS, seg_begin, seg_vel)
+
+
+# ---------------------------------------------------------------------------
+def config1(seed: int = 0) -> Problem:
+    rng = np.random.default_rng(seed)
+    P = rng.uniform([0.4, -0.1, -0.1], [0.6, 0.1, 0.1], (1000, 3)).astype(F32)
+    scene = Scene(P[:, 0].copy(), P[:, 1].copy(), P[:, 2].copy(), R_OBS)
+    agents = default_agents(rng, 8)
+    return Problem(scene, agents, _query((0, 0, 0), (1, 0, 0)), Params(n_steps=100), "config1")
+
+
+def config2(seed: int = 1, n_points: int = 50_000, n_agents: int = 64, n_steps: int = 500) -> Problem:
+    rng = np.random.default_rng(seed)
+    scene = objects_scene(rng, n_points)
+    agents = default_agents(rng, n_agents)
+    return Problem(scene, agents, _query((0.02, 0.5, 0.5), (0.98, 0.5, 0.5)), Params(n_steps=n_steps), "config2")
+
+
+def _ray_box_depth(dirs, origin, c, e, yaw):
+    """Distance along each unit-z-normalised ray (camera z-depth) to an upright box
+    rotated by yaw about the world z axis; inf where the ray misses."""
+    cy, sy = math.cos(yaw), math.sin(yaw)
+    R = np.array([[cy, -sy, 0], [sy, cy, 0], [0, 0, 1]])
+    o = (origin - c) @ R           # into the box frame (R orthonormal: R^T x = x @ R)
+    d = dirs @ R
+    half = 0.5 * np.asarray(e)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        t1 = (-half - o) / d
+        t2 = (half - o) / d
+    tmin = np.nanmax(np.minimum(t1, t2), axis=1)
+    tmax = np.nanmin(np.maximum(t1, t2), axis=1)
+    hit = (tmax >= tmin) & (tmax > 0)
+    return np.where(hit, np.maximum(tmin, 0.0), np.inf)
+
+
+def config3_frame(seed: int = 2, w: int = 640, h: int = 480, n_boxes: int = 20) -> DepthFrame:
+    """Ray-cast z-depth image of random boxes on the plane z = 0, camera 1 m above
+    looking straight down (camera x = world x, camera y = -world y)."""
+    rng = np.random.default_rng(seed)
+    fx = fy = 525.0
+    cx, cy = (w - 1) / 2.0, (h - 1) / 2.0
+    R_wc = np.diag([1.0, -1.0, -1.0])
+    t_wc = np.array([0.0, 0.0, 1.0])
+    u, v = np.meshgrid(np.arange(w, dtype=float), np.arange(h, dtype=float))
+    rays_c = np.stack([(u - cx) / fx, (v - cy) / fy, np.ones_like(u)], -1).reshape(-1, 3)  # z-depth 1
+    rays_w = rays_c @ R_wc.T
+    depth = np.full(rays_w.shape[0], 1.0)          # plane z = 0 sits at depth 1
+    half_w, half_h = 0.5 * w / fx, 0.5 * h / fy
+    for _ in range(n_boxes):
+        e = rng.uniform(0.05, 0.30, 3)
+        yaw = rng.uniform(0, math.pi)
+        c = np.array([rng.uniform(-half_w + 0.1, half_w - 0.1), rng.uniform(-half_h + 0.1, half_h - 0.1),
+                      0.5 * e[2]])
+        depth = np.minimum(depth, _ray_box_depth(rays_w, t_wc, c, e, yaw))
+    T = np.concatenate([R_wc, t_wc[:, None]], 1)
+    voxel = 2 * R_OBS
+    box_lo = np.array([-0.645, -0.485, -0.015])
+    dims = np.array([130, 98, 40], np.int32)
+    return DepthFrame(depth.reshape(h, w).astype(F32), np.array([fx, fy, cx, cy], F32), T.astype(F32),
+                      box_lo.astype(F32), dims, voxel)
+
+
+def config3_agents(seed: int = 2, n_agents: int = 256, n_steps: int = 1000):
+    rng = np.random.default_rng(seed + 1000)
+    return default_agents(rng, n_agents), _query((-0.5, 0.0, 0.35), (0.5, 0.0, 0.35)), Params(n_steps=n_steps)
+
+
+def config4(seed: int = 3, n_points: int = 20_000, n_agents: int = 128, n_steps: int = 400) -> Problem:
+    rng = np.random.default_rng(seed)
+    objs = [(rng.uniform(0.3, 0.7, 3), rng.uniform(0.05, 0.15)) for _ in range(5)]
+    counts = _allocate(n_points, [r * r for _, r in objs])
+    P = np.concatenate([_sphere_surface(rng, m, c, r) for (c, r), m in zip(objs, counts)])
+    P = (P + rng.normal(0.0, 0.005, P.shape)).astype(F32)
+    scene = Scene(P[:, 0].copy(), P[:, 1].copy(), P[:, 2].copy(), R_OBS)
+    agents = default_agents(rng, n_agents, jitter=0.2)
+    return Problem(scene, agents, _query((0.05, 0.5, 0.5), (0.95, 0.5, 0.5)),
+                   Params(n_steps=n_steps, cutoff=1), "config4")
+
+
+@dataclasses.dataclass
+class Request:
+    problem: Problem
+    arrival_s: float
+
+
+def config5(seed: int = 4, n_scenes: int = 512, rate_hz: float = 1000.0, n_lo: int = 1000, n_hi: int = 200_000,
+            agent_choices=(16, 64, 256), k_lo: int = 100, k_hi: int = 1000) -> List[Request]:
+    """Uneven replanning requests with Poisson arrival times (exponential gaps)."""
+    rng = np.random.default_rng(seed)
+    out, t = [], 0.0
+    for i in range(n_scenes):
+        n_o = int(rng.integers(n_lo, n_hi + 1))
+        n_a = int(rng.choice(agent_choices))
+        n_k = int(rng.integers(k_lo, k_hi + 1))
+        sub = np.random.default_rng([seed, i])
+        scene = objects_scene(sub, n_o)
+        agents = default_agents(sub, n_a)
+        prob = Problem(scene, agents, _query((0.02, 0.5, 0.5), (0.98, 0.5, 0.5)), Params(n_steps=n_k), f"req{i}")
+        out.append(Request(prob, t))
+        t += float(rng.exponential(1.0 / rate_hz))
+    return out
+
+
+def tiny(seed: int, n_points: int = 8, n_agents: int = 4, n_steps: int = 10, moving: bool = False,
+         cutoff: int = 0) -> Problem:
+    """Small random problem for brute-force checks: points near the straight
+    start-goal line so that the cut-off is exercised."""
+    rng = np.random.default_rng(seed)
+    P = np.stack([rng.uniform(0.0, 0.05, n_points), rng.uniform(-0.06, 0.06, n_points),
+                  rng.uniform(-0.06, 0.06, n_points)], 1).astype(F32)
+    seg_begin = seg_vel = None
+    if moving and n_points > 0:
+        cut = np.sort(rng.integers(0, n_points + 1, 2))
+        seg_begin = np.array([0, cut[0], cut[1], n_points], np.int32)
+        seg_vel = (0.2 * unit_vectors(rng, 3)).astype(F32)
+    scene = Scene(P[:, 0].copy(), P[:, 1].copy(), P[:, 2].copy(), R_OBS, seg_begin, seg_vel)
+    agents = default_agents(rng, n_agents)
+    q = _query((0.0, 0.0, 0.0), (0.1, 0.0, 0.0), v0=(0.3, 0.0, 0.0))
+    return Problem(scene, agents, q, Params(n_steps=n_steps, cutoff=cutoff), f"tiny{seed}")

@@ -1,0 +1,17 @@
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X (runs through the C-ABI library on the device)")
+
+
+def pytest_collection_modifyitems(config, items):
+    # GPU tests run last inside any file so that CPU checks report first
+    items.sort(key=lambda it: 1 if it.get_closest_marker("gpu") else 0)

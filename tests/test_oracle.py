@@ -1,0 +1,395 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+None of these checks re-types the oracle's own formulas: each compares it with a
+hand-derived closed form, a physical invariant of the method, an independent
+library routine (matrix powers, k-d tree nearest neighbours, ODE exponentials) or
+a symmetry.  Together they are meant to fail on a dropped term, a wrong sign,
+a wrong index or a transposed operand anywhere in the oracle.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.linalg
+import scipy.spatial
+
+import oracle
+from paper_2606_12579_amd import scenes
+
+KF = 0.01
+
+
+def _problem_from_points(P, agents, p0, goal, v0=(0, 0, 0), n_steps=50, seg_begin=None, seg_vel=None,
+                         r_obs=scenes.R_OBS, cutoff=0):
+    P = np.asarray(P, np.float32).reshape(-1, 3)
+    sc = scenes.Scene(P[:, 0].copy(), P[:, 1].copy(), P[:, 2].copy(), r_obs, seg_begin, seg_vel)
+    q = scenes.Query(np.asarray(p0, np.float32), np.asarray(v0, np.float32), np.asarray(goal, np.float32))
+    return scenes.Problem(sc, agents, q, scenes.Params(n_steps=n_steps, cutoff=cutoff))
+
+
+def _agents(n, **kw):
+    rng = np.random.default_rng(123)
+    ag = scenes.default_agents(rng, n)
+    for k, v in kw.items():
+        setattr(ag, k, np.full_like(getattr(ag, k), v) if np.isscalar(v) else np.asarray(v, np.float32))
+    return ag
+
+
+# --------------------------------------------------------------------------- Eq. (2)/(3), one pair
+def test_pair_worked_example_perpendicular_current():
+    # p = 0, w = (1,0,0), sphere centre (0, 0.1, 0), omega = (0,0,1), R = 0:
+    # d = (0,-0.1,0), n = (0,-1,0), c = omega (already orthogonal to n),
+    # c x w = (0,1,0), (w/|w|) x (c x w) = (0,0,1), rho = 0.1  =>  f = (k_f/0.1) (0,0,1).
+    f, rho = oracle.pair_force([0, 0, 0], [1, 0, 0], [0, 0.1, 0], [0, 0, 1], KF, 0.2, 0.0, 1e-3)
+    assert rho == pytest.approx(0.1, abs=1e-15)
+    np.testing.assert_allclose(f, [0, 0, 10 * KF], atol=1e-15)
+
+
+def test_pair_worked_example_projection_and_speed():
+    # sphere straight below the agent: d = (0,0,0.05), n = (0,0,1); omega = (1,0,1)/sqrt2
+    # => c = omega - n(n.omega) = (1/sqrt2, 0, 0); w = (0,2,0): c x w = (0,0,2/sqrt2),
+    # (w/|w|) x (c x w) = (2/sqrt2, 0, 0); R = 0.005 => rho = 0.045.
+    s2 = math.sqrt(2.0)
+    f, rho = oracle.pair_force([0, 0, 0], [0, 2, 0], [0, 0, -0.05], [1 / s2, 0, 1 / s2], KF, 0.1, 0.005, 1e-3)
+    assert rho == pytest.approx(0.045, rel=1e-14)
+    np.testing.assert_allclose(f, [KF / 0.045 * 2 / s2, 0, 0], rtol=1e-13, atol=1e-16)
+    # omega parallel to n: the current vanishes, so does the force
+    f, _ = oracle.pair_force([0, 0, 0], [0, 2, 0], [0, 0, -0.05], [0, 0, 1], KF, 0.1, 0.005, 1e-3)
+    np.testing.assert_allclose(f, 0, atol=1e-18)
+
+
+def test_pair_clamp_cutoff_and_degenerate_cases():
+    # inside the inflated sphere: rho clamps to eps (Alg. 1's max(., eps))
+    f, rho = oracle.pair_force([0, 0, 0], [1, 0, 0], [0, 0.003, 0], [0, 0, 1], KF, 0.1, 0.005, 1e-3)
+    assert rho == 1e-3
+    np.testing.assert_allclose(f, [0, 0, KF / 1e-3], rtol=1e-14)
+    # hard cut-off keeps rho <= r_d and drops rho > r_d
+    f_in, rho = oracle.pair_force([0, 0, 0], [1, 0, 0], [0, 0.125, 0], [0, 0, 1], KF, 0.125, 0.0, 1e-3)
+    assert rho == 0.125 and f_in[2] > 0
+    f_out, _ = oracle.pair_force([0, 0, 0], [1, 0, 0], [0, 0.125, 0], [0, 0, 1], KF, 0.12499999, 0.0, 1e-3)
+    np.testing.assert_array_equal(f_out, 0)
+    # zero relative velocity: no force;  agent on the centre: n = 0, c = omega
+    f, _ = oracle.pair_force([0, 0, 0], [0, 0, 0], [0, 0.05, 0], [0, 0, 1], KF, 0.1, 0.0, 1e-3)
+    np.testing.assert_array_equal(f, 0)
+    f, rho = oracle.pair_force([0.3, 0, 0], [0, 1, 0], [0.3, 0, 0], [0, 0, 1], KF, 0.1, 0.0, 1e-3)
+    assert rho == 1e-3
+    # c = omega = (0,0,1), w = (0,1,0): c x w = (-1,0,0), (w/|w|) x (c x w) = (0,0,1), rho = eps
+    np.testing.assert_allclose(f, [0, 0, KF / 1e-3], rtol=1e-14)
+
+
+def test_taper_closed_form():
+    # C1 smoothstep s^2 (3 - 2 s), s = (r_d - rho)/(band r_d): value 1/2 at mid-band, 1 inside, 0 at r_d
+    r_d, band = 0.1, 0.1
+    for rho, sig in [(0.095, 0.5), (0.09, 1.0), (0.05, 1.0), (0.1, 0.0), (0.0975, 0.15625)]:
+        f, r = oracle.pair_force([0, 0, 0], [1, 0, 0], [0, rho, 0], [0, 0, 1], KF, r_d, 0.0, 1e-3, cutoff=1,
+                                 band=band)
+        assert f[2] == pytest.approx(sig * KF / rho, rel=1e-12, abs=1e-18)
+
+
+def test_pair_invariants_random():
+    """f . w = 0 (no work), |f| <= k_f |w| |omega| / rho, evenness in d and in w."""
+    rng = np.random.default_rng(7)
+    for _ in range(200):
+        p, q = rng.normal(size=3) * 0.05, rng.normal(size=3) * 0.05
+        w, om = rng.normal(size=3), rng.normal(size=3)
+        f, rho = oracle.pair_force(p, w, q, om, KF, 1.0, 0.005, 1e-3)
+        assert abs(np.dot(f, w)) <= 1e-12 * np.linalg.norm(f) * np.linalg.norm(w) + 1e-300
+        assert np.linalg.norm(f) <= KF * np.linalg.norm(w) * np.linalg.norm(om) / rho * (1 + 1e-12)
+        f2, _ = oracle.pair_force(p, -w, q, om, KF, 1.0, 0.005, 1e-3)
+        f3, _ = oracle.pair_force(p, w, 2 * p - q, om, KF, 1.0, 0.005, 1e-3)   # d -> -d
+        np.testing.assert_allclose(f2, f, rtol=1e-12, atol=1e-15)
+        np.testing.assert_allclose(f3, f, rtol=1e-12, atol=1e-15)
+        # the force is orthogonal to w and depends on omega only through its part
+        # orthogonal to n: adding a multiple of n to omega changes nothing
+        d = p - q
+        n = d / np.linalg.norm(d)
+        f4, _ = oracle.pair_force(p, w, q, om + 3.7 * n, KF, 1.0, 0.005, 1e-3)
+        np.testing.assert_allclose(f4, f, rtol=1e-10, atol=1e-13)
+
+
+# --------------------------------------------------------------------------- Alg. 1 sums
+def test_repulsion_linear_in_points():
+    """Duplicating every sphere doubles the force and keeps rho_min."""
+    pb = scenes.tiny(3, n_points=16, n_agents=4)
+    rng = np.random.default_rng(0)
+    p = rng.uniform(-0.02, 0.06, (4, 3))
+    v = rng.normal(size=(4, 3))
+    r1 = oracle.repulsion(pb, p, v, 0.0)
+    sc = pb.scene
+    pb2 = _problem_from_points(np.concatenate([np.stack([sc.x, sc.y, sc.z], 1)] * 2), pb.agents, [0, 0, 0],
+                               [1, 0, 0])
+    r2 = oracle.repulsion(pb2, p, v, 0.0)
+    np.testing.assert_allclose(r2.force, 2 * r1.force, rtol=1e-12, atol=1e-15)
+    np.testing.assert_array_equal(r2.rho_min, r1.rho_min)
+
+
+def test_min_distance_matches_kdtree():
+    """rho_min^(k) = max(nearest-centre distance - (r_O + r_a), eps): checked with scipy's k-d tree."""
+    pb = scenes.config1()
+    pb.params.n_steps = 60
+    res = oracle.rollout(pb)
+    P = np.stack([pb.scene.x, pb.scene.y, pb.scene.z], 1).astype(np.float64)
+    tree = scipy.spatial.cKDTree(P)
+    R = float(np.float32(pb.scene.r_obs)) + pb.agents.r_a.astype(np.float64)[:, None]
+    dist, _ = tree.query(res.traj[:, :-1].reshape(-1, 3))
+    expect = np.maximum(dist.reshape(res.min_clear.shape) - R, np.float32(pb.params.eps))
+    np.testing.assert_allclose(res.min_clear, expect, rtol=1e-13, atol=1e-16)
+
+
+def test_min_distance_moving_segments_bruteforce():
+    """Moving obstacles: sphere j sits at q_j + t_k v_seg(j), t_k = (k-1) dt."""
+    pb = scenes.tiny(11, n_points=12, n_agents=3, n_steps=8, moving=True)
+    res = oracle.rollout(pb)
+    sc = pb.scene
+    Q = np.stack([sc.x, sc.y, sc.z], 1).astype(np.float64)
+    V = np.zeros_like(Q)
+    for s in range(sc.n_seg):
+        V[sc.seg_begin[s]:sc.seg_begin[s + 1]] = sc.seg_vel[s]
+    dt = float(np.float32(pb.params.dt))
+    for k in range(1, pb.params.n_steps + 1):
+        tree = scipy.spatial.cKDTree(Q + (k - 1) * dt * V)
+        dist, _ = tree.query(res.traj[:, k - 1])
+        expect = np.maximum(dist - (float(np.float32(sc.r_obs)) + pb.agents.r_a), float(np.float32(1e-3)))
+        np.testing.assert_allclose(res.min_clear[:, k - 1], expect, rtol=1e-13)
+
+
+# --------------------------------------------------------------------------- Eqs. (6)-(11)
+def _attractive_closed_form(pb):
+    """Per axis, e_k = x_k - g and v_{k-1} follow s_{k+1} = M s_k with
+    M = [[1 - dt^2 k/2m, dt (1 - dt d/2m)], [-dt k/2m, 1 - dt d/2m]]; powers of M by numpy."""
+    prm = pb.params
+    dt, invm = float(np.float32(prm.dt)), float(np.float32(prm.inv_mass))
+    out = []
+    for i in range(pb.agents.n):
+        k, d = float(pb.agents.k_a[i]), float(pb.agents.d_a[i])
+        h = 0.5 * dt * invm
+        M = np.array([[1 - dt * h * k, dt * (1 - h * d)], [-h * k, 1 - h * d]])
+        e0 = pb.query.p0.astype(np.float64) - pb.query.goal.astype(np.float64)
+        s = np.stack([e0, pb.query.v0.astype(np.float64)])   # [2, 3]
+        traj = [np.linalg.matrix_power(M, n) @ s for n in range(prm.n_steps + 1)]
+        out.append(np.stack([t[0] for t in traj]) + pb.query.goal.astype(np.float64))
+    return np.stack(out)
+
+
+def test_attractive_only_matches_matrix_power():
+    ag = _agents(3, k_a=[400.0, 100.0, 900.0], d_a=[56.5685, 5.0, 30.0])
+    pb = _problem_from_points(np.zeros((0, 3)), ag, [0.1, -0.2, 0.3], [1.0, 0.5, -0.25], v0=[0.3, 0.0, -0.1],
+                              n_steps=300)
+    res = oracle.rollout(pb)
+    np.testing.assert_allclose(res.traj, _attractive_closed_form(pb), rtol=0, atol=1e-12)
+    # k_f = 0 with obstacles present is the same motion
+    pb2 = scenes.config1()
+    pb2.agents.k_f[:] = 0
+    pb2.params.n_steps = 100
+    res2 = oracle.rollout(pb2)
+    np.testing.assert_allclose(res2.traj, _attractive_closed_form(pb2), rtol=0, atol=1e-12)
+
+
+def test_attractive_converges_to_continuous_damped_oscillator():
+    """The scheme integrates xdd = (k (g - x) - d xd) / (2m) (Eq. 10 keeps its 1/2);
+    halving dt halves the error at a fixed time (first order)."""
+    ag = _agents(1, k_a=400.0, d_a=20.0)
+    T = 0.2
+    errs = []
+    for dt in (1e-3, 5e-4, 2.5e-4):
+        pb = _problem_from_points(np.zeros((0, 3)), ag, [0, 0, 0], [1, 0, 0], n_steps=int(round(T / dt)))
+        pb.params.dt = dt
+        res = oracle.rollout(pb)
+        dt32 = float(np.float32(dt))
+        n = pb.params.n_steps
+        A = np.array([[0, 1], [-400.0 / 2, -20.0 / 2]])
+        e = scipy.linalg.expm(A * n * dt32) @ np.array([-1.0, 0.0])
+        errs.append(abs(res.traj[0, n, 0] - (1.0 + e[0])))
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 1.8 < r1 < 2.2 and 1.8 < r2 < 2.2, errs
+
+
+def test_circular_field_does_no_work():
+    """k_a = d_a = 0, static spheres: F is orthogonal to v^(k-1), so
+    |v^(k)|^2 = |v^(k-1)|^2 + (dt/2m)^2 |F^(k)|^2 exactly (discrete energy identity)."""
+    pb = scenes.config1()
+    pb.agents.k_a[:] = 0
+    pb.agents.d_a[:] = 0
+    pb.query.v0[:] = [1.5, 0.1, -0.05]
+    pb.params.n_steps = 400
+    res = oracle.rollout(pb)
+    h = 0.5 * float(np.float32(pb.params.dt)) * float(np.float32(pb.params.inv_mass))
+    v2 = np.sum(res.vel ** 2, -1)
+    lhs = v2[:, 1:] - v2[:, :-1]
+    rhs = h * h * np.sum(res.ftot ** 2, -1)
+    assert np.abs(res.force).max() > 10.0   # the field really acts
+    np.testing.assert_allclose(lhs, rhs, rtol=1e-7, atol=1e-12 * v2.max())
+    # per step the work term 2 h v^(k-1).F^(k) vanishes
+    work = np.sum(res.vel[:, :-1] * res.ftot, -1)
+    assert np.abs(work).max() <= 1e-11 * np.abs(res.ftot).max()
+
+
+def test_jerk_identity():
+    """Delta^3 p^(k) = (dt^2/2m)(F^(k-1) - F^(k-2)) under the explicit half-kick scheme."""
+    pb = scenes.config1()
+    res = oracle.rollout(pb)
+    dt, invm = float(np.float32(pb.params.dt)), float(np.float32(pb.params.inv_mass))
+    p = res.traj
+    d3 = p[:, 3:-1] - 3 * p[:, 2:-2] + 3 * p[:, 1:-3] - p[:, :-4]            # k = 4..N
+    ident = 0.5 * dt * dt * invm * (res.ftot[:, 2:-1] - res.ftot[:, 1:-2])  # F^(k-1) - F^(k-2)
+    np.testing.assert_allclose(d3, ident, rtol=0, atol=1e-9 * np.abs(ident).max())
+
+
+# --------------------------------------------------------------------------- Eqs. (16)-(20)
+def test_costs_straight_constant_velocity():
+    N, dt = 80, 1e-3
+    prm = scenes.Params(n_steps=N, dt=dt)
+    dt = float(np.float32(dt))
+    u = np.array([0.6, 0.0, 0.8])
+    p0 = np.array([0.1, 0.2, 0.3])
+    pos = p0 + np.arange(N)[:, None] * dt * u
+    goal = p0 + (N - 1) * dt * u
+    c = oracle.costs(pos, np.full(N, 1.0), goal, prm)
+    rc = float(np.float32(prm.r_cost))
+    assert c[0] == pytest.approx(dt * (N - 1) / (2 * rc), rel=1e-12)   # sum of (N-k) dt / r_c
+    assert c[1] == 0.0                                                  # no sphere within r_c
+    assert abs(c[2]) < 1e-12                                            # L = d1
+    assert c[3] < 1e-20                                                 # no jerk
+    assert c[4] == pytest.approx(c.sum() - c[4], rel=1e-12)
+
+
+def test_costs_cubic_and_degenerate():
+    N, dt = 50, 1e-3
+    prm = scenes.Params(n_steps=N, dt=dt, a_max=10.0)
+    dt = float(np.float32(dt))
+    cc = 1e-9
+    k = np.arange(1, N + 1)
+    pos = np.stack([cc * k ** 3, np.zeros(N), np.zeros(N)], 1)
+    c = oracle.costs(pos, np.full(N, 0.0), [5.0, 0, 0], prm)
+    J = (N - 3) * (6 * cc) ** 2
+    a = float(np.float32(10.0))
+    assert c[3] == pytest.approx(min(1.0, J / (N * dt ** 4 * a * a)), rel=1e-9)
+    assert c[1] == pytest.approx(1.0)                                   # touching every step
+    assert c[0] == 1.0                                                  # goal farther than r_c throughout
+    L = cc * (N ** 3 - 1)
+    d1 = 5.0 - cc
+    assert c[2] == pytest.approx(1 - L / d1, rel=1e-12)                 # L < d1 branch
+    still = np.tile([0.2, 0.0, 0.0], (N, 1))
+    assert oracle.costs(still, np.full(N, 1.0), [0.7, 0, 0], prm)[2] == 1.0   # L = 0 < d1
+    assert oracle.costs(still, np.full(N, 1.0), [0.2, 0, 0], prm)[2] == 0.0   # L = d1 = 0
+    eps = float(np.float32(1e-3))
+    c = oracle.costs(still, np.full(N, eps), [0.2, 0, 0], prm)
+    assert c[1] == pytest.approx(1 - eps / float(np.float32(prm.r_cost)))
+    # smooth cost saturates at 1
+    big = np.stack([1e-3 * k ** 3, np.zeros(N), np.zeros(N)], 1)
+    assert oracle.costs(big, np.full(N, 1.0), [0, 0, 0], prm)[3] == 1.0
+
+
+def test_selection_rule():
+    assert oracle.select([3.0, 1.0, 2.0, 1.0]) == 1                 # argmin, lowest index on ties
+    assert oracle.select([np.nan, 2.0, np.nan]) == 1                  # NaN never wins
+    # with an incumbent b: only C_i < alpha C_b can replace it
+    assert oracle.select([1.0, 0.95, 0.85], incumbent=0, alpha=0.9) == 2
+    assert oracle.select([1.0, 0.95, 0.91], incumbent=0, alpha=0.9) == 0
+    assert oracle.select([1.0, 0.5, 0.5], incumbent=0, alpha=0.9) == 1
+    assert oracle.select([], incumbent=-1) == -1
+
+
+# --------------------------------------------------------------------------- symmetry / structure
+def _rotation(rng):
+    Q, _ = np.linalg.qr(rng.normal(size=(3, 3)))
+    if np.linalg.det(Q) < 0:
+        Q[:, 0] = -Q[:, 0]
+    return Q
+
+
+def test_rotation_and_translation_covariance():
+    rng = np.random.default_rng(5)
+    pb = scenes.tiny(2, n_points=40, n_agents=3, n_steps=40)
+    base = oracle.rollout(pb)
+    R = _rotation(rng)
+    t = np.array([0.3, -0.2, 0.1])
+    P = np.stack([pb.scene.x, pb.scene.y, pb.scene.z], 1).astype(np.float64)
+    # rotate the float64 scene; the oracle takes float64 values as given
+    import copy
+    pb2 = copy.deepcopy(pb)
+    sc = pb2.scene
+    P2 = P @ R.T + t
+    sc.x, sc.y, sc.z = P2[:, 0], P2[:, 1], P2[:, 2]
+    pb2.agents.omega = pb.agents.omega.astype(np.float64) @ R.T   # proper rotation: omega rotates too
+    pb2.query.p0 = pb.query.p0.astype(np.float64) @ R.T + t
+    pb2.query.goal = pb.query.goal.astype(np.float64) @ R.T + t
+    pb2.query.v0 = pb.query.v0.astype(np.float64) @ R.T
+    res = oracle.rollout(pb2)
+    np.testing.assert_allclose(res.traj, base.traj @ R.T + t, rtol=0, atol=1e-10)
+    np.testing.assert_allclose(res.cost, base.cost, rtol=1e-8, atol=1e-10)
+    assert res.best == base.best
+
+
+def test_agents_are_independent_and_point_order_free():
+    pb = scenes.config1()
+    pb.params.n_steps = 30
+    base = oracle.rollout(pb)
+    import copy
+    sub = copy.deepcopy(pb)
+    sub.agents = pb.agents.subset([5, 2])
+    r = oracle.rollout(sub)
+    np.testing.assert_array_equal(r.traj, base.traj[[5, 2]])
+    perm = np.random.default_rng(1).permutation(pb.scene.n)
+    sh = copy.deepcopy(pb)
+    sh.scene.x, sh.scene.y, sh.scene.z = pb.scene.x[perm], pb.scene.y[perm], pb.scene.z[perm]
+    r = oracle.rollout(sh)
+    np.testing.assert_allclose(r.traj, base.traj, rtol=0, atol=1e-12)
+
+
+# --------------------------------------------------------------------------- gradients
+def test_dual_gradient_matches_central_differences():
+    pb = scenes.tiny(4, n_points=24, n_agents=2, n_steps=25, cutoff=1)
+    pb.agents.k_f[:] = 0.02
+    g = oracle.rollout_grad(pb)
+    base = oracle.rollout(pb)
+    np.testing.assert_allclose(g[:, 0], base.cost[:, 4], rtol=1e-13)
+    import copy
+    names = [("k_a", None), ("d_a", None), ("k_f", None), ("omega", 0), ("omega", 1), ("omega", 2)]
+    for i in range(pb.agents.n):
+        for col, (name, ax) in enumerate(names):
+            theta = float(getattr(pb.agents, name)[i] if ax is None else pb.agents.omega[i, ax])
+            errs = []
+            for h in (1e-3, 5e-4):
+                step = h * max(1.0, abs(theta))
+                vals = []
+                for sgn in (1, -1):
+                    q = copy.deepcopy(pb)
+                    for f in ("k_a", "d_a", "k_f", "r_d", "r_a", "omega"):
+                        setattr(q.agents, f, getattr(q.agents, f).astype(np.float64))
+                    if ax is None:
+                        getattr(q.agents, name)[i] = theta + sgn * step
+                    else:
+                        q.agents.omega[i, ax] = theta + sgn * step
+                    vals.append(oracle.rollout(q).cost[i, 4])
+                fd = (vals[0] - vals[1]) / (2 * step)
+                errs.append(abs(fd - g[i, 1 + col]))
+            scale = max(abs(g[i, 1 + col]), 1e-6)
+            assert errs[-1] <= 1e-4 * scale + 1e-9, (i, name, ax, errs, g[i, 1 + col])
+            # second-order convergence (or already at rounding level)
+            assert errs[1] <= 0.5 * errs[0] or errs[1] < 1e-9 * max(1.0, scale), (i, name, ax, errs)
+
+
+def test_moving_obstacles_galilean_invariance():
+    """Without attractor and damping (k_a = d_a = 0) the force depends only on the
+    relative position and the relative velocity w = v - v_obj.  Moving every sphere
+    with u and giving the agent v0 + u reproduces the static motion shifted by
+    u t_k, t_k = (k-1) dt, with velocities shifted by u."""
+    import copy
+    pb = scenes.tiny(21, n_points=30, n_agents=3, n_steps=60)
+    pb.agents.k_a[:] = 0
+    pb.agents.d_a[:] = 0
+    pb.agents.k_f[:] = 0.05
+    base = oracle.rollout(pb)
+    u = np.array([0.15, -0.1, 0.05])
+    mv = copy.deepcopy(pb)
+    mv.scene.seg_begin = np.array([0, pb.scene.n], np.int32)
+    mv.scene.seg_vel = u.reshape(1, 3)
+    mv.query.v0 = pb.query.v0.astype(np.float64) + u
+    res = oracle.rollout(mv)
+    dt = float(np.float32(pb.params.dt))
+    shift = (np.arange(pb.params.n_steps + 1) * dt)[:, None] * u
+    assert np.abs(base.force).max() > 1.0
+    np.testing.assert_allclose(res.traj, base.traj + shift, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(res.vel, base.vel + u, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(res.min_clear, base.min_clear, rtol=1e-10)

@@ -1,0 +1,158 @@
+/*
+ * gmapp.h -- C ABI of the MI355X (gfx950) multi-agent circular-field rollout
+ * library: the data-parallel hot path of G-MAPP (Bishnoi et al., "G-MAPP:
+ * GPU-accelerated Multi-Agent Planning and Perception for Reactive Motion
+ * Generation").
+ *
+ * The calls follow the paper's problem statement (Sec. II): a sphere-world point
+ * cloud S_W (Eq. 5), start and goal poses, N_a planning agents with their
+ * parameters and a horizon of N_k steps go in; per-agent trajectories (Eq. 15),
+ * costs (Eqs. 16-20) and the selected agent come out.
+ *
+ * Conventions for every entry point
+ *  - Return value: GMAPP_OK (0) or a negative gmapp_status.  Argument checks
+ *    happen on the host, before anything is enqueued; on error nothing is
+ *    enqueued and gmapp_last_error() describes the problem.
+ *  - Array arguments marked "device" are device pointers (hipMalloc or torch
+ *    allocations on the context's device) owned by the caller; the library never
+ *    frees or retains them past the call.  Arrays marked "host" are read during
+ *    the call only.
+ *  - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream) and is
+ *    complete once that stream is synchronised.  Calls on one context must be
+ *    ordered (one stream at a time): the context's workspace is shared by them.
+ *  - Layouts are C order, FP32 unless stated: points SoA x[N_O], y[N_O], z[N_O];
+ *    per-agent scalars [N_a]; vectors [N_a][3].
+ *  - A context is used by one host thread at a time; a server is thread-safe.
+ */
+#ifndef GMAPP_H
+#define GMAPP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t gmapp_status;
+#define GMAPP_OK 0
+#define GMAPP_EINVAL (-1)     /* invalid argument (nothing enqueued) */
+#define GMAPP_ENOMEM (-2)     /* workspace or device memory exhausted */
+#define GMAPP_EDEVICE (-3)    /* no usable device, or a HIP runtime error */
+#define GMAPP_ECAPACITY (-4)  /* request exceeds a fixed capacity (grid residency, output capacity) */
+#define GMAPP_ETIMEOUT (-5)   /* deadline passed, or the in-kernel watchdog fired */
+#define GMAPP_ECANCELLED (-6) /* request cancelled */
+
+typedef struct gmapp_ctx gmapp_ctx;
+
+/* Create a context on HIP device `device`.  `workspace_bytes` sizes the device
+ * arena used for cross-workgroup exchange, voxel grids and adjoint checkpoints
+ * (0 = 256 MiB).  The arena is allocated once here and freed by gmapp_destroy. */
+gmapp_status gmapp_create(int32_t device, size_t workspace_bytes, gmapp_ctx **out);
+void gmapp_destroy(gmapp_ctx *ctx);
+/* Message for the last failing call on this context (never NULL). */
+const char *gmapp_last_error(const gmapp_ctx *ctx);
+/* Library version string, e.g. "gmapp 0.1 gfx950". */
+const char *gmapp_version(void);
+
+/* Sphere world S_W of Eq. (5): N_O sphere centres with one radius r_O.
+ * Optional moving obstacles: the points are grouped into n_seg contiguous
+ * segments (objects), seg_begin[s] .. seg_begin[s+1]-1, each translating with the
+ * constant velocity seg_vel[s] over the horizon (sphere j sits at
+ * p_j + t_k v_seg(j), t_k = t0 + (k-1) dt, see gmapp_query).  Points outside every
+ * segment are static.
+ * seg_begin must be non-decreasing with seg_begin[0] = 0 and
+ * seg_begin[n_seg] = N_O; other tables give unspecified (but memory-safe) results. */
+typedef struct {
+    const float *x, *y, *z;       /* device [N_O] each */
+    int64_t n_points;             /* N_O; with n_points_dev: the capacity of x, y, z */
+    const int64_t *n_points_dev;  /* device [1] or NULL: actual N_O (<= n_points), e.g. from
+                                     gmapp_voxel_downsample, read on the device (no host sync) */
+    float r_obs;                  /* r_O >= 0 */
+    int32_t n_seg;                /* 0 = static scene */
+    const int32_t *seg_begin;     /* device [n_seg + 1] */
+    const float *seg_vel;         /* device [n_seg][3], m/s */
+} gmapp_scene;
+
+/* Per-agent parameters (Alg. 1 inputs and the attractor of Eq. 7): circular-field
+ * gain k_f, detection radius r_d, agent radius r_a, stiffness K = k_a I, damping
+ * D = d_a I, and the rotation vector omega that parameterises the current vector
+ * of Eq. (3): c = omega - n (n . omega). */
+typedef struct {
+    const float *k_a, *d_a, *k_f, *r_d, *r_a; /* device [N_a] each */
+    const float *omega;                       /* device [N_a][3] */
+    int32_t n_agents;                         /* N_a >= 0 */
+} gmapp_agents;
+
+/* Planning query (host values): start position p^(1), start velocity v^(0),
+ * goal p_g; `incumbent` is the agent selected in the previous cycle (-1 = none),
+ * whose cost plays C_best in the selection rule; t0 is the time of step 1 on the
+ * clock of the moving segments (step k is at t_k = t0 + (k-1) dt), so a resident
+ * scene can be replanned cycle after cycle without moving its points. */
+typedef struct {
+    float p0[3], v0[3], goal[3];
+    int32_t incumbent;
+    float t0;
+} gmapp_query;
+
+/* Integrator, cost and selection parameters (host values).
+ *   v^(k) = v^(k-1) + (dt/2) inv_mass F^(k)            Eqs. (9), (10)
+ *   p^(k+1) = p^(k) + dt v^(k)                          Eq. (11), point mass
+ *   rho = max(|p - p_O| - (r_O + r_a), eps)             Alg. 1
+ *   cutoff 0: force kept iff rho <= r_d (Alg. 1); 1: C1 smoothstep taper over
+ *   [r_d (1 - taper_band), r_d].  Costs use the radius r_cost (Eqs. 17-18), the
+ *   weights w_* (Eq. 16) and a_max (Eq. 20); alpha tightens the selection rule. */
+typedef struct {
+    float dt, inv_mass, eps, r_cost;
+    float w_goal, w_obs, w_path, w_smooth;
+    float a_max, alpha, taper_band;
+    int32_t n_steps; /* N_k >= 1 */
+    int32_t cutoff;  /* 0 hard, 1 taper */
+} gmapp_params;
+
+/* Outputs (device).  traj[i][k] = p^(k+1) for k = 0..N_k (N_k + 1 poses);
+ * cost[i] = {C_goal, C_obs, C_path, C_smooth, C_total}; min_clear[i][k] =
+ * rho_min^(k+1), the smallest clamped surface distance at step k+1 (+inf when the
+ * scene is empty); best[0] = i*, or -1 when N_a = 0, or GMAPP_ETIMEOUT when the
+ * in-kernel watchdog aborted the rollout.  traj and min_clear may be NULL. */
+typedef struct {
+    float *traj;      /* device [N_a][N_k + 1][3] or NULL */
+    float *cost;      /* device [N_a][5] */
+    float *min_clear; /* device [N_a][N_k] or NULL */
+    int32_t *best;    /* device [1] */
+} gmapp_outputs;
+
+/* Forward rollout of one planning cycle (Sec. IV-A, Eqs. 6-11 and 15-20, Alg. 1 at
+ * every step, selection rule of Sec. IV-A): all N_a agents over N_k steps in one
+ * persistent launch; the repulsive force of each agent at each step is the sum of
+ * Eq. (2) over all N_O spheres.  Selection: i* = argmin{C_i : C_i < alpha C_best},
+ * ties to the lowest index; no incumbent gives the plain argmin. */
+gmapp_status gmapp_rollout(gmapp_ctx *ctx, const gmapp_scene *scene, const gmapp_agents *agents,
+                           const gmapp_query *query, const gmapp_params *params, const gmapp_outputs *out,
+                           void *stream);
+
+/* Teacher-forced response of Alg. 1: for each agent i, the repulsive force
+ * f_r[i] = sum_j Eq. (2) at position p[i], velocity v[i] and time t, and rho_min[i].
+ * Same device code as one step of gmapp_rollout.  p, v, f_r: device [N_a][3];
+ * rho_min: device [N_a] (may be NULL). */
+gmapp_status gmapp_force_probe(gmapp_ctx *ctx, const gmapp_scene *scene, const gmapp_agents *agents,
+                               const float *p, const float *v, float t, const gmapp_params *params, float *f_r,
+                               float *rho_min, void *stream);
+
+/* Tiling of the rollout kernel: agents per workgroup (power of two, 1..256),
+ * waves per workgroup (1, 2, 4, 8), point shards per agent group (>= 1; > 1 uses a
+ * cooperative launch with one cross-workgroup exchange per step) and LDS tile
+ * capacity in points.  Zero fields mean "choose". */
+typedef struct {
+    int32_t agents_per_block, waves, shards, tile_points;
+} gmapp_tiling;
+/* Force a tiling for later rollouts on this context (NULL restores the automatic choice). */
+gmapp_status gmapp_set_tiling(gmapp_ctx *ctx, const gmapp_tiling *tiling);
+/* The tiling gmapp_rollout would use for this problem shape. */
+gmapp_status gmapp_get_tiling(gmapp_ctx *ctx, int64_t n_points, int32_t n_agents, int32_t n_steps, int32_t n_seg,
+                              int32_t cutoff, gmapp_tiling *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GMAPP_H */

@@ -105,7 +105,7 @@ def rollout(problem) -> RolloutResult:
     N, na = int(prm.n_steps), ag.n
     keep, sargs = _scene_args(sc)
     A, pA = _d(_agents_rows(ag))
-    Q, pQ = _d(np.concatenate([q.p0, q.v0, q.goal]).astype(np.float64))
+    Q, pQ = _d(np.concatenate([q.p0, q.v0, q.goal, [np.float32(q.t0)]]).astype(np.float64))
     P, pP = _d(_params_row(prm))
     traj = np.zeros((na, N + 1, 3)); cost = np.zeros((na, 5)); mc = np.zeros((na, N))
     force = np.zeros((na, N, 3)); vel = np.zeros((na, N + 1, 3)); ftot = np.zeros((na, N, 3))
@@ -151,7 +151,7 @@ def rollout_grad(problem) -> np.ndarray:
     sc, ag, q, prm = problem.scene, problem.agents, problem.query, problem.params
     keep, sargs = _scene_args(sc)
     A, pA = _d(_agents_rows(ag))
-    Q, pQ = _d(np.concatenate([q.p0, q.v0, q.goal]).astype(np.float64))
+    Q, pQ = _d(np.concatenate([q.p0, q.v0, q.goal, [np.float32(q.t0)]]).astype(np.float64))
     P, pP = _d(_params_row(prm))
     out = np.zeros((ag.n, 7))
     rc = lib.oracle_rollout_grad(*sargs, ag.n, pA, pQ, pP, int(prm.n_steps), int(prm.cutoff),

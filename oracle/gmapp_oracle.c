@@ -216,6 +216,7 @@ int oracle_select(int n, const double *total, int incumbent, double alpha)
 
 /* One agent's forward rollout (Eqs. 6, 7, 9, 10, 11 for a point mass), with the
  * repulsive force of Alg. 1 at every step.
+ * query: p0[3], v0[3], goal[3], t0 (time of step 1; moving spheres sit at p_j + t v_seg).
  * Records: pos [N+1][3] (p^(1..N+1)), vel [N+1][3] (v^(0..N)), rmin [N], force [N][3]
  * (F_r^(1..N)) and total force ftot [N][3] (F^(1..N)). */
 static void rollout_one(long n_pts, const double *px, const double *py, const double *pz, double r_obs,
@@ -229,7 +230,7 @@ static void rollout_one(long n_pts, const double *px, const double *py, const do
     double dt = prm[P_DT], invm = prm[P_INVM];
     vel[0] = v[0]; vel[1] = v[1]; vel[2] = v[2];
     for (int k = 1; k <= N; ++k) {
-        double t = (k - 1) * dt;
+        double t = query[9] + (k - 1) * dt;   /* cycle start time + step offset */
         double Fr[3], rho_min;
         repulsion_one(n_pts, px, py, pz, r_obs, n_seg, seg_begin, seg_vel, ag, p, v, t, prm, cutoff, Fr,
                       &rho_min, NULL, NULL, NULL);

@@ -160,7 +160,7 @@ int oracle_rollout_grad(long n_pts, const double *px, const double *py, const do
         dual p[3] = {dc(query[0]), dc(query[1]), dc(query[2])};
         dual v[3] = {dc(query[3]), dc(query[4]), dc(query[5])};
         for (int k = 1; k <= N; ++k) {
-            double t = (k - 1) * dt;
+            double t = query[9] + (k - 1) * dt;
             dual Fr[3] = {dc(0.0), dc(0.0), dc(0.0)};
             dual rm = dc(INFINITY);
             for (long j = 0; j < n_pts; ++j) {

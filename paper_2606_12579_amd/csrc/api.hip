@@ -1,0 +1,238 @@
+// C ABI entry points: context lifetime, argument validation and dispatch.
+// Every check runs on the host before anything is enqueued.
+#include "gmapp_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+using gm::fail;
+
+namespace {
+
+__global__ void k_fill_u32(unsigned *p, size_t n, unsigned v)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+bool finite(float x) { return std::isfinite(x); }
+
+gmapp_status check_ctx(gmapp_ctx *ctx)
+{
+    if (!ctx) return GMAPP_EINVAL;
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return gm::hip_fail(ctx, e, "hipSetDevice");
+    return GMAPP_OK;
+}
+
+gmapp_status check_scene(gmapp_ctx *ctx, const gmapp_scene *sc)
+{
+    if (!sc) return fail(ctx, GMAPP_EINVAL, "scene is NULL");
+    if (sc->n_points < 0) return fail(ctx, GMAPP_EINVAL, "n_points must be >= 0");
+    if (sc->n_points > (int64_t)INT32_MAX) return fail(ctx, GMAPP_ECAPACITY, "n_points exceeds 2^31 - 1");
+    if (sc->n_points > 0 && (!sc->x || !sc->y || !sc->z)) return fail(ctx, GMAPP_EINVAL, "scene x/y/z is NULL");
+    if (!finite(sc->r_obs) || sc->r_obs < 0) return fail(ctx, GMAPP_EINVAL, "r_obs must be finite and >= 0");
+    if (sc->n_seg < 0) return fail(ctx, GMAPP_EINVAL, "n_seg must be >= 0");
+    if (sc->n_seg > 0 && (!sc->seg_begin || !sc->seg_vel))
+        return fail(ctx, GMAPP_EINVAL, "seg_begin/seg_vel is NULL with n_seg > 0");
+    if (sc->n_seg > 0 && sc->n_points_dev)
+        return fail(ctx, GMAPP_EINVAL, "a device-resident point count needs a static scene (n_seg = 0)");
+    return GMAPP_OK;
+}
+
+gmapp_status check_agents(gmapp_ctx *ctx, const gmapp_agents *ag)
+{
+    if (!ag) return fail(ctx, GMAPP_EINVAL, "agents is NULL");
+    if (ag->n_agents < 0) return fail(ctx, GMAPP_EINVAL, "n_agents must be >= 0");
+    if (ag->n_agents > (1 << 24)) return fail(ctx, GMAPP_ECAPACITY, "n_agents exceeds 2^24");
+    if (ag->n_agents > 0 && (!ag->k_a || !ag->d_a || !ag->k_f || !ag->r_d || !ag->r_a || !ag->omega))
+        return fail(ctx, GMAPP_EINVAL, "an agent parameter array is NULL");
+    return GMAPP_OK;
+}
+
+gmapp_status check_params(gmapp_ctx *ctx, const gmapp_params *p, bool need_steps)
+{
+    if (!p) return fail(ctx, GMAPP_EINVAL, "params is NULL");
+    if (need_steps && p->n_steps < 1) return fail(ctx, GMAPP_EINVAL, "n_steps must be >= 1");
+    if (p->n_steps > (1 << 24)) return fail(ctx, GMAPP_ECAPACITY, "n_steps exceeds 2^24");
+    if (!finite(p->dt) || p->dt <= 0) return fail(ctx, GMAPP_EINVAL, "dt must be finite and > 0");
+    if (!finite(p->inv_mass)) return fail(ctx, GMAPP_EINVAL, "inv_mass must be finite");
+    if (!finite(p->eps) || p->eps <= 0) return fail(ctx, GMAPP_EINVAL, "eps must be finite and > 0");
+    if (!finite(p->r_cost) || p->r_cost <= 0) return fail(ctx, GMAPP_EINVAL, "r_cost must be finite and > 0");
+    if (!finite(p->a_max) || p->a_max <= 0) return fail(ctx, GMAPP_EINVAL, "a_max must be finite and > 0");
+    if (!finite(p->w_goal) || !finite(p->w_obs) || !finite(p->w_path) || !finite(p->w_smooth) || !finite(p->alpha))
+        return fail(ctx, GMAPP_EINVAL, "cost weights and alpha must be finite");
+    if (p->cutoff != 0 && p->cutoff != 1) return fail(ctx, GMAPP_EINVAL, "cutoff must be 0 (hard) or 1 (taper)");
+    if (p->cutoff == 1 && (!finite(p->taper_band) || p->taper_band <= 0 || p->taper_band > 1))
+        return fail(ctx, GMAPP_EINVAL, "taper_band must be in (0, 1]");
+    return GMAPP_OK;
+}
+
+gm::Scn dev_scene(const gmapp_scene *sc)
+{
+    gm::Scn s;
+    s.x = sc->x; s.y = sc->y; s.z = sc->z;
+    s.n_cap = sc->n_points;
+    s.n_dev = reinterpret_cast<const long long *>(sc->n_points_dev);
+    s.r_obs = sc->r_obs;
+    s.n_seg = sc->n_seg;
+    s.seg_begin = sc->seg_begin;
+    s.seg_vel = sc->seg_vel;
+    return s;
+}
+
+gm::Agt dev_agents(const gmapp_agents *ag)
+{
+    return gm::Agt{ag->k_a, ag->d_a, ag->k_f, ag->r_d, ag->r_a, ag->omega, ag->n_agents};
+}
+
+gm::Prm dev_params(const gmapp_params *p, const gmapp_query *q)
+{
+    gm::Prm r;
+    r.dt = p->dt; r.inv_mass = p->inv_mass; r.eps = p->eps; r.r_cost = p->r_cost;
+    r.w0 = p->w_goal; r.w1 = p->w_obs; r.w2 = p->w_path; r.w3 = p->w_smooth;
+    r.a_max = p->a_max; r.alpha = p->alpha; r.band = p->cutoff == 1 ? p->taper_band : 1.0f;
+    r.n_steps = p->n_steps; r.cutoff = p->cutoff;
+    for (int a = 0; a < 3; ++a) {
+        r.p0[a] = q ? q->p0[a] : 0.f;
+        r.v0[a] = q ? q->v0[a] : 0.f;
+        r.goal[a] = q ? q->goal[a] : 0.f;
+    }
+    r.incumbent = q ? q->incumbent : -1;
+    r.t0 = q ? q->t0 : 0.f;
+    return r;
+}
+
+gm::Tiling tiling_for(gmapp_ctx *ctx, long long n_points, int n_agents, int n_steps, int n_seg, int cutoff)
+{
+    gm::Tiling t = gm::choose_tiling(ctx, n_points, n_agents, n_steps, n_seg, cutoff);
+    if (ctx->forced) {
+        const gmapp_tiling &f = ctx->forced_tiling;
+        if (f.agents_per_block > 0) t.A = f.agents_per_block;
+        if (f.waves > 0) t.W = f.waves;
+        if (f.shards > 0) t.S = f.shards;
+        if (f.tile_points > 0) t.tile = f.tile_points;
+        else {
+            long long per = (n_points + t.S - 1) / t.S;
+            t.tile = (int)std::min<long long>(std::max<long long>((per + 63) / 64 * 64, 64), 8192);
+        }
+    }
+    return t;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *gmapp_version(void) { return "gmapp 0.1 gfx950"; }
+
+gmapp_status gmapp_create(int32_t device, size_t workspace_bytes, gmapp_ctx **out)
+{
+    if (!out) return GMAPP_EINVAL;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) return GMAPP_EDEVICE;
+    if (device < 0 || device >= n) return GMAPP_EINVAL;
+    if (hipSetDevice(device) != hipSuccess) return GMAPP_EDEVICE;
+    gmapp_ctx *ctx = new (std::nothrow) gmapp_ctx();
+    if (!ctx) return GMAPP_ENOMEM;
+    ctx->device = device;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) { delete ctx; return GMAPP_EDEVICE; }
+    ctx->n_cu = prop.multiProcessorCount;
+    ctx->lds_per_cu = (int)prop.maxSharedMemoryPerMultiProcessor;
+    if (workspace_bytes == 0) workspace_bytes = (size_t)256 << 20;
+    const size_t sync_bytes = (gm::kSyncWords * sizeof(unsigned) + 4095) / 4096 * 4096;
+    if (workspace_bytes < sync_bytes + (1 << 20)) workspace_bytes = sync_bytes + (1 << 20);
+    void *p = nullptr;
+    if (hipMalloc(&p, workspace_bytes) != hipSuccess) { delete ctx; return GMAPP_ENOMEM; }
+    ctx->arena = static_cast<char *>(p);
+    ctx->arena_bytes = workspace_bytes;
+    ctx->sync = reinterpret_cast<unsigned *>(ctx->arena);
+    ctx->scratch = ctx->arena + sync_bytes;
+    ctx->scratch_bytes = workspace_bytes - sync_bytes;
+    hipLaunchKernelGGL(k_fill_u32, dim3(64), dim3(256), 0, nullptr, ctx->sync, gm::kSyncWords, 0u);
+    if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+        hipFree(p);
+        delete ctx;
+        return GMAPP_EDEVICE;
+    }
+    *out = ctx;
+    return GMAPP_OK;
+}
+
+void gmapp_destroy(gmapp_ctx *ctx)
+{
+    if (!ctx) return;
+    hipSetDevice(ctx->device);
+    hipDeviceSynchronize();
+    if (ctx->arena) hipFree(ctx->arena);
+    delete ctx;
+}
+
+const char *gmapp_last_error(const gmapp_ctx *ctx)
+{
+    if (!ctx) return "no context";
+    return ctx->err.c_str();
+}
+
+gmapp_status gmapp_set_tiling(gmapp_ctx *ctx, const gmapp_tiling *t)
+{
+    if (!ctx) return GMAPP_EINVAL;
+    if (!t) { ctx->forced = false; return GMAPP_OK; }
+    if (t->agents_per_block < 0 || t->waves < 0 || t->shards < 0 || t->tile_points < 0)
+        return fail(ctx, GMAPP_EINVAL, "tiling fields must be >= 0");
+    ctx->forced = true;
+    ctx->forced_tiling = *t;
+    return GMAPP_OK;
+}
+
+gmapp_status gmapp_get_tiling(gmapp_ctx *ctx, int64_t n_points, int32_t n_agents, int32_t n_steps, int32_t n_seg,
+                              int32_t cutoff, gmapp_tiling *out)
+{
+    if (!ctx || !out) return GMAPP_EINVAL;
+    gm::Tiling t = tiling_for(ctx, n_points, n_agents, n_steps, n_seg, cutoff);
+    *out = gmapp_tiling{t.A, t.W, t.S, t.tile};
+    return GMAPP_OK;
+}
+
+gmapp_status gmapp_rollout(gmapp_ctx *ctx, const gmapp_scene *scene, const gmapp_agents *agents,
+                           const gmapp_query *query, const gmapp_params *params, const gmapp_outputs *out,
+                           void *stream)
+{
+    gmapp_status st = check_ctx(ctx);
+    if (st) return st;
+    if ((st = check_scene(ctx, scene)) || (st = check_agents(ctx, agents)) || (st = check_params(ctx, params, true)))
+        return st;
+    if (!query) return fail(ctx, GMAPP_EINVAL, "query is NULL");
+    for (int a = 0; a < 3; ++a)
+        if (!finite(query->p0[a]) || !finite(query->v0[a]) || !finite(query->goal[a]))
+            return fail(ctx, GMAPP_EINVAL, "query start/velocity/goal must be finite");
+    if (!finite(query->t0)) return fail(ctx, GMAPP_EINVAL, "query t0 must be finite");
+    if (!out || !out->best) return fail(ctx, GMAPP_EINVAL, "outputs.best is NULL");
+    if (agents->n_agents > 0 && !out->cost) return fail(ctx, GMAPP_EINVAL, "outputs.cost is NULL");
+    gm::Tiling t = tiling_for(ctx, scene->n_points, agents->n_agents, params->n_steps, scene->n_seg, params->cutoff);
+    gm::Out o{out->traj, out->cost, out->min_clear, out->best};
+    return gm::launch_rollout(ctx, dev_scene(scene), dev_agents(agents), dev_params(params, query), o, nullptr, t,
+                              static_cast<hipStream_t>(stream));
+}
+
+gmapp_status gmapp_force_probe(gmapp_ctx *ctx, const gmapp_scene *scene, const gmapp_agents *agents, const float *p,
+                               const float *v, float t, const gmapp_params *params, float *f_r, float *rho_min,
+                               void *stream)
+{
+    gmapp_status st = check_ctx(ctx);
+    if (st) return st;
+    if ((st = check_scene(ctx, scene)) || (st = check_agents(ctx, agents)) || (st = check_params(ctx, params, false)))
+        return st;
+    if (agents->n_agents > 0 && (!p || !v || !f_r)) return fail(ctx, GMAPP_EINVAL, "p, v and f_r must be non-NULL");
+    if (!finite(t)) return fail(ctx, GMAPP_EINVAL, "t must be finite");
+    gm::Tiling tl = tiling_for(ctx, scene->n_points, agents->n_agents, 1, scene->n_seg, params->cutoff);
+    gm::Probe pb{p, v, t, f_r, rho_min};
+    gm::Out o{nullptr, nullptr, nullptr, nullptr};
+    return gm::launch_rollout(ctx, dev_scene(scene), dev_agents(agents), dev_params(params, nullptr), o, &pb, tl,
+                              static_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"

@@ -102,6 +102,7 @@ class Query:
     v0: np.ndarray
     goal: np.ndarray
     incumbent: int = -1
+    t0: float = 0.0        # time of step 1 (moving obstacles sit at p_j + t v_seg)
 
 
 @dataclasses.dataclass

@@ -1,0 +1,69 @@
+"""The C-ABI library loads and exports every entry point that include/gmapp.h
+declares; without a device, context creation reports GMAPP_EDEVICE.  No compute
+call is made here (these run on the CPU-only host)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gmapp.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gmapp_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_entry_points():
+    names = declared_functions()
+    for required in ("gmapp_create", "gmapp_destroy", "gmapp_last_error", "gmapp_rollout", "gmapp_force_probe"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2606_12579_amd import gmapp
+    lib = gmapp.load_library()
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+    out = subprocess.run(["nm", "-D", "--defined-only", gmapp.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\b(gmapp_[a-z0-9_]+)\b", out))
+    assert set(declared_functions()) <= exported
+
+
+def test_version_and_no_device_error():
+    import torch
+    from paper_2606_12579_amd import gmapp
+    lib = gmapp.load_library()
+    assert lib.gmapp_version().startswith(b"gmapp")
+    if torch.cuda.is_available():
+        pytest.skip("a device is present")
+    h = ctypes.c_void_p()
+    assert lib.gmapp_create(0, 0, ctypes.byref(h)) == gmapp.EDEVICE
+    assert lib.gmapp_create(0, 0, None) == gmapp.EINVAL
+    lib.gmapp_destroy(None)                       # NULL is accepted
+    assert lib.gmapp_last_error(None) == b"no context"
+
+
+def test_struct_layouts_match_header():
+    """ctypes mirrors of the C structs have the sizes the C compiler gives them."""
+    from paper_2606_12579_amd import gmapp
+    src = r'''
+#include <stdio.h>
+#include "gmapp.h"
+int main(void){printf("%zu %zu %zu %zu %zu %zu\n", sizeof(gmapp_scene), sizeof(gmapp_agents), sizeof(gmapp_query),
+ sizeof(gmapp_params), sizeof(gmapp_outputs), sizeof(gmapp_tiling)); return 0;}
+'''
+    import tempfile
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "s.c")
+        open(c, "w").write(src)
+        exe = os.path.join(d, "s")
+        subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe], check=True)
+        sizes = [int(x) for x in subprocess.run([exe], capture_output=True, text=True).stdout.split()]
+    mine = [ctypes.sizeof(s) for s in (gmapp.Scene, gmapp.Agents, gmapp.Query, gmapp.Params, gmapp.Outputs,
+                                       gmapp.Tiling)]
+    assert sizes == mine

@@ -139,18 +139,49 @@ gmapp_status gmapp_force_probe(gmapp_ctx *ctx, const gmapp_scene *scene, const g
                                const float *p, const float *v, float t, const gmapp_params *params, float *f_r,
                                float *rho_min, void *stream);
 
-/* Tiling of the rollout kernel: agents per workgroup (power of two, 1..256),
- * waves per workgroup (1, 2, 4, 8), point shards per agent group (>= 1; > 1 uses a
- * cooperative launch with one cross-workgroup exchange per step) and LDS tile
- * capacity in points.  Zero fields mean "choose". */
+/* Tiling of the rollout kernel.  An agent group is `agents` agents (power of two)
+ * sharing the lanes of one wavefront (group = 1: agents 1..64) or of the whole
+ * workgroup (group = 2: agents 1..8, 4/8/16 waves); a workgroup has `waves`
+ * wavefronts (1, 2, 4, 8, 16) and one of `shards` point shards (>= 1; > 1 uses a
+ * cooperative launch with one cross-workgroup exchange per step).  The shard sits
+ * in LDS for the whole rollout (layout 1) or is streamed through tiles of
+ * tile_points points every step (layout 2); layout 0 picks resident whenever it
+ * fits.  Zero fields mean "choose". */
 typedef struct {
-    int32_t agents_per_block, waves, shards, tile_points;
+    int32_t agents, waves, shards;
+    int32_t tile_points, layout;
+    int32_t group; /* 0 choose, 1 wavefront, 2 workgroup */
 } gmapp_tiling;
 /* Force a tiling for later rollouts on this context (NULL restores the automatic choice). */
 gmapp_status gmapp_set_tiling(gmapp_ctx *ctx, const gmapp_tiling *tiling);
 /* The tiling gmapp_rollout would use for this problem shape. */
 gmapp_status gmapp_get_tiling(gmapp_ctx *ctx, int64_t n_points, int32_t n_agents, int32_t n_steps, int32_t n_seg,
                               int32_t cutoff, gmapp_tiling *out);
+
+/* Back-projection of a z-depth image into world points (Sec. IV-B / V-A: the
+ * perception pipeline's coordinate transform).  Pixel (u, v) = column, row with
+ * depth z = depth[v * w + u] (metres) maps to the camera point
+ * ((u - c_x) z / f_x, (v - c_y) z / f_y, z) and then to R X_c + t with
+ * T_wc = [R | t] (host, row-major 3 x 4).  K = {f_x, f_y, c_x, c_y} (host).
+ * Pixels with z <= 0 or non-finite z give NaN points (dropped by the voxel pass).
+ * depth: device [h][w]; x, y, z: device [w * h] SoA outputs. */
+gmapp_status gmapp_depth_to_points(gmapp_ctx *ctx, const float *depth, int32_t w, int32_t h, const float K[4],
+                                   const float T_wc[12], float *x, float *y, float *z, void *stream);
+
+/* Uniform voxel lattice of the sphere world (Sec. IV-B; voxel size 2 r_O in
+ * Sec. V-A, voxel-centre clouds): the cell of a point is floor((p - lo) / voxel)
+ * per axis (FP32); points outside the box lo + [0, dims * voxel) or non-finite are
+ * dropped (the workspace bounding-box filter).  Every cell holding at least
+ * min_count points (>= 1; larger values filter sensing artifacts) contributes its
+ * centre lo + (k + 1/2) voxel.  Centres are written to ox, oy, oz (device
+ * [capacity]) in increasing linear cell index (x fastest, then y, then z); the
+ * number of occupied cells goes to n_out_dev (device int64 [1]), even when it
+ * exceeds capacity (then only the first `capacity` centres are written).  Uses
+ * 4 bytes of context workspace per cell.  x, y, z: device [n]. */
+gmapp_status gmapp_voxel_downsample(gmapp_ctx *ctx, const float *x, const float *y, const float *z, int64_t n,
+                                    float voxel, const float lo[3], const int32_t dims[3], int32_t min_count,
+                                    float *ox, float *oy, float *oz, int64_t capacity, int64_t *n_out_dev,
+                                    void *stream);
 
 #ifdef __cplusplus
 }

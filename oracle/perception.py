@@ -1,0 +1,61 @@
+"""FP64 / exact reference of the perception pass -- TEST INFRASTRUCTURE ONLY.
+
+  back_project(depth, K, T_wc)   pinhole back-projection and the camera-to-world
+                                 transform (Sec. IV-B, V-A), FP64 from FP32 inputs
+  voxel_cells(x, y, z, ...)      occupied cells of the uniform voxel lattice of size
+                                 2 r_O (Sec. IV-B, V-A): cell = floor((p - lo) / voxel)
+                                 per axis, decided in FP32 as the library does (the
+                                 quantisation is an integer decision)
+  voxel_centres(cells, ...)      the voxel-centre cloud lo + (k + 1/2) voxel (FP64)
+"""
+import numpy as np
+
+
+def back_project(depth, K, T_wc):
+    """World points [h*w, 3] (NaN rows for depth <= 0 or non-finite)."""
+    d = np.asarray(depth, np.float64)
+    h, w = d.shape
+    fx, fy, cx, cy = (float(np.float32(k)) for k in K)
+    T = np.asarray(T_wc, np.float32).astype(np.float64).reshape(3, 4)
+    u, v = np.meshgrid(np.arange(w, dtype=np.float64), np.arange(h, dtype=np.float64))
+    with np.errstate(invalid="ignore", over="ignore"):
+        Xc = np.stack([(u - cx) * d / fx, (v - cy) * d / fy, d], -1).reshape(-1, 3)
+        P = Xc @ T[:, :3].T + T[:, 3]
+    bad = ~(np.isfinite(d.reshape(-1)) & (d.reshape(-1) > 0))
+    P[bad] = np.nan
+    return P
+
+
+def voxel_keys(x, y, z, voxel, lo, dims):
+    """Integer cell coordinates [n, 3] and a validity mask (inside the box, finite).
+
+    The floor is taken of the FP32 quotient (p - lo) / voxel, each operation
+    correctly rounded in FP32, as the library computes it."""
+    P = np.stack([np.asarray(x, np.float32), np.asarray(y, np.float32), np.asarray(z, np.float32)], 1)
+    lo32 = np.asarray(lo, np.float32)
+    s32 = np.float32(voxel)
+    with np.errstate(invalid="ignore"):
+        q = np.floor((P - lo32) / s32)
+        ok = np.isfinite(P).all(1) & (q >= 0).all(1) & (q < np.asarray(dims)).all(1)
+    k = np.zeros(P.shape, np.int64)
+    k[ok] = q[ok].astype(np.int64)
+    return k, ok
+
+
+def voxel_cells(x, y, z, voxel, lo, dims, min_count=1):
+    """Sorted linear indices (x fastest) of the cells holding >= min_count points."""
+    k, ok = voxel_keys(x, y, z, voxel, lo, dims)
+    dims = np.asarray(dims, np.int64)
+    lin = (k[ok, 2] * dims[1] + k[ok, 1]) * dims[0] + k[ok, 0]
+    cells, counts = np.unique(lin, return_counts=True)
+    return cells[counts >= min_count]
+
+
+def voxel_centres(cells, voxel, lo, dims):
+    dims = np.asarray(dims, np.int64)
+    kx = cells % dims[0]
+    ky = (cells // dims[0]) % dims[1]
+    kz = cells // (dims[0] * dims[1])
+    lo = np.asarray(lo, np.float32).astype(np.float64)
+    s = float(np.float32(voxel))
+    return np.stack([lo[0] + (kx + 0.5) * s, lo[1] + (ky + 0.5) * s, lo[2] + (kz + 0.5) * s], 1)

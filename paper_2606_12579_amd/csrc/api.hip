@@ -109,14 +109,12 @@ gm::Tiling tiling_for(gmapp_ctx *ctx, long long n_points, int n_agents, int n_st
     gm::Tiling t = gm::choose_tiling(ctx, n_points, n_agents, n_steps, n_seg, cutoff);
     if (ctx->forced) {
         const gmapp_tiling &f = ctx->forced_tiling;
-        if (f.agents_per_block > 0) t.A = f.agents_per_block;
+        if (f.group > 0) t.wg = f.group == 2 ? 1 : 0;
+        if (f.agents > 0) t.A = f.agents;
         if (f.waves > 0) t.W = f.waves;
         if (f.shards > 0) t.S = f.shards;
         if (f.tile_points > 0) t.tile = f.tile_points;
-        else {
-            long long per = (n_points + t.S - 1) / t.S;
-            t.tile = (int)std::min<long long>(std::max<long long>((per + 63) / 64 * 64, 64), 8192);
-        }
+        t.layout = f.layout;
     }
     return t;
 }
@@ -144,17 +142,19 @@ gmapp_status gmapp_create(int32_t device, size_t workspace_bytes, gmapp_ctx **ou
     ctx->lds_per_cu = (int)prop.maxSharedMemoryPerMultiProcessor;
     if (workspace_bytes == 0) workspace_bytes = (size_t)256 << 20;
     const size_t sync_bytes = (gm::kSyncWords * sizeof(unsigned) + 4095) / 4096 * 4096;
-    if (workspace_bytes < sync_bytes + (1 << 20)) workspace_bytes = sync_bytes + (1 << 20);
+    const size_t fixed = sync_bytes + gm::kXchgBytes;
+    if (workspace_bytes < fixed + (1 << 20)) workspace_bytes = fixed + (1 << 20);
     void *p = nullptr;
     if (hipMalloc(&p, workspace_bytes) != hipSuccess) { delete ctx; return GMAPP_ENOMEM; }
     ctx->arena = static_cast<char *>(p);
     ctx->arena_bytes = workspace_bytes;
     ctx->sync = reinterpret_cast<unsigned *>(ctx->arena);
-    ctx->scratch = ctx->arena + sync_bytes;
-    ctx->scratch_bytes = workspace_bytes - sync_bytes;
-    hipLaunchKernelGGL(k_fill_u32, dim3(64), dim3(256), 0, nullptr, ctx->sync, gm::kSyncWords, 0u);
+    ctx->xchg = reinterpret_cast<unsigned long long *>(ctx->arena + sync_bytes);
+    ctx->scratch = ctx->arena + fixed;
+    ctx->scratch_bytes = workspace_bytes - fixed;
+    hipLaunchKernelGGL(k_fill_u32, dim3(256), dim3(256), 0, nullptr, ctx->sync, fixed / sizeof(unsigned), 0u);
     if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
-        hipFree(p);
+        (void)hipFree(p);
         delete ctx;
         return GMAPP_EDEVICE;
     }
@@ -165,9 +165,9 @@ gmapp_status gmapp_create(int32_t device, size_t workspace_bytes, gmapp_ctx **ou
 void gmapp_destroy(gmapp_ctx *ctx)
 {
     if (!ctx) return;
-    hipSetDevice(ctx->device);
-    hipDeviceSynchronize();
-    if (ctx->arena) hipFree(ctx->arena);
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    if (ctx->arena) (void)hipFree(ctx->arena);
     delete ctx;
 }
 
@@ -181,7 +181,8 @@ gmapp_status gmapp_set_tiling(gmapp_ctx *ctx, const gmapp_tiling *t)
 {
     if (!ctx) return GMAPP_EINVAL;
     if (!t) { ctx->forced = false; return GMAPP_OK; }
-    if (t->agents_per_block < 0 || t->waves < 0 || t->shards < 0 || t->tile_points < 0)
+    if (t->agents < 0 || t->waves < 0 || t->shards < 0 || t->tile_points < 0 || t->layout < 0 || t->group < 0 ||
+        t->group > 2)
         return fail(ctx, GMAPP_EINVAL, "tiling fields must be >= 0");
     ctx->forced = true;
     ctx->forced_tiling = *t;
@@ -193,7 +194,7 @@ gmapp_status gmapp_get_tiling(gmapp_ctx *ctx, int64_t n_points, int32_t n_agents
 {
     if (!ctx || !out) return GMAPP_EINVAL;
     gm::Tiling t = tiling_for(ctx, n_points, n_agents, n_steps, n_seg, cutoff);
-    *out = gmapp_tiling{t.A, t.W, t.S, t.tile};
+    *out = gmapp_tiling{t.A, t.W, t.S, t.tile, t.layout, t.wg ? 2 : 1};
     return GMAPP_OK;
 }
 
@@ -233,6 +234,56 @@ gmapp_status gmapp_force_probe(gmapp_ctx *ctx, const gmapp_scene *scene, const g
     gm::Out o{nullptr, nullptr, nullptr, nullptr};
     return gm::launch_rollout(ctx, dev_scene(scene), dev_agents(agents), dev_params(params, nullptr), o, &pb, tl,
                               static_cast<hipStream_t>(stream));
+}
+
+gmapp_status gmapp_depth_to_points(gmapp_ctx *ctx, const float *depth, int32_t w, int32_t h, const float K[4],
+                                   const float T_wc[12], float *x, float *y, float *z, void *stream)
+{
+    gmapp_status st = check_ctx(ctx);
+    if (st) return st;
+    if (w < 0 || h < 0) return fail(ctx, GMAPP_EINVAL, "image size must be >= 0");
+    if ((long long)w * h > (long long)INT32_MAX) return fail(ctx, GMAPP_ECAPACITY, "image exceeds 2^31 - 1 pixels");
+    if (!K || !T_wc) return fail(ctx, GMAPP_EINVAL, "K and T_wc must be non-NULL");
+    for (int i = 0; i < 4; ++i)
+        if (!finite(K[i])) return fail(ctx, GMAPP_EINVAL, "intrinsics must be finite");
+    if (K[0] == 0.f || K[1] == 0.f) return fail(ctx, GMAPP_EINVAL, "focal lengths must be non-zero");
+    gm::Mat34 T;
+    for (int i = 0; i < 12; ++i) {
+        if (!finite(T_wc[i])) return fail(ctx, GMAPP_EINVAL, "T_wc must be finite");
+        T.r[i] = T_wc[i];
+    }
+    if ((long long)w * h > 0 && (!depth || !x || !y || !z))
+        return fail(ctx, GMAPP_EINVAL, "depth and output pointers must be non-NULL");
+    return gm::launch_depth_to_points(ctx, depth, w, h, K, T, x, y, z, static_cast<hipStream_t>(stream));
+}
+
+gmapp_status gmapp_voxel_downsample(gmapp_ctx *ctx, const float *x, const float *y, const float *z, int64_t n,
+                                    float voxel, const float lo[3], const int32_t dims[3], int32_t min_count,
+                                    float *ox, float *oy, float *oz, int64_t capacity, int64_t *n_out_dev,
+                                    void *stream)
+{
+    gmapp_status st = check_ctx(ctx);
+    if (st) return st;
+    if (n < 0 || capacity < 0) return fail(ctx, GMAPP_EINVAL, "n and capacity must be >= 0");
+    if (n > 0 && (!x || !y || !z)) return fail(ctx, GMAPP_EINVAL, "input points must be non-NULL");
+    if (capacity > 0 && (!ox || !oy || !oz)) return fail(ctx, GMAPP_EINVAL, "output arrays must be non-NULL");
+    if (!n_out_dev) return fail(ctx, GMAPP_EINVAL, "n_out_dev must be non-NULL");
+    if (!lo || !dims) return fail(ctx, GMAPP_EINVAL, "lo and dims must be non-NULL");
+    if (!finite(voxel) || voxel <= 0.f) return fail(ctx, GMAPP_EINVAL, "voxel must be finite and > 0");
+    if (min_count < 1) return fail(ctx, GMAPP_EINVAL, "min_count must be >= 1");
+    gm::VoxGrid g;
+    g.voxel = voxel;
+    long long cells = 1;
+    for (int a = 0; a < 3; ++a) {
+        if (!finite(lo[a])) return fail(ctx, GMAPP_EINVAL, "lo must be finite");
+        if (dims[a] < 1) return fail(ctx, GMAPP_EINVAL, "dims must be >= 1");
+        g.lo[a] = lo[a];
+        g.dims[a] = dims[a];
+        cells *= dims[a];
+        if (cells > (1ll << 31)) return fail(ctx, GMAPP_ECAPACITY, "voxel grid exceeds 2^31 cells");
+    }
+    return gm::launch_voxel_downsample(ctx, x, y, z, n, g, (unsigned)min_count, ox, oy, oz, capacity,
+                                       reinterpret_cast<long long *>(n_out_dev), static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

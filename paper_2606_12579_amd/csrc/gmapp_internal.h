@@ -53,21 +53,41 @@ struct Probe {
 
 // cross-workgroup exchange area (part of the context arena)
 struct Xch {
-    float4 *partial;     // [2][G][S][A]
-    unsigned *flags;     // [G * S]   step counters, zero between launches
+    unsigned long long *partial;  // [2][wave groups][S][AW][4] words: Fx, Fy, Fz, min r2, each | step tag << 32
+    unsigned *flags;     // spare counters (zero between launches)
     unsigned *done;      // [1]       finished-workgroup counter, zero between launches
     unsigned *status;    // [1]       watchdog flag, zero between launches
     int S, G;
 };
 
+// camera-to-world transform, row-major 3x4 [R | t]
+struct Mat34 {
+    float r[12];
+};
+
+// voxel lattice over the workspace box: cells of size `voxel` from `lo`
+struct VoxGrid {
+    float lo[3];
+    float voxel;
+    int dims[3];
+};
+
 struct Tiling {
-    int A, W, S, tile;
+    int A, W, S;      // agents per group, waves per workgroup, shards
+    int tile;         // points per tile (streamed layout)
+    int layout;       // 0 auto, 1 resident, 2 streamed tiles
+    int wg;           // 0: every wave is a group; 1: the workgroup is one group
 };
 
 // ---------------------------------------------------------------- sizes
 constexpr int kMaxShards = 64;
+constexpr int kMaxGather = 256;                       // shards x agents per wave (LDS gather)
+constexpr int kMaxSegments = 1024;                    // moving segments per scene
+constexpr int kMaxGroups = 4096;                      // agent groups per launch
 constexpr int kMaxWorkgroups = 65536;
-constexpr size_t kSyncWords = kMaxWorkgroups + 64;   // flags + done + status (+ pad)
+constexpr size_t kCounterWords = (size_t)kMaxGroups * 16;
+constexpr size_t kSyncWords = kCounterWords + 64;     // counters + done + status (+ pad)
+constexpr size_t kXchgBytes = (size_t)16 << 20;       // rollout exchange area
 
 }  // namespace gm
 
@@ -79,10 +99,11 @@ struct gmapp_ctx {
     char *arena = nullptr;        // device arena
     size_t arena_bytes = 0;
     unsigned *sync = nullptr;     // kSyncWords, kept zero between launches
-    char *scratch = nullptr;      // remainder of the arena (partials, voxel grids, checkpoints)
+    unsigned long long *xchg = nullptr;  // rollout exchange words (kXchgBytes), kept zero between launches
+    char *scratch = nullptr;      // remainder of the arena (voxel grids, checkpoints, work tables)
     size_t scratch_bytes = 0;
     bool forced = false;
-    gmapp_tiling forced_tiling{0, 0, 0, 0};
+    gmapp_tiling forced_tiling{0, 0, 0, 0, 0, 0};
     std::string err;
 };
 
@@ -114,6 +135,15 @@ inline gmapp_status hip_fail(gmapp_ctx *ctx, hipError_t e, const char *what)
 gmapp_status launch_rollout(gmapp_ctx *ctx, const Scn &sc, const Agt &ag, const Prm &pr, const Out &out,
                             const Probe *probe, const Tiling &t, hipStream_t stream);
 Tiling choose_tiling(const gmapp_ctx *ctx, long long n_points, int n_agents, int n_steps, int n_seg, int cutoff);
-gmapp_status check_tiling(gmapp_ctx *ctx, const Tiling &t, int n_agents, int cutoff);
+
+// perception (perception.hip)
+gmapp_status launch_depth_to_points(gmapp_ctx *ctx, const float *depth, int w, int h, const float K[4],
+                                    const Mat34 &T, float *x, float *y, float *z, hipStream_t stream);
+size_t voxel_workspace_bytes(long long cells);
+gmapp_status launch_voxel_downsample(gmapp_ctx *ctx, const float *x, const float *y, const float *z, long long n,
+                                     const VoxGrid &g, unsigned min_count, float *ox, float *oy, float *oz,
+                                     long long capacity, long long *n_out_dev, hipStream_t stream);
+gmapp_status check_tiling(gmapp_ctx *ctx, const Tiling &t, long long n_points, int n_seg, int cutoff);
+size_t rollout_lds_bytes(const Tiling &t, long long n_points, int n_seg);
 
 }  // namespace gm

@@ -2,17 +2,25 @@
 // and Alg. 1), one persistent launch per planning cycle, for gfx950 (CDNA4).
 //
 // Work decomposition
-//   A workgroup owns A agents ("agent group") and one shard of the sphere world:
-//   a contiguous range of the N_O points.  Its 64*W lanes are (agent, slice)
-//   pairs: lane = agent + A * slice, so each agent's share of the shard is split
-//   over L = 64*W/A slices.  The shard's points sit in LDS (SoA x|y|z) for the
-//   whole rollout when they fit, else they are streamed through LDS tiles each
-//   step.  Every point read from LDS is used by A lanes at once (LDS broadcast).
-//   S workgroups (shards) cover one agent group; after each step they exchange
-//   their partial sums through the context arena (one agent-scope release and
-//   acquire per step) and each adds the S partials in shard order, so all
-//   shards hold bit-identical agent states.  Shards of one group are placed on
-//   one XCD (workgroups are dispatched round-robin over the 8 XCDs).
+//   Every wavefront is an independent agent group: its 64 lanes are (agent,
+//   slice) pairs, lane = agent + AW * slice, so each of its AW agents spreads the
+//   shard's points over L = 64 / AW lanes.  A workgroup of W waves holds W such
+//   groups (W * AW agents) and one shard of the sphere world (a contiguous range of
+//   the N_O points) in LDS, read by all its waves; S workgroups (shards) cover the
+//   points.  Points of one segment (object) are dealt round-robin to the L lanes,
+//   so every point read is broadcast to the AW agents of its slice, segment runs
+//   change at the same loop index in all lanes, and a run wastes at most one
+//   interaction per lane.  No workgroup barrier sits in the step loop when the
+//   shard is LDS-resident; shards too large for LDS are streamed through tiles.
+//
+//   After each step the S shards of a wave group exchange partial sums through the
+//   context arena.  Each 64-bit word carries one float and the step number, so a
+//   reader knows a word is current without any fence or counter: the device-scope
+//   (sc1) stores and loads are single-copy atomic.  Every shard adds the S
+//   partials in shard order, so all shards hold bit-identical agent states.
+//   Shards of a group are placed on one XCD (dispatch is round-robin over 8 XCDs).
+//   Waves wait for their own exchange only, so the waves of a CU overlap one
+//   another's exchange latency.
 //
 // Per interaction (agent i, sphere j) the lane evaluates the factored form of
 // Eq. (2) with the current vector c = omega - n (n . omega):
@@ -20,25 +28,27 @@
 // where P_w projects out w (the relative velocity, uniform over a segment) so
 //   sum_j f_j = k_f |w| P_w (omega G - S),  G = sum g_j,  S = sum g_j (d_j . omega) d_j / |d_j|^2.
 // The lane accumulates G, S (4 floats) and min |d|^2 over its points with
-// 20 VALU ops and 2 transcendentals (rsq, rcp) per interaction; P_w is applied
-// once per segment run.  rho_min^(k) = max(sqrt(min |d|^2) - (r_O + r_a), eps).
+// 20 VALU ops and 2 transcendentals (rsq, rcp) per interaction.
+// rho_min^(k) = max(sqrt(min |d|^2) - (r_O + r_a), eps).
 //
 // Integration (Eqs. 6, 7, 9-11; explicit: forces use v^(k-1)) and the running
 // costs (Eqs. 17-20) are O(1) per agent per step; positions, velocities and
 // cost sums carry Kahan compensation.  The jerk of Eq. (20) uses the identity
 // p^(k) - 3p^(k-1) + 3p^(k-2) - p^(k-3) = (dt^2 / 2m) (F^(k-1) - F^(k-2)).
-// The last workgroup to finish applies the selection rule and resets the
-// exchange area to zero for the next launch.
+// The last workgroup to finish applies the selection rule and clears the
+// exchange area for the next launch.
 #include "gmapp_internal.h"
 
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 namespace gm {
 
 namespace {
 
 constexpr float kTiny = 1e-30f;                 // keeps |d|^2 > 0 (agent on a sphere centre)
+constexpr float kFar = 1e18f;                   // padding point: beyond any cut-off, never the minimum
 constexpr unsigned long long kWatchdogTicks = 400000000ull;  // 4 s of the 100 MHz real-time clock
 
 __device__ __forceinline__ void kahan_add(float &s, float &c, float x)
@@ -75,7 +85,7 @@ __device__ __forceinline__ void interact(float qx, float qy, float qz, float psx
     m2 = fminf(m2, r2);
 }
 
-// Points [b, e) of the LDS tile, slice `sl` of L.
+// Points [b, e) of the LDS copy, slice `sl` of L (round-robin).
 template <int L, int CUT>
 __device__ __forceinline__ void interact_run(const float *__restrict__ lx, const float *__restrict__ ly,
                                              const float *__restrict__ lz, int b, int e, int sl, float psx,
@@ -102,36 +112,131 @@ __device__ __forceinline__ void st_agent(unsigned *p, unsigned v)
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+__device__ __forceinline__ void st64_agent(unsigned long long *p, unsigned long long v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long ld64_agent(const unsigned long long *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// exchange word: float bits | step tag << 32
+__device__ __forceinline__ unsigned long long xword(float v, unsigned tag)
+{
+    return (unsigned long long)__float_as_uint(v) | ((unsigned long long)tag << 32);
+}
+__device__ __forceinline__ float xval(unsigned long long q) { return __uint_as_float((unsigned)q); }
+__device__ __forceinline__ unsigned xtag(unsigned long long q) { return (unsigned)(q >> 32); }
+
+// Sum / min over the lanes of one agent (lanes congruent mod AW) of a wavefront,
+// leaving the identical result in every such lane: rotations by 8, 4, 2, 1 inside
+// 16-lane rows (DPP), then the xor-16 swizzle and the 32-lane swap.  Each stage
+// adds a partner whose own partner holds an equal value, so commutativity makes
+// every lane's result bit-identical.
+template <int AW, bool MIN>
+__device__ __forceinline__ float agent_allreduce(float x)
+{
+    auto op = [](float a, float b) { return MIN ? fminf(a, b) : a + b; };
+    auto dpp = [](float v, auto ctrl) {
+        return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), decltype(ctrl)::value, 0xF, 0xF, false));
+    };
+    if constexpr (AW <= 8) x = op(x, dpp(x, std::integral_constant<int, 0x128>{}));   // row_ror:8
+    if constexpr (AW <= 4) x = op(x, dpp(x, std::integral_constant<int, 0x124>{}));   // row_ror:4
+    if constexpr (AW <= 2) x = op(x, dpp(x, std::integral_constant<int, 0x122>{}));   // row_ror:2
+    if constexpr (AW <= 1) x = op(x, dpp(x, std::integral_constant<int, 0x121>{}));   // row_ror:1
+    if constexpr (AW <= 16) x = op(x, __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(x), 0x401F)));
+    if constexpr (AW <= 32) {
+        auto sw = __builtin_amdgcn_permlane32_swap(__float_as_int(x), __float_as_int(x), false, false);
+        x = op(__int_as_float(sw[0]), __int_as_float(sw[1]));
+    }
+    return x;
+}
+
+// k_f |w| P_w (omega G - S) added to F (w = relative velocity, uniform over the segment)
+__device__ __forceinline__ void project_add(float ux, float uy, float uz, float kf, float wx, float wy, float wz,
+                                            float G, float Sx, float Sy, float Sz, float &Fx, float &Fy, float &Fz)
+{
+    const float w2 = fmaf(uz, uz, fmaf(uy, uy, ux * ux));
+    if (w2 > 0.0f) {
+        const float cx = fmaf(wx, G, -Sx), cy = fmaf(wy, G, -Sy), cz = fmaf(wz, G, -Sz);
+        const float ri = __builtin_amdgcn_rsqf(w2);
+        const float wc = fmaf(uz, cz, fmaf(uy, cy, ux * cx)) * (ri * ri);
+        const float f = kf * (w2 * ri);
+        Fx = fmaf(f, fmaf(-ux, wc, cx), Fx);
+        Fy = fmaf(f, fmaf(-uy, wc, cy), Fy);
+        Fz = fmaf(f, fmaf(-uz, wc, cz), Fz);
+    }
+}
+
 struct Agent {
     float ka, da, kf, rd, R, wx, wy, wz, tb_a, tb_b;
 };
 
 }  // namespace
 
-// PROBE: one teacher-forced step at the given states (no integration, no costs).
-template <int A, int W, int CUT, bool PROBE>
-__global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out out, Probe pb, Xch xc, int tile_cap)
+// Launch-time layout of the shard in LDS.
+struct Lay {
+    int resident;   // 1 = the whole shard is loaded once, 0 = streamed tiles
+    int cap;        // points held in LDS (shard capacity or tile size)
+    int runs_cap;   // segment runs per shard
+};
+
+// Dynamic LDS layout of k_rollout, in bytes (16-byte aligned pieces):
+//   x | y | z [cap]  ·  red float4 [2][W][AW]  ·  tot float4 [groups][AW]  ·  xt float4 [groups][S*AW]
+//   ·  runs int4 [runs_cap]  ·  rvel float4 [runs_cap]  ·  sel (float, int) [NT]
+struct LdsPlan {
+    size_t cx, cy, cz, red, tot, xt, runs, rvel, sel, total;
+};
+__host__ __device__ inline LdsPlan lds_plan(const Lay &l, int W, int WS, int AW, int S)
+{
+    LdsPlan p;
+    const size_t plane = ((size_t)l.cap * 4 + 15) / 16 * 16;
+    const int groups = W / WS;                    // agent groups per workgroup
+    p.cx = 0; p.cy = plane; p.cz = 2 * plane;
+    p.red = 3 * plane;                            // [2][W][AW] wave partials (WS > 1)
+    p.tot = p.red + (WS > 1 ? (size_t)2 * W * AW * 16 : 0);   // [groups][AW] group totals (WS > 1)
+    p.xt = p.tot + (WS > 1 ? (size_t)groups * AW * 16 : 0);
+    p.runs = p.xt + (S > 1 ? (size_t)groups * S * AW * 16 : 0);
+    p.rvel = p.runs + (size_t)l.runs_cap * 16;
+    p.sel = p.rvel + (size_t)l.runs_cap * 16;
+    p.total = p.sel + (size_t)64 * W * 8;
+    return p;
+}
+
+// An agent group is WS waves (1 or W) sharing AW agents; a workgroup holds W / WS
+// groups.  PROBE: one teacher-forced step at the given states (no integration, no costs).
+template <int AW, int W, int WS, int CUT, bool PROBE>
+__global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out out, Probe pb, Xch xc, Lay lay)
 {
     constexpr int NT = 64 * W;
-    constexpr int L = NT / A;                     // slices per agent
-    static_assert(A >= 1 && A <= NT && NT % A == 0, "agents per block");
+    constexpr int GPW = W / WS;                   // agent groups per workgroup
+    constexpr int L = 64 * WS / AW;               // slices per agent
+    static_assert(AW >= 1 && AW <= 64 && 64 % AW == 0, "agents per group");
+    static_assert(WS == 1 || WS == W, "a group is one wave or the whole workgroup");
     extern __shared__ float4 lds4[];
-    float *lx = reinterpret_cast<float *>(lds4);
-    float *ly = lx + tile_cap;
-    float *lz = ly + tile_cap;
-    float4 *red = lds4 + (3 * tile_cap + 3) / 4;  // [2][NT]
-    float4 *tot = red + 2 * NT;                   // [A]
-    __shared__ int s_last;
+    const int S = xc.S, G = xc.G;                // G: workgroups per shard
+    const LdsPlan lp = lds_plan(lay, W, WS, AW, S);
+    char *lds = reinterpret_cast<char *>(lds4);
+    float *lx = reinterpret_cast<float *>(lds + lp.cx);
+    float *ly = reinterpret_cast<float *>(lds + lp.cy);
+    float *lz = reinterpret_cast<float *>(lds + lp.cz);
+    int4 *runs = reinterpret_cast<int4 *>(lds + lp.runs);      // [runs_cap]: begin, end, first slice, slices
+    float4 *rvel = reinterpret_cast<float4 *>(lds + lp.rvel);  // [runs_cap]
+    __shared__ int s_last, s_nruns, s_split;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    const int a_loc = tid % A;
-    const int slice = tid / A;
-    const int S = xc.S, G = xc.G;
+    const int gi = wave / WS;                     // group within the workgroup
+    const int a_w = lane % AW;
+    const int slice = ((wave % WS) * 64 + lane) / AW;
+    const bool lead = (wave % WS) == 0;           // the group's wave that exchanges with other shards
+    float4 *red = reinterpret_cast<float4 *>(lds + lp.red);
+    float4 *tot = reinterpret_cast<float4 *>(lds + lp.tot) + (size_t)gi * AW;
+    float4 *xtw = reinterpret_cast<float4 *>(lds + lp.xt) + (size_t)gi * S * AW;  // this group's gather
 
-    // workgroup -> (agent group g, shard s); for S > 1 the S shards of a group
-    // share an XCD (dispatch is round-robin over 8 XCDs)
+    // workgroup -> (group g, shard s); for S > 1 the S shards of a group share an
+    // XCD (dispatch is round-robin over 8 XCDs)
     int g, s;
     if (S > 1) {
         const int nwg = gridDim.x;                // multiple of 8
@@ -144,7 +249,9 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
     }
     if (g >= G) return;                           // padding workgroup (not counted in `done`)
 
-    const int agent = g * A + a_loc;
+    const int GW = G * GPW;                       // agent groups in the launch
+    const int gw = g * GPW + gi;                  // this lane's group
+    const int agent = gw * AW + a_w;
     const bool valid = agent < ag.n;
     const int ai = valid ? agent : 0;
     Agent P;
@@ -163,18 +270,110 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
     if (sc.n_dev) n_pts = min(max(*sc.n_dev, 0ll), sc.n_cap);
     const long long sb = n_pts * s / S, se = n_pts * (s + 1) / S;
     const long long n_shard = se - sb;
-    const bool resident = n_shard <= (long long)tile_cap;
 
-    auto load_tile = [&](long long tb, int cnt) {
-        for (int i = tid; i < cnt; i += NT) {
-            lx[i] = sc.x[tb + i];
-            ly[i] = sc.y[tb + i];
-            lz[i] = sc.z[tb + i];
+    // segment runs of this shard: [begin, end) relative to sb and the run's
+    // velocity (0 for static points).  A table that is not non-decreasing still
+    // yields runs covering the shard exactly once.
+    if (tid == 0) {
+        int nr = 0;
+        if (sc.n_seg == 0) {
+            if (n_shard > 0) {
+                runs[0] = make_int4(0, (int)n_shard, 0, 0);
+                rvel[0] = make_float4(0.f, 0.f, 0.f, 0.f);
+                nr = 1;
+            }
+        } else {
+            auto clampi = [&](long long v) { return min(max(v, 0ll), n_pts); };
+            int lo = 0, hi = sc.n_seg;             // first segment whose end > sb
+            while (lo < hi) {
+                int mid = (lo + hi) >> 1;
+                if (clampi(sc.seg_begin[mid + 1]) > sb) hi = mid; else lo = mid + 1;
+            }
+            int si = lo;
+            long long c = sb;
+            while (c < se && nr < lay.runs_cap - 1) {
+                long long re;
+                float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (si < sc.n_seg) {
+                    long long b_s = clampi(sc.seg_begin[si]), e_s = clampi(sc.seg_begin[si + 1]);
+                    if (b_s <= c) {
+                        re = min(e_s, se);
+                        v = make_float4(sc.seg_vel[3 * si], sc.seg_vel[3 * si + 1], sc.seg_vel[3 * si + 2], 0.f);
+                    } else {
+                        re = min(b_s, se);
+                    }
+                } else {
+                    re = se;
+                }
+                if (re <= c) re = se;
+                runs[nr] = make_int4((int)(c - sb), (int)(re - sb), 0, 0);
+                rvel[nr] = v;
+                ++nr;
+                c = re;
+                while (si < sc.n_seg && clampi(sc.seg_begin[si + 1]) <= c) ++si;
+            }
+            if (c < se) {                           // out of slots (malformed table): rest static
+                runs[nr] = make_int4((int)(c - sb), (int)n_shard, 0, 0);
+                rvel[nr] = make_float4(0.f, 0.f, 0.f, 0.f);
+                ++nr;
+            }
         }
-    };
-    if (resident) {
-        load_tile(sb, (int)n_shard);
-        __syncthreads();
+        // split the L slices of every agent over the runs in proportion to their
+        // length (at least one slice each), so that each lane walks one run only
+        int split = (nr > 0 && nr <= L) ? 1 : 0;
+        if (split) {
+            int used = 0;
+            for (int r = 0; r < nr; ++r) {
+                const long long len = runs[r].y - runs[r].x;
+                runs[r].w = max(1, (int)(len * L / max(n_shard, 1ll)));
+                used += runs[r].w;
+            }
+            while (used > L) {                      // give back slices where they cost least
+                int best = -1;
+                for (int r = 0; r < nr; ++r)
+                    if (runs[r].w > 1 && (best < 0 || (long long)(runs[r].y - runs[r].x) * runs[best].w <
+                                                       (long long)(runs[best].y - runs[best].x) * runs[r].w))
+                        best = r;
+                --runs[best].w;
+                --used;
+            }
+            while (used < L) {                      // add slices where the points per slice are highest
+                int best = 0;
+                for (int r = 1; r < nr; ++r)
+                    if ((long long)(runs[r].y - runs[r].x) * runs[best].w >
+                        (long long)(runs[best].y - runs[best].x) * runs[r].w)
+                        best = r;
+                ++runs[best].w;
+                ++used;
+            }
+            int first = 0;
+            for (int r = 0; r < nr; ++r) {
+                runs[r].z = first;
+                first += runs[r].w;
+            }
+        }
+        s_split = split;
+        s_nruns = nr;
+    }
+    const bool resident = lay.resident && n_shard <= (long long)lay.cap;
+    if (resident)
+        for (int i = tid; i < (int)n_shard; i += NT) {
+            lx[i] = sc.x[sb + i]; ly[i] = sc.y[sb + i]; lz[i] = sc.z[sb + i];
+        }
+    __syncthreads();
+    const int n_runs = s_nruns;
+    // this lane's run when the slices are split over the runs (resident layout)
+    const bool split = resident && s_split;
+    int my_j0 = 0, my_n = 0, my_stride = 1;
+    float4 my_v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (split) {
+        int r = 0;
+        while (r + 1 < n_runs && runs[r + 1].z <= slice) ++r;
+        const int4 rr = runs[r];
+        my_j0 = rr.x + (slice - rr.z);
+        my_stride = rr.w;
+        my_n = (rr.y > my_j0) ? (rr.y - my_j0 + rr.w - 1) / rr.w : 0;
+        my_v = rvel[r];
     }
 
     // agent state
@@ -193,6 +392,7 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
     const float gx = pr.goal[0], gy = pr.goal[1], gz = pr.goal[2];
     const float h = 0.5f * pr.dt * pr.inv_mass;
     const float hj = h * pr.dt;                                     // dt^2 / 2m
+    const float inv_rc = 1.0f / pr.r_cost;
     const bool writer = valid && s == 0 && slice == 0 && !PROBE;
     const int n_steps = PROBE ? 1 : pr.n_steps;
     const size_t traj_row = (size_t)(pr.n_steps + 1) * 3;
@@ -207,135 +407,116 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
         float Fx = 0, Fy = 0, Fz = 0, m2 = INFINITY;
 
         // ---- pairwise pass over this shard (hot loop)
-        for (long long tb = sb; tb < se; tb += tile_cap) {
-            const int cnt = (int)min((long long)tile_cap, se - tb);
+        if (split) {
+            const float psx = fmaf(-t, my_v.x, px), psy = fmaf(-t, my_v.y, py), psz = fmaf(-t, my_v.z, pz);
+            float Gs = 0, Sx = 0, Sy = 0, Sz = 0;
+            int j = my_j0;
+#pragma unroll 4
+            for (int i = 0; i < my_n; ++i, j += my_stride)
+                interact<CUT>(lx[j], ly[j], lz[j], psx, psy, psz, P.wx, P.wy, P.wz, P.R, pr.eps, P.rd, P.tb_a, P.tb_b,
+                              Gs, Sx, Sy, Sz, m2);
+            project_add(vx - my_v.x, vy - my_v.y, vz - my_v.z, P.kf, P.wx, P.wy, P.wz, Gs, Sx, Sy, Sz, Fx, Fy, Fz);
+        }
+        const int tile = resident ? (int)max(n_shard, 1ll) : lay.cap;
+        for (long long tb = sb; tb < se && !split; tb += tile) {
+            const int tn = (int)min((long long)tile, se - tb);
             if (!resident) {
                 __syncthreads();
-                load_tile(tb, cnt);
+                for (int i = tid; i < tn; i += NT) {
+                    lx[i] = sc.x[tb + i]; ly[i] = sc.y[tb + i]; lz[i] = sc.z[tb + i];
+                }
                 __syncthreads();
             }
-            const long long te = tb + cnt;
-            // walk the segment runs covering [tb, te) (uniform control flow)
-            int si = 0;
-            if (sc.n_seg > 0) {
-                int lo = 0, hi = sc.n_seg;               // first segment whose end > tb
-                while (lo < hi) {
-                    int mid = (lo + hi) >> 1;
-                    long long e_mid = min(max((long long)sc.seg_begin[mid + 1], 0ll), n_pts);
-                    if (e_mid > tb) hi = mid; else lo = mid + 1;
-                }
-                si = lo;
-            }
-            long long c = tb;
-            while (c < te) {
-                long long re;
-                float ox = 0, oy = 0, oz = 0;
-                if (si < sc.n_seg) {
-                    long long b_s = min(max((long long)sc.seg_begin[si], 0ll), n_pts);
-                    long long e_s = min(max((long long)sc.seg_begin[si + 1], 0ll), n_pts);
-                    if (b_s <= c) {
-                        re = min(e_s, te);
-                        ox = sc.seg_vel[3 * si]; oy = sc.seg_vel[3 * si + 1]; oz = sc.seg_vel[3 * si + 2];
-                    } else {
-                        re = min(b_s, te);
-                    }
-                } else {
-                    re = te;
-                }
-                if (re <= c) re = te;                    // malformed table: finish the tile as static
-                // agent position relative to the moving segment, and relative velocity
-                const float psx = fmaf(-t, ox, px), psy = fmaf(-t, oy, py), psz = fmaf(-t, oz, pz);
+            const int t0r = (int)(tb - sb), t1r = t0r + tn;
+            for (int r = 0; r < n_runs; ++r) {
+                const int4 rr = runs[r];
+                const int b = max(rr.x, t0r), e = min(rr.y, t1r);
+                if (b >= e) continue;
+                const float4 ov = rvel[r];
+                // agent position relative to the moving segment
+                const float psx = fmaf(-t, ov.x, px), psy = fmaf(-t, ov.y, py), psz = fmaf(-t, ov.z, pz);
                 float Gs = 0, Sx = 0, Sy = 0, Sz = 0;
-                interact_run<L, CUT>(lx, ly, lz, (int)(c - tb), (int)(re - tb), slice, psx, psy, psz, P.wx, P.wy,
-                                     P.wz, P.R, pr.eps, P.rd, P.tb_a, P.tb_b, Gs, Sx, Sy, Sz, m2);
-                const float ux = vx - ox, uy = vy - oy, uz = vz - oz;
-                const float w2 = fmaf(uz, uz, fmaf(uy, uy, ux * ux));
-                if (w2 > 0.0f) {
-                    const float cx = fmaf(P.wx, Gs, -Sx), cy = fmaf(P.wy, Gs, -Sy), cz = fmaf(P.wz, Gs, -Sz);
-                    const float wn = sqrtf(w2);
-                    const float wc = fmaf(uz, cz, fmaf(uy, cy, ux * cx)) / w2;
-                    const float f = P.kf * wn;
-                    Fx = fmaf(f, fmaf(-ux, wc, cx), Fx);
-                    Fy = fmaf(f, fmaf(-uy, wc, cy), Fy);
-                    Fz = fmaf(f, fmaf(-uz, wc, cz), Fz);
-                }
-                c = re;
-                while (si < sc.n_seg && min(max((long long)sc.seg_begin[si + 1], 0ll), n_pts) <= c) ++si;
+                interact_run<L, CUT>(lx, ly, lz, b - t0r, e - t0r, slice, psx, psy, psz, P.wx, P.wy, P.wz, P.R,
+                                     pr.eps, P.rd, P.tb_a, P.tb_b, Gs, Sx, Sy, Sz, m2);
+                project_add(vx - ov.x, vy - ov.y, vz - ov.z, P.kf, P.wx, P.wy, P.wz, Gs, Sx, Sy, Sz, Fx, Fy, Fz);
             }
         }
 
         // ---- reduce over the slices of each agent: inside the wave ...
-        if constexpr (A < 64) {
-#pragma unroll
-            for (int off = A; off < 64; off <<= 1) {
-                Fx += __shfl_xor(Fx, off, 64);
-                Fy += __shfl_xor(Fy, off, 64);
-                Fz += __shfl_xor(Fz, off, 64);
-                m2 = fminf(m2, __shfl_xor(m2, off, 64));
-            }
+        if constexpr (AW < 64) {
+            Fx = agent_allreduce<AW, false>(Fx);
+            Fy = agent_allreduce<AW, false>(Fy);
+            Fz = agent_allreduce<AW, false>(Fz);
+            m2 = agent_allreduce<AW, true>(m2);
         }
-        // ... then across waves and shards
-        constexpr int NR = (A <= 64) ? W : L;    // partials per agent in the workgroup
         const int par = k & 1;
-        if (NR > 1 || S > 1) {
-            const bool rep = (A <= 64) ? (lane < A) : true;
-            const int r_idx = (A <= 64) ? wave : slice;
-            if (rep) red[par * NT + r_idx * A + a_loc] = make_float4(Fx, Fy, Fz, m2);
+        // ... across the waves of a workgroup-wide group (LDS) ...
+        if constexpr (WS > 1) {
+            if (lane < AW) red[(par * W + wave) * AW + lane] = make_float4(Fx, Fy, Fz, m2);
             __syncthreads();
-            if (S == 1) {
-                float4 acc = red[par * NT + a_loc];
+            float4 acc = red[(par * W) * AW + a_w];
 #pragma unroll
-                for (int r = 1; r < NR; ++r) {
-                    float4 q = red[par * NT + r * A + a_loc];
-                    acc.x += q.x; acc.y += q.y; acc.z += q.z; acc.w = fminf(acc.w, q.w);
+            for (int r = 1; r < W; ++r) {
+                const float4 q = red[(par * W + r) * AW + a_w];
+                acc.x += q.x; acc.y += q.y; acc.z += q.z; acc.w = fminf(acc.w, q.w);
+            }
+            Fx = acc.x; Fy = acc.y; Fz = acc.z; m2 = acc.w;
+        }
+        // ... and over the shards (device-scope exchange by the group's lead wave)
+        if (S > 1) {
+            const unsigned tag = (unsigned)k;
+            if (lead) {
+                if (lane < AW) {
+                    unsigned long long *slot = xc.partial + 4 * (((size_t)(par * GW + gw) * S + s) * AW + lane);
+                    st64_agent(slot, xword(Fx, tag));
+                    st64_agent(slot + 1, xword(Fy, tag));
+                    st64_agent(slot + 2, xword(Fz, tag));
+                    st64_agent(slot + 3, xword(m2, tag));
                 }
-                Fx = acc.x; Fy = acc.y; Fz = acc.z; m2 = acc.w;
-            } else {
-                // A <= 64 here (checked on the host): wave 0 publishes and gathers
-                if (wave == 0) {
-                    float4 acc = make_float4(0.f, 0.f, 0.f, INFINITY);
-                    if (lane < A) {
-                        acc = red[par * NT + lane];
-#pragma unroll
-                        for (int r = 1; r < NR; ++r) {
-                            float4 q = red[par * NT + r * A + lane];
-                            acc.x += q.x; acc.y += q.y; acc.z += q.z; acc.w = fminf(acc.w, q.w);
+                // each lane watches the last word of (shard, agent) slots, then reads and checks all four
+                for (int l = lane; l < S * AW; l += 64) {
+                    const unsigned long long *slot =
+                        xc.partial + 4 * (((size_t)(par * GW + gw) * S + l / AW) * AW + l % AW);
+                    unsigned long long q0, q1, q2, q3;
+                    unsigned spins = 0;
+                    while (true) {
+                        q3 = ld64_agent(slot + 3);
+                        if (xtag(q3) == tag) {
+                            q0 = ld64_agent(slot); q1 = ld64_agent(slot + 1); q2 = ld64_agent(slot + 2);
+                            if (xtag(q0) == tag && xtag(q1) == tag && xtag(q2) == tag) break;
                         }
-                        xc.partial[((size_t)(par * G + g) * S + s) * A + lane] = acc;
-                    }
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-                    if (lane == 0) st_agent(&xc.flags[g * S + s], (unsigned)k);
-                    if (lane < S) {
-                        unsigned spins = 0;
-                        while (ld_agent(&xc.flags[g * S + lane]) < (unsigned)k) {
-                            __builtin_amdgcn_s_sleep(1);
-                            if ((++spins & 255u) == 0) {
-                                if (ld_agent(xc.status) != 0u) break;
-                                if (__builtin_amdgcn_s_memrealtime() - t_start > kWatchdogTicks) {
-                                    st_agent(xc.status, 1u);
-                                    break;
-                                }
+                        __builtin_amdgcn_s_sleep(2);
+                        if ((++spins & 63u) == 0) {
+                            if (ld_agent(xc.status) != 0u) break;
+                            if (__builtin_amdgcn_s_memrealtime() - t_start > kWatchdogTicks) {
+                                st_agent(xc.status, 1u);
+                                break;
                             }
                         }
                     }
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-                    if (lane < A) {
-                        const float4 *pp = xc.partial + (size_t)(par * G + g) * S * A + lane;
-                        float4 a4 = pp[0];
-                        for (int r = 1; r < S; ++r) {
-                            float4 q = pp[(size_t)r * A];
-                            a4.x += q.x; a4.y += q.y; a4.z += q.z; a4.w = fminf(a4.w, q.w);
-                        }
-                        tot[lane] = a4;
-                    }
+                    xtw[l] = make_float4(xval(q0), xval(q1), xval(q2), xval(q3));
                 }
-                __syncthreads();
-                float4 a4 = tot[a_loc];
+                __builtin_amdgcn_wave_barrier();
+                float4 a4 = xtw[a_w];
+                for (int r = 1; r < S; ++r) {           // fixed shard order in every shard
+                    const float4 q = xtw[r * AW + a_w];
+                    a4.x += q.x; a4.y += q.y; a4.z += q.z; a4.w = fminf(a4.w, q.w);
+                }
                 Fx = a4.x; Fy = a4.y; Fz = a4.z; m2 = a4.w;
+                if constexpr (WS > 1) {
+                    if (lane < AW) tot[lane] = a4;
+                }
+            }
+            if constexpr (WS > 1) {
+                __syncthreads();
+                const float4 a4 = tot[a_w];
+                Fx = a4.x; Fy = a4.y; Fz = a4.z; m2 = a4.w;
+            } else {
+                __builtin_amdgcn_wave_barrier();        // xtw is rewritten next step
             }
         }
 
-        const float rho_min = (m2 < INFINITY) ? fmaxf(sqrtf(m2) - P.R, pr.eps) : INFINITY;
+        const float rho_min = (m2 < INFINITY) ? fmaxf(__builtin_amdgcn_sqrtf(m2) - P.R, pr.eps) : INFINITY;
         if constexpr (PROBE) {
             if (valid && s == 0 && slice == 0) {
                 pb.f_r[3 * agent] = Fx; pb.f_r[3 * agent + 1] = Fy; pb.f_r[3 * agent + 2] = Fz;
@@ -349,10 +530,10 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
         const float Ftx = fmaf(P.ka, ex, fmaf(-P.da, vx, Fx));
         const float Fty = fmaf(P.ka, ey, fmaf(-P.da, vy, Fy));
         const float Ftz = fmaf(P.ka, ez, fmaf(-P.da, vz, Fz));
-        const float dgoal = sqrtf(fmaf(ez, ez, fmaf(ey, ey, ex * ex)));
-        kahan_add(sg, cg, fminf(dgoal, pr.r_cost) / pr.r_cost);
-        kahan_add(so, co, 1.0f - fminf(rho_min, pr.r_cost) / pr.r_cost);
-        if (k >= 2) kahan_add(sp, cp, pr.dt * sqrtf(fmaf(vz, vz, fmaf(vy, vy, vx * vx))));
+        const float dgoal = __builtin_amdgcn_sqrtf(fmaf(ez, ez, fmaf(ey, ey, ex * ex)));
+        kahan_add(sg, cg, fminf(dgoal, pr.r_cost) * inv_rc);
+        kahan_add(so, co, 1.0f - fminf(rho_min, pr.r_cost) * inv_rc);
+        if (k >= 2) kahan_add(sp, cp, pr.dt * __builtin_amdgcn_sqrtf(fmaf(vz, vz, fmaf(vy, vy, vx * vx))));
         if (k >= 4) {
             const float jx = hj * (F1x - F2x), jy = hj * (F1y - F2y), jz = hj * (F1z - F2z);
             kahan_add(sj, cj, fmaf(jz, jz, fmaf(jy, jy, jx * jx)));
@@ -373,6 +554,7 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
             if (out.min_clear) out.min_clear[(size_t)agent * pr.n_steps + (k - 1)] = rho_min;
         }
     }
+
     // ---- final costs (Eqs. 16-20)
     if (writer) {
         const float N = (float)pr.n_steps;
@@ -389,7 +571,7 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
         co5[0] = Cg; co5[1] = Co; co5[2] = Cp; co5[3] = Cs; co5[4] = C;
     }
 
-    // ---- last workgroup: selection rule, then reset the exchange area
+    // ---- last workgroup: selection rule, then clear the exchange area
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
     if (tid == 0) {
@@ -400,42 +582,47 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
     if (!s_last) return;
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     if constexpr (!PROBE) {
-    // argmin over C_i (ties -> lowest index, NaN never wins), incumbent rule
-    const int inc = (pr.incumbent >= 0 && pr.incumbent < ag.n) ? pr.incumbent : -1;
-    const float bound = inc >= 0 ? pr.alpha * out.cost[5 * (size_t)inc + 4] : INFINITY;
-    float bv = INFINITY;
-    int bi = -1;
-    for (int i = tid; i < ag.n; i += NT) {
-        float c = out.cost[5 * (size_t)i + 4];
-        if (!(c == c)) continue;
-        if (inc >= 0 && !(c < bound)) continue;
-        if (bi < 0 || c < bv) { bv = c; bi = i; }
-    }
-    // block reduction of (bv, bi): smaller value, then smaller index
-    float *rv = reinterpret_cast<float *>(red);
-    int *ri = reinterpret_cast<int *>(red) + NT;
-    rv[tid] = bv;
-    ri[tid] = bi;
-    __syncthreads();
-    for (int off = NT / 2; off > 0; off >>= 1) {
-        if (tid < off) {
-            float v2 = rv[tid + off];
-            int i2 = ri[tid + off];
-            if (i2 >= 0 && (ri[tid] < 0 || v2 < rv[tid] || (v2 == rv[tid] && i2 < ri[tid]))) {
-                rv[tid] = v2;
-                ri[tid] = i2;
-            }
+        // argmin over C_i (ties -> lowest index, NaN never wins), incumbent rule
+        const int inc = (pr.incumbent >= 0 && pr.incumbent < ag.n) ? pr.incumbent : -1;
+        const float bound = inc >= 0 ? pr.alpha * out.cost[5 * (size_t)inc + 4] : INFINITY;
+        float bv = INFINITY;
+        int bi = -1;
+        for (int i = tid; i < ag.n; i += NT) {
+            float c = out.cost[5 * (size_t)i + 4];
+            if (!(c == c)) continue;
+            if (inc >= 0 && !(c < bound)) continue;
+            if (bi < 0 || c < bv) { bv = c; bi = i; }
         }
+        // block reduction of (bv, bi): smaller value, then smaller index
+        float *rv = reinterpret_cast<float *>(lds + lp.sel);
+        int *ri = reinterpret_cast<int *>(lds + lp.sel) + NT;
+        rv[tid] = bv;
+        ri[tid] = bi;
         __syncthreads();
+        for (int off = NT / 2; off > 0; off >>= 1) {
+            if (tid < off) {
+                float v2 = rv[tid + off];
+                int i2 = ri[tid + off];
+                if (i2 >= 0 && (ri[tid] < 0 || v2 < rv[tid] || (v2 == rv[tid] && i2 < ri[tid]))) {
+                    rv[tid] = v2;
+                    ri[tid] = i2;
+                }
+            }
+            __syncthreads();
+        }
+        if (tid == 0) {
+            int best = ri[0];
+            if (best < 0) best = inc;             // no candidate beats the incumbent (or N_a = 0)
+            if (ld_agent(xc.status) != 0u) best = GMAPP_ETIMEOUT;
+            out.best[0] = best;
+        }
+    } else {
+        if (tid == 0 && ld_agent(xc.status) != 0u && pb.rho_min) pb.rho_min[0] = NAN;
     }
-    if (tid == 0) {
-        int best = ri[0];
-        if (best < 0) best = inc;                 // no candidate beats the incumbent (or N_a = 0)
-        if (ld_agent(xc.status) != 0u) best = GMAPP_ETIMEOUT;
-        out.best[0] = best;
+    if (S > 1) {
+        const size_t words = (size_t)2 * GW * S * AW * 4;
+        for (size_t i = tid; i < words; i += NT) st64_agent(xc.partial + i, 0ull);
     }
-    }
-    for (int i = tid; i < G * S; i += NT) st_agent(&xc.flags[i], 0u);
     if (tid == 0) {
         st_agent(xc.status, 0u);
         st_agent(xc.done, 0u);
@@ -450,85 +637,136 @@ __global__ void k_write_best(int *best, int v)
 // ---------------------------------------------------------------- host side
 namespace {
 
-using KFn = void (*)(Scn, Agt, Prm, Out, Probe, Xch, int);
+using KFn = void (*)(Scn, Agt, Prm, Out, Probe, Xch, Lay);
 
-template <int A, int W>
+template <int AW, int W, int WS>
 KFn pick_cut(int cut, bool probe)
 {
-    if (probe) return cut ? k_rollout<A, W, 1, true> : k_rollout<A, W, 0, true>;
-    return cut ? k_rollout<A, W, 1, false> : k_rollout<A, W, 0, false>;
+    if (probe) return cut ? k_rollout<AW, W, WS, 1, true> : k_rollout<AW, W, WS, 0, true>;
+    return cut ? k_rollout<AW, W, WS, 1, false> : k_rollout<AW, W, WS, 0, false>;
 }
 
+// per-wave groups: every (AW, W); workgroup-wide groups: AW <= 8 with 4, 8 or 16 waves
 template <int W>
-KFn pick_a(int A, int cut, bool probe)
+KFn pick_a(int AW, bool wg, int cut, bool probe)
 {
-    switch (A) {
-    case 1: return pick_cut<1, W>(cut, probe);
-    case 2: return pick_cut<2, W>(cut, probe);
-    case 4: return pick_cut<4, W>(cut, probe);
-    case 8: return pick_cut<8, W>(cut, probe);
-    case 16: return pick_cut<16, W>(cut, probe);
-    case 32: return pick_cut<32, W>(cut, probe);
-    case 64: return pick_cut<64, W>(cut, probe);
-    case 128: if constexpr (W >= 2) return pick_cut<128, W>(cut, probe); else return nullptr;
-    case 256: if constexpr (W >= 4) return pick_cut<256, W>(cut, probe); else return nullptr;
+    if (wg) {
+        if constexpr (W >= 4) {
+            switch (AW) {
+            case 1: return pick_cut<1, W, W>(cut, probe);
+            case 2: return pick_cut<2, W, W>(cut, probe);
+            case 4: return pick_cut<4, W, W>(cut, probe);
+            case 8: return pick_cut<8, W, W>(cut, probe);
+            default: return nullptr;
+            }
+        }
+        return nullptr;
+    }
+    switch (AW) {
+    case 1: return pick_cut<1, W, 1>(cut, probe);
+    case 2: return pick_cut<2, W, 1>(cut, probe);
+    case 4: return pick_cut<4, W, 1>(cut, probe);
+    case 8: return pick_cut<8, W, 1>(cut, probe);
+    case 16: return pick_cut<16, W, 1>(cut, probe);
+    case 32: return pick_cut<32, W, 1>(cut, probe);
+    case 64: return pick_cut<64, W, 1>(cut, probe);
     default: return nullptr;
     }
 }
 
-KFn pick_kernel(int A, int W, int cut, bool probe)
+KFn pick_kernel(int AW, int W, bool wg, int cut, bool probe)
 {
     switch (W) {
-    case 1: return pick_a<1>(A, cut, probe);
-    case 2: return pick_a<2>(A, cut, probe);
-    case 4: return pick_a<4>(A, cut, probe);
-    case 8: return pick_a<8>(A, cut, probe);
+    case 1: return pick_a<1>(AW, wg, cut, probe);
+    case 2: return pick_a<2>(AW, wg, cut, probe);
+    case 4: return pick_a<4>(AW, wg, cut, probe);
+    case 8: return pick_a<8>(AW, wg, cut, probe);
+    case 16: return pick_a<16>(AW, wg, cut, probe);
     default: return nullptr;
     }
 }
 
-size_t lds_bytes(const Tiling &t)
-{
-    const int NT = 64 * t.W;
-    return (size_t)((3 * t.tile + 3) / 4) * 16 + (size_t)2 * NT * 16 + (size_t)t.A * 16;
-}
+constexpr size_t kLdsBudget = 160 * 1024;
 
 }  // namespace
 
-gmapp_status check_tiling(gmapp_ctx *ctx, const Tiling &t, int n_agents, int cutoff)
+// Layout for a tiling: the whole shard resident in LDS when it fits (or when
+// forced), else streamed tiles of t.tile points.
+Lay make_layout(const Tiling &t, long long n_points, int n_seg)
 {
-    if (!pick_kernel(t.A, t.W, cutoff, false))
-        return fail(ctx, GMAPP_EINVAL, "unsupported tiling: %d agents per block with %d waves", t.A, t.W);
+    Lay l;
+    l.runs_cap = 2 * n_seg + 2;
+    const long long per = (n_points + t.S - 1) / t.S;     // largest shard
+    l.resident = t.layout == 2 ? 0 : 1;
+    l.cap = (int)std::min<long long>(std::max<long long>(per, 1), 1 << 24);
+    if (t.layout == 0 && lds_plan(l, t.W, t.wg ? t.W : 1, t.A, t.S).total > kLdsBudget) l.resident = 0;
+    if (!l.resident) l.cap = t.tile > 0 ? t.tile : 4096;
+    return l;
+}
+
+size_t rollout_lds_bytes(const Tiling &t, long long n_points, int n_seg)
+{
+    Lay l = make_layout(t, n_points, n_seg);
+    return lds_plan(l, t.W, t.wg ? t.W : 1, t.A, t.S).total;
+}
+
+gmapp_status check_tiling(gmapp_ctx *ctx, const Tiling &t, long long n_points, int n_seg, int cutoff)
+{
+    if (!pick_kernel(t.A, t.W, t.wg != 0, cutoff, false))
+        return fail(ctx, GMAPP_EINVAL, "unsupported tiling: %d agents per %s with %d waves", t.A,
+                    t.wg ? "workgroup" : "wave", t.W);
     if (t.S < 1 || t.S > kMaxShards) return fail(ctx, GMAPP_EINVAL, "shards must be in [1, %d]", kMaxShards);
-    if (t.S > 1 && t.A > 64) return fail(ctx, GMAPP_EINVAL, "sharded tilings need at most 64 agents per block");
-    if (t.tile < 64) return fail(ctx, GMAPP_EINVAL, "tile_points must be >= 64");
-    if (lds_bytes(t) > 160 * 1024) return fail(ctx, GMAPP_ECAPACITY, "tile of %d points exceeds LDS", t.tile);
-    (void)n_agents;
+    if (t.S > 1 && t.S * t.A > kMaxGather)
+        return fail(ctx, GMAPP_EINVAL, "shards x agents per group must be <= %d", kMaxGather);
+    if (t.tile != 0 && t.tile < 64) return fail(ctx, GMAPP_EINVAL, "tile_points must be >= 64");
+    if (t.layout < 0 || t.layout > 2) return fail(ctx, GMAPP_EINVAL, "layout must be 0, 1 or 2");
+    if (n_seg > kMaxSegments) return fail(ctx, GMAPP_ECAPACITY, "at most %d segments are supported", kMaxSegments);
+    if (rollout_lds_bytes(t, n_points, n_seg) > kLdsBudget)
+        return fail(ctx, GMAPP_ECAPACITY, "tiling does not fit in LDS (%s layout)",
+                    make_layout(t, n_points, n_seg).resident ? "resident" : "streamed");
     return GMAPP_OK;
 }
 
 Tiling choose_tiling(const gmapp_ctx *ctx, long long n_points, int n_agents, int n_steps, int n_seg, int cutoff)
 {
-    (void)n_steps; (void)n_seg; (void)cutoff;
+    (void)n_steps; (void)cutoff;
     const int cus = ctx && ctx->n_cu > 0 ? ctx->n_cu : 256;
-    Tiling t{8, 4, 1, 8192};
-    if (n_agents >= 4 * cus) t.A = 16;
-    int G = (n_agents + t.A - 1) / t.A;
-    if (G < 1) G = 1;
-    // shard the points until the chip is covered, keeping >= 1024 points per shard
-    int S = 1;
-    while (S * 2 <= kMaxShards && G * S * 2 <= cus && n_points / (S * 2) >= 1024) S *= 2;
-    t.S = S;
-    long long per = (n_points + S - 1) / S;
-    t.tile = (int)std::min<long long>(std::max<long long>(per, 64), 8192);
-    t.tile = (t.tile + 63) / 64 * 64;
-    return t;
+    // shard count: the smallest power of two that covers the chip with an
+    // LDS-resident shard, within the co-residency a cooperative launch needs
+    auto shard = [&](Tiling t) {
+        const int per_wg = t.wg ? t.A : t.A * t.W;
+        const long long G = std::max(1, (n_agents + per_wg - 1) / per_wg);
+        int best = 1;
+        for (int S = 1; S <= kMaxShards && S * t.A <= kMaxGather; S *= 2) {
+            if (S > 1 && n_points / S < 64) break;
+            Tiling u = t;
+            u.S = S;
+            const Lay l = make_layout(u, n_points, n_seg);
+            const size_t lds = lds_plan(l, t.W, t.wg ? t.W : 1, t.A, S).total;
+            const long long per_cu = std::min<long long>(kLdsBudget / std::max<size_t>(lds, 1), 16 / t.W);
+            if (S > 1 && G * S > per_cu * cus) break;
+            best = S;
+            if (G * S >= cus && l.resident) break;
+        }
+        t.S = best;
+        return t;
+    };
+    // many agents: every wave is its own group (no barriers in the step loop);
+    // few agents: workgroup-wide groups keep the shard count, hence the exchange, small
+    if ((long long)n_agents >= (long long)cus * 4) {
+        Tiling t{1, 4, 1, 4096, 0, 0};
+        while (t.A < 8 && (long long)n_agents >= (long long)cus * t.W * t.A * 2) t.A *= 2;
+        return shard(t);
+    }
+    Tiling t{1, 8, 1, 4096, 0, 1};
+    while (t.A < 8 && (long long)n_agents > (long long)cus * t.A / 4) t.A *= 2;
+    return shard(t);
 }
 
 gmapp_status launch_rollout(gmapp_ctx *ctx, const Scn &sc, const Agt &ag, const Prm &pr, const Out &out,
                             const Probe *probe, const Tiling &t, hipStream_t stream)
 {
-    gmapp_status st = check_tiling(ctx, t, ag.n, pr.cutoff);
+    gmapp_status st = check_tiling(ctx, t, sc.n_cap, sc.n_seg, pr.cutoff);
     if (st) return st;
     const bool is_probe = probe != nullptr;
     if (ag.n == 0) {
@@ -536,29 +774,31 @@ gmapp_status launch_rollout(gmapp_ctx *ctx, const Scn &sc, const Agt &ag, const 
         GM_HIP(ctx, hipGetLastError());
         return GMAPP_OK;
     }
-    KFn fn = pick_kernel(t.A, t.W, pr.cutoff, is_probe);
-    const int G = (ag.n + t.A - 1) / t.A;
+    KFn fn = pick_kernel(t.A, t.W, t.wg != 0, pr.cutoff, is_probe);
+    const int per_wg = t.wg ? t.A : t.A * t.W;
+    const int gpw = t.wg ? 1 : t.W;
+    const int G = (ag.n + per_wg - 1) / per_wg;
     const long long nwg_real = (long long)G * t.S;
     long long nwg = nwg_real;
     if (t.S > 1) nwg = (nwg + 7) / 8 * 8;
-    if (nwg_real > kMaxWorkgroups || nwg > kMaxWorkgroups)
+    if (nwg > kMaxWorkgroups)
         return fail(ctx, GMAPP_ECAPACITY, "%lld workgroups exceed the limit %d", nwg, kMaxWorkgroups);
-    const size_t need_partial = (size_t)2 * G * t.S * t.A * sizeof(float4);
-    if (t.S > 1 && need_partial > ctx->scratch_bytes)
-        return fail(ctx, GMAPP_ENOMEM, "exchange area needs %zu bytes, workspace has %zu", need_partial,
-                    ctx->scratch_bytes);
+    const size_t need_partial = (size_t)2 * G * gpw * t.S * t.A * 4 * sizeof(unsigned long long);
+    if (t.S > 1 && need_partial > kXchgBytes)
+        return fail(ctx, GMAPP_ECAPACITY, "exchange area needs %zu bytes, the context holds %zu", need_partial,
+                    kXchgBytes);
     Xch xc;
-    xc.partial = reinterpret_cast<float4 *>(ctx->scratch);
+    xc.partial = ctx->xchg;
     xc.flags = ctx->sync;
-    xc.done = ctx->sync + kMaxWorkgroups;
-    xc.status = ctx->sync + kMaxWorkgroups + 16;
+    xc.done = ctx->sync + kCounterWords;
+    xc.status = ctx->sync + kCounterWords + 16;
     xc.S = t.S;
     xc.G = G;
     Probe pb{};
     if (probe) pb = *probe;
-    const size_t shm = lds_bytes(t);
-    int tile = t.tile;
-    void *args[] = {(void *)&sc, (void *)&ag, (void *)&pr, (void *)&out, (void *)&pb, (void *)&xc, (void *)&tile};
+    Lay lay = make_layout(t, sc.n_cap, sc.n_seg);
+    const size_t shm = lds_plan(lay, t.W, t.wg ? t.W : 1, t.A, t.S).total;
+    void *args[] = {(void *)&sc, (void *)&ag, (void *)&pr, (void *)&out, (void *)&pb, (void *)&xc, (void *)&lay};
     GM_HIP(ctx, hipFuncSetAttribute(reinterpret_cast<const void *>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
                                     (int)shm));
     if (t.S > 1) {

@@ -63,11 +63,11 @@ class Outputs(ctypes.Structure):
 
 
 class Tiling(ctypes.Structure):
-    _fields_ = [("agents_per_block", ctypes.c_int32), ("waves", ctypes.c_int32), ("shards", ctypes.c_int32),
-                ("tile_points", ctypes.c_int32)]
+    _fields_ = [("agents", ctypes.c_int32), ("waves", ctypes.c_int32), ("shards", ctypes.c_int32),
+                ("tile_points", ctypes.c_int32), ("layout", ctypes.c_int32), ("group", ctypes.c_int32)]
 
     def as_tuple(self):
-        return (self.agents_per_block, self.waves, self.shards, self.tile_points)
+        return (self.agents, self.waves, self.shards, self.tile_points, self.layout, self.group)
 
 
 _lib = None
@@ -92,6 +92,11 @@ def load_library(path: str = LIB_PATH):
         "gmapp_force_probe": (ctypes.c_int32, [vp, P(Scene), P(Agents), vp, vp, ctypes.c_float, P(Params), vp, vp,
                                                vp]),
         "gmapp_set_tiling": (ctypes.c_int32, [vp, P(Tiling)]),
+        "gmapp_depth_to_points": (ctypes.c_int32, [vp, vp, ctypes.c_int32, ctypes.c_int32, P(ctypes.c_float),
+                                                   P(ctypes.c_float), vp, vp, vp, vp]),
+        "gmapp_voxel_downsample": (ctypes.c_int32, [vp, vp, vp, vp, ctypes.c_int64, ctypes.c_float, P(ctypes.c_float),
+                                                    P(ctypes.c_int32), ctypes.c_int32, vp, vp, vp, ctypes.c_int64, vp,
+                                                    vp]),
         "gmapp_get_tiling": (ctypes.c_int32, [vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                               ctypes.c_int32, P(Tiling)]),
     }
@@ -238,8 +243,10 @@ class Context:
         return ctypes.c_void_p(s.cuda_stream)
 
     # ------------------------------------------------------------------ tiling
-    def set_tiling(self, agents_per_block=0, waves=0, shards=0, tile_points=0):
-        t = Tiling(agents_per_block, waves, shards, tile_points)
+    def set_tiling(self, agents=0, waves=0, shards=0, tile_points=0, layout=0, group=0):
+        """Force a tiling (zeros = choose): agents per group, waves per workgroup, shards,
+        streamed tile points, layout (0 auto, 1 resident, 2 streamed), group (1 wave, 2 workgroup)."""
+        t = Tiling(agents, waves, shards, tile_points, layout, group)
         self._raise(self.lib.gmapp_set_tiling(self.handle, ctypes.byref(t)))
 
     def clear_tiling(self):
@@ -291,3 +298,44 @@ class Context:
                                         float(t), ctypes.byref(prm), _ptr(f), _ptr(r), self._stream(stream))
         self._raise(st)
         return f, r
+
+    # ------------------------------------------------------------------ perception
+    def depth_to_points(self, depth, K, T_wc, out=None, stream=None):
+        """gmapp_depth_to_points: depth [h, w] (device float32) -> x, y, z [h*w] (NaN for invalid pixels)."""
+        import torch
+        if depth.dim() != 2:
+            raise ValueError("depth must be [h, w]")
+        h, w = depth.shape
+        _check_tensor(depth, "depth", h * w, torch.float32, self.device)
+        if out is None:
+            out = tuple(torch.empty(h * w, dtype=torch.float32, device=self.device) for _ in range(3))
+        for i, t in enumerate(out):
+            _check_tensor(t, f"out[{i}]", h * w, torch.float32, self.device)
+        Kc = (ctypes.c_float * 4)(*[float(v) for v in np.asarray(K, np.float32).reshape(4)])
+        Tc = (ctypes.c_float * 12)(*[float(v) for v in np.asarray(T_wc, np.float32).reshape(12)])
+        st = self.lib.gmapp_depth_to_points(self.handle, _ptr(depth), int(w), int(h), Kc, Tc, _ptr(out[0]),
+                                            _ptr(out[1]), _ptr(out[2]), self._stream(stream))
+        self._raise(st)
+        return out
+
+    def voxel_downsample(self, x, y, z, voxel, lo, dims, min_count=1, capacity=None, out=None, stream=None):
+        """gmapp_voxel_downsample: occupied voxel centres (sorted by cell) and the device count.
+
+        Returns (ox, oy, oz, n_out) with n_out an int64 [1] device tensor."""
+        import torch
+        n = int(x.numel())
+        for nm, t in (("x", x), ("y", y), ("z", z)):
+            _check_tensor(t, nm, n, torch.float32, self.device)
+        if capacity is None:
+            capacity = n
+        if out is None:
+            out = tuple(torch.empty(max(capacity, 1), dtype=torch.float32, device=self.device) for _ in range(3)) + \
+                (torch.zeros(1, dtype=torch.int64, device=self.device),)
+        loc = (ctypes.c_float * 3)(*[float(v) for v in np.asarray(lo, np.float32).reshape(3)])
+        dc = (ctypes.c_int32 * 3)(*[int(v) for v in np.asarray(dims).reshape(3)])
+        st = self.lib.gmapp_voxel_downsample(self.handle, _ptr(x), _ptr(y), _ptr(z), n, float(voxel), loc, dc,
+                                             int(min_count), _ptr(out[0]), _ptr(out[1]), _ptr(out[2]),
+                                             int(capacity), _ptr(out[3]), self._stream(stream))
+        self._raise(st)
+        return out
+

@@ -74,7 +74,7 @@ class Agents:
         return int(self.k_a.shape[0])
 
     def subset(self, idx) -> "Agents":
-        idx = np.asarray(idx)
+        idx = np.asarray(idx, dtype=np.int64)
         return Agents(*(np.ascontiguousarray(getattr(self, f.name)[idx]) for f in dataclasses.fields(self)))
 
 

@@ -20,6 +20,8 @@ def gpu_rollout(ctx, pb, device="cuda:0", tiling=None, stream=None):
     torch.cuda.synchronize()
     res = {k: (v.cpu().numpy() if v is not None else None) for k, v in out.items()}
     res["best"] = int(res["best"][0])
+    if pb.agents.n > 0:
+        assert 0 <= res["best"] < pb.agents.n, f"best = {res['best']} (negative = device error status)"
     return res
 
 

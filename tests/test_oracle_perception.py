@@ -1,0 +1,88 @@
+"""Pins of the perception oracle: projection round trip, brute-force voxel sets,
+geometric properties of voxel centres, idempotence."""
+import math
+
+import numpy as np
+
+from oracle import perception as op
+from paper_2606_12579_amd import scenes
+
+
+def test_back_projection_round_trip():
+    """Project known world points with the pinhole model, back-project their depth: same points."""
+    rng = np.random.default_rng(0)
+    fr = scenes.config3_frame(n_boxes=0, w=64, h=48)
+    K = fr.K.astype(np.float64)
+    T = fr.T_wc.astype(np.float64)
+    R, t = T[:, :3], T[:, 3]
+    # world points in front of the camera
+    Pw = np.stack([rng.uniform(-0.03, 0.03, 200), rng.uniform(-0.02, 0.02, 200), rng.uniform(0.0, 0.5, 200)], 1)
+    Pc = (Pw - t) @ R                                # R^T (p - t)
+    u = K[0] * Pc[:, 0] / Pc[:, 2] + K[2]
+    v = K[1] * Pc[:, 1] / Pc[:, 2] + K[3]
+    # an image holding exactly these depths at integer pixels: use pixel centres instead
+    ui, vi = np.round(u).astype(int), np.round(v).astype(int)
+    keep = (ui >= 0) & (ui < 64) & (vi >= 0) & (vi < 48)
+    _, first = np.unique(vi * 64 + ui, return_index=True)      # one world point per pixel
+    keep &= np.isin(np.arange(len(ui)), first)
+    assert keep.sum() > 20
+    depth = np.zeros((48, 64))
+    depth[vi[keep], ui[keep]] = Pc[keep, 2]
+    P = op.back_project(depth, fr.K, fr.T_wc).reshape(48, 64, 3)
+    # the back-projected pixel centre lies on the ray through that pixel at the given depth
+    for j in np.flatnonzero(keep):
+        p = P[vi[j], ui[j]]
+        pc = (p - t) @ R
+        assert abs(pc[2] - Pc[j, 2]) < 1e-12
+        assert abs(K[0] * pc[0] / pc[2] + K[2] - ui[j]) < 1e-9
+        assert abs(K[1] * pc[1] / pc[2] + K[3] - vi[j]) < 1e-9
+
+
+def test_back_projection_plane_and_invalid():
+    fr = scenes.config3_frame(n_boxes=0, w=32, h=24)
+    P = op.back_project(fr.depth, fr.K, fr.T_wc)
+    assert np.abs(P[:, 2]).max() < 1e-6                     # camera 1 m above the plane z = 0
+    d = fr.depth.copy()
+    d[0, 0], d[1, 1], d[2, 2] = 0.0, np.nan, -1.0
+    P = op.back_project(d, fr.K, fr.T_wc)
+    assert np.isnan(P[[0, 32 + 1, 64 + 2]]).all() and np.isfinite(P[3]).all()
+
+
+def test_voxel_bruteforce_small():
+    rng = np.random.default_rng(1)
+    s, lo, dims = 0.01, np.array([-0.05, -0.05, 0.0]), np.array([10, 10, 5])
+    P = rng.uniform([-0.06, -0.06, -0.01], [0.06, 0.06, 0.06], (500, 3)).astype(np.float32)
+    cells = op.voxel_cells(P[:, 0], P[:, 1], P[:, 2], s, lo, dims)
+    expect = set()
+    for p in P.astype(np.float64):
+        k = [math.floor(float(np.float32((np.float32(p[a]) - np.float32(lo[a])) / np.float32(s)))) for a in range(3)]
+        if all(0 <= k[a] < dims[a] for a in range(3)):
+            expect.add((k[2] * dims[1] + k[1]) * dims[0] + k[0])
+    assert list(cells) == sorted(expect)
+    # min_count keeps exactly the cells with enough points
+    k, ok = op.voxel_keys(P[:, 0], P[:, 1], P[:, 2], s, lo, dims)
+    lin = (k[ok, 2] * dims[1] + k[ok, 1]) * dims[0] + k[ok, 0]
+    for m in (2, 3):
+        c2 = op.voxel_cells(P[:, 0], P[:, 1], P[:, 2], s, lo, dims, min_count=m)
+        assert all((lin == c).sum() >= m for c in c2)
+        assert all((lin == c).sum() < m for c in set(lin) - set(c2))
+
+
+def test_voxel_centre_properties_and_idempotence():
+    fr = scenes.config3_frame()
+    P = op.back_project(fr.depth, fr.K, fr.T_wc).astype(np.float32)
+    cells = op.voxel_cells(P[:, 0], P[:, 1], P[:, 2], fr.voxel, fr.box_lo, fr.dims)
+    C = op.voxel_centres(cells, fr.voxel, fr.box_lo, fr.dims)
+    assert 0 < len(cells) <= len(P)
+    # every kept point lies in its cell: within sqrt(3) s / 2 of the centre
+    k, ok = op.voxel_keys(P[:, 0], P[:, 1], P[:, 2], fr.voxel, fr.box_lo, fr.dims)
+    d = np.asarray(fr.dims, np.int64)
+    lin = (k[ok, 2] * d[1] + k[ok, 1]) * d[0] + k[ok, 0]
+    centre = C[np.searchsorted(cells, lin)]
+    assert (np.linalg.norm(P[ok].astype(np.float64) - centre, axis=1) <= math.sqrt(3) * fr.voxel / 2 * (1 + 1e-5)).all()
+    # re-voxelising the centres gives the same cells
+    C32 = C.astype(np.float32)
+    again = op.voxel_cells(C32[:, 0], C32[:, 1], C32[:, 2], fr.voxel, fr.box_lo, fr.dims)
+    assert np.array_equal(again, cells)
+    # the scene really has boxes above the plane and the plane fills the footprint
+    assert len(cells) > 11000 and (C[:, 2] > 0.03).sum() > 500

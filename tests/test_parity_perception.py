@@ -1,0 +1,141 @@
+"""GPU parity of the perception pass (gmapp_depth_to_points, gmapp_voxel_downsample)
+against the oracle, and the rollout on the device-resident sphere world."""
+import copy
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import perception as op
+from paper_2606_12579_amd import scenes
+from tests import gpu_util as gu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_2606_12579_amd import gmapp
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = gmapp.Context(0)
+    yield c
+    c.close()
+
+
+def _gpu_points(ctx, fr):
+    import torch
+    d = torch.as_tensor(fr.depth, device="cuda")
+    x, y, z = ctx.depth_to_points(d, fr.K, fr.T_wc)
+    torch.cuda.synchronize()
+    return np.stack([x.cpu().numpy(), y.cpu().numpy(), z.cpu().numpy()], 1)
+
+
+def test_depth_to_points(ctx):
+    fr = scenes.config3_frame()
+    fr.depth[0, :7] = [0.0, -1.0, np.nan, np.inf, 1.0, 0.5, 2.0]      # invalid pixels, then valid ones
+    ref = op.back_project(fr.depth, fr.K, fr.T_wc)
+    got = _gpu_points(ctx, fr).astype(np.float64)
+    assert np.array_equal(np.isnan(got), np.isnan(ref))
+    ok = ~np.isnan(ref[:, 0])
+    err = np.abs(got[ok] - ref[ok])
+    assert (err <= 4e-7 * np.abs(ref[ok]) + 2e-7).all(), err.max()
+
+
+def test_voxel_exact_on_oracle_points(ctx):
+    """Same FP32 points on both sides: identical occupied cells, centres = FP32 rounding of the exact centres."""
+    import torch
+    fr = scenes.config3_frame()
+    P = op.back_project(fr.depth, fr.K, fr.T_wc).astype(np.float32)
+    for min_count in (1, 3):
+        cells = op.voxel_cells(P[:, 0], P[:, 1], P[:, 2], fr.voxel, fr.box_lo, fr.dims, min_count)
+        C = op.voxel_centres(cells, fr.voxel, fr.box_lo, fr.dims).astype(np.float32)
+        t = [torch.as_tensor(np.ascontiguousarray(P[:, a]), device="cuda") for a in range(3)]
+        ox, oy, oz, n = ctx.voxel_downsample(*t, fr.voxel, fr.box_lo, fr.dims, min_count=min_count)
+        torch.cuda.synchronize()
+        n = int(n.item())
+        assert n == len(cells), (n, len(cells))
+        G = np.stack([ox[:n].cpu().numpy(), oy[:n].cpu().numpy(), oz[:n].cpu().numpy()], 1)
+        assert np.array_equal(G, C)
+
+
+def test_voxel_edges(ctx):
+    import torch
+    rng = np.random.default_rng(3)
+    lo, dims, s = np.array([0.0, 0.0, 0.0], np.float32), np.array([7, 5, 3], np.int32), 0.01
+    P = rng.uniform(-0.02, 0.09, (3000, 3)).astype(np.float32)      # many outside the box
+    P[:5] = np.nan
+    cells = op.voxel_cells(P[:, 0], P[:, 1], P[:, 2], s, lo, dims)
+    t = [torch.as_tensor(np.ascontiguousarray(P[:, a]), device="cuda") for a in range(3)]
+    for cap in (len(cells), 10, 0):                                   # capacity overflow keeps the count
+        ox, oy, oz, n = ctx.voxel_downsample(*t, s, lo, dims, capacity=cap)
+        torch.cuda.synchronize()
+        assert int(n.item()) == len(cells)
+        C = op.voxel_centres(cells[:cap], s, lo, dims).astype(np.float32)
+        if cap:
+            assert np.array_equal(ox[:cap].cpu().numpy(), C[:, 0])
+    e = [torch.empty(0, device="cuda") for _ in range(3)]
+    ox, oy, oz, n = ctx.voxel_downsample(*e, s, lo, dims, capacity=4)
+    torch.cuda.synchronize()
+    assert int(n.item()) == 0
+
+
+def test_pipeline_config3(ctx):
+    """Depth image -> points -> voxel centres on the GPU against the oracle's
+    pipeline; cells may differ only where an input point lies within 1e-5 of a
+    voxel face (FP32 vs FP64 back-projection)."""
+    import torch
+    fr = scenes.config3_frame()
+    ref_P = op.back_project(fr.depth, fr.K, fr.T_wc)
+    ref_cells = op.voxel_cells(ref_P[:, 0], ref_P[:, 1], ref_P[:, 2], fr.voxel, fr.box_lo, fr.dims)
+    d = torch.as_tensor(fr.depth, device="cuda")
+    x, y, z = ctx.depth_to_points(d, fr.K, fr.T_wc)
+    ox, oy, oz, n = ctx.voxel_downsample(x, y, z, fr.voxel, fr.box_lo, fr.dims)
+    torch.cuda.synchronize()
+    nv = int(n.item())
+    G = np.stack([ox[:nv].cpu().numpy(), oy[:nv].cpu().numpy(), oz[:nv].cpu().numpy()], 1).astype(np.float64)
+    g_cells = np.round((G - fr.box_lo.astype(np.float64)) / fr.voxel - 0.5).astype(np.int64)
+    dims = fr.dims.astype(np.int64)
+    g_lin = (g_cells[:, 2] * dims[1] + g_cells[:, 1]) * dims[0] + g_cells[:, 0]
+    assert np.all(np.diff(g_lin) > 0)                                # sorted by cell, no duplicates
+    # points whose cell is ambiguous: within 1e-5 (relative to the voxel) of a face
+    q = (ref_P - fr.box_lo.astype(np.float64)) / fr.voxel
+    near = np.isfinite(q).all(1) & (np.abs(q - np.round(q)) < 1e-5).any(1)
+    k, ok = op.voxel_keys(ref_P[:, 0].astype(np.float32), ref_P[:, 1].astype(np.float32),
+                          ref_P[:, 2].astype(np.float32), fr.voxel, fr.box_lo, fr.dims)
+    lin = (k[:, 2] * dims[1] + k[:, 1]) * dims[0] + k[:, 0]
+    sure = set(lin[ok & ~near])
+    diff = set(ref_cells) ^ set(g_lin)
+    assert sure <= set(g_lin)
+    assert len(diff) <= 2 * near.sum(), (len(diff), near.sum())
+    print(f"config3 voxels: gpu {nv}, oracle {len(ref_cells)}, ambiguous points {near.sum()}", flush=True)
+
+
+def test_rollout_on_device_sphere_world(ctx):
+    """The rollout reads N_O from the voxel pass's device counter (no host sync).
+    Input: the oracle's FP32 points, voxelised on the GPU (the same cells and
+    centres as the oracle's, as the exact test shows); the oracle rolls out on its
+    own centres.  256 agents at full size; the oracle checks a spread subset."""
+    import torch
+    from paper_2606_12579_amd import gmapp
+    fr = scenes.config3_frame()
+    P = op.back_project(fr.depth, fr.K, fr.T_wc).astype(np.float32)
+    cells = op.voxel_cells(P[:, 0], P[:, 1], P[:, 2], fr.voxel, fr.box_lo, fr.dims)
+    C = op.voxel_centres(cells, fr.voxel, fr.box_lo, fr.dims).astype(np.float32)
+    t = [torch.as_tensor(np.ascontiguousarray(P[:, a]), device="cuda") for a in range(3)]
+    ox, oy, oz, n = ctx.voxel_downsample(*t, fr.voxel, fr.box_lo, fr.dims, capacity=32768)
+    agents, q, prm = scenes.config3_agents(n_agents=256, n_steps=120)
+    sc = gmapp.DeviceScene(ox, oy, oz, scenes.R_OBS, n_points_dev=n)
+    ag = gmapp.agents_to_device(agents)
+    ctx.clear_tiling()
+    out = ctx.rollout(sc, ag, q, prm)
+    torch.cuda.synchronize()
+    idx = np.arange(0, 256, 16)
+    pb = scenes.Problem(scenes.Scene(C[:, 0].copy(), C[:, 1].copy(), C[:, 2].copy(), scenes.R_OBS),
+                        agents.subset(idx), q, prm)
+    ref = oracle.rollout(pb)
+    gpu = {"traj": out["traj"].cpu().numpy()[idx], "cost": out["cost"].cpu().numpy()[idx],
+           "min_clear": out["min_clear"].cpu().numpy()[idx], "best": int(out["best"].item())}
+    err = gu.compare_rollout(pb, gpu, ref)
+    print(f"config3 rollout on {len(C)} voxel centres: pos err {err:.2e}", flush=True)

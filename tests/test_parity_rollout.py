@@ -37,11 +37,16 @@ def test_config1_rollout(ctx):
     _log(f"config1 pos err {err:.2e}")
 
 
-@pytest.mark.parametrize("tiling", [(1, 1, 1, 0), (2, 2, 1, 0), (8, 4, 1, 0), (8, 4, 1, 256), (64, 1, 1, 0),
-                                    (4, 4, 4, 0), (8, 4, 8, 128), (16, 8, 2, 0), (1, 4, 16, 0), (128, 2, 1, 0),
-                                    (256, 4, 1, 512)])
+# (agents per group, waves per workgroup, shards, streamed tile points, layout, group: 1 wave / 2 workgroup)
+TILINGS = [(1, 1, 1, 0, 0, 1), (2, 2, 1, 0, 1, 1), (8, 4, 1, 0, 0, 1), (8, 4, 1, 256, 2, 1), (64, 1, 1, 0, 1, 1),
+           (4, 4, 4, 0, 0, 1), (8, 1, 8, 128, 2, 1), (16, 8, 2, 0, 1, 1), (1, 4, 16, 0, 1, 1), (32, 2, 1, 0, 0, 1),
+           (64, 4, 1, 512, 2, 1), (2, 16, 4, 0, 1, 1), (4, 2, 2, 64, 2, 1), (1, 8, 64, 0, 0, 1),
+           (1, 4, 1, 0, 1, 2), (2, 8, 4, 0, 1, 2), (8, 16, 2, 0, 0, 2), (4, 4, 8, 128, 2, 2), (1, 16, 16, 0, 1, 2)]
+
+
+@pytest.mark.parametrize("tiling", TILINGS)
 def test_tilings_config1(ctx, tiling):
-    """Every tiling (agents per block, waves, shards, LDS tile) gives the oracle's result."""
+    """Every tiling (agents per group, waves, shards, tile size, layout, grouping) gives the oracle's result."""
     pb = scenes.config1()
     _log(f"config1 tiling {tiling}")
     gpu = gu.gpu_rollout(ctx, pb, tiling=tiling)
@@ -103,7 +108,8 @@ def test_edge_cases(ctx, case):
     elif case == "far":
         pb.scene = scenes.Scene(pb.scene.x + 5, pb.scene.y, pb.scene.z)   # nothing within r_d
     ref = oracle.rollout(pb)
-    for tiling in (None, (2, 1, 2, 64), (8, 2, 1, 64)):
+    for tiling in (None, (2, 1, 2, 0, 1, 1), (8, 2, 1, 64, 2, 1), (4, 4, 4, 0, 2, 1), (1, 2, 8, 0, 1, 1),
+                   (2, 4, 4, 0, 1, 2), (1, 8, 2, 64, 2, 2)):
         gpu = gu.gpu_rollout(ctx, pb, tiling=tiling)
         gu.compare_rollout(pb, gpu, ref)
         gu.check_selection(gpu["best"], ref.cost, gpu["cost"])
@@ -136,10 +142,11 @@ def test_n_agents_zero(ctx):
 
 def test_deterministic(ctx):
     pb = scenes.config2(n_agents=16, n_steps=50)
-    a = gu.gpu_rollout(ctx, pb, tiling=(8, 4, 4, 0))
-    b = gu.gpu_rollout(ctx, pb, tiling=(8, 4, 4, 0))
-    for k in ("traj", "cost", "min_clear"):
-        assert np.array_equal(a[k], b[k]), k
+    for t in ((1, 8, 4, 0, 0, 1), (2, 8, 4, 0, 0, 2)):
+        a = gu.gpu_rollout(ctx, pb, tiling=t)
+        b = gu.gpu_rollout(ctx, pb, tiling=t)
+        for k in ("traj", "cost", "min_clear"):
+            assert np.array_equal(a[k], b[k]), (t, k)
 
 
 def test_config2_full_size(ctx):
@@ -176,7 +183,7 @@ def test_validation_errors(ctx):
     with pytest.raises(gmapp.GmappError):
         ctx.rollout(sc, ag, q, pb.params)
     with pytest.raises(gmapp.GmappError) as ei:
-        ctx.set_tiling(3, 4, 1, 0)
+        ctx.set_tiling(3, 4, 1)
         ctx.rollout(sc, ag, pb.query, pb.params)
     assert ei.value.status == gmapp.EINVAL
     ctx.clear_tiling()

@@ -25,20 +25,54 @@ def _percentile(xs, q):
     return float(np.percentile(np.asarray(xs), q)) if xs else None
 
 
-def cpu_baseline(pb_full):
-    """The FP64 oracle on a bounded sample of the same workload (all agents, the
-    first 200 steps), timed on this host's cores."""
-    import copy
+def cpu_baseline(pb):
+    """The FP64 oracle on the same workload (all agents, all steps, all points),
+    timed on this host's cores (OpenMP over agents)."""
     import oracle
-    sub = copy.deepcopy(pb_full)
-    sub.params.n_steps = min(200, pb_full.params.n_steps)
     t0 = time.perf_counter()
-    oracle.rollout(sub)
+    oracle.rollout(pb)
     dt = time.perf_counter() - t0
-    n = oracle.interactions(sub)
+    n = oracle.interactions(pb)
     return {"value": n / dt, "unit": "interactions/s", "cores": oracle.n_threads(), "kind": "oracle",
-            "sample": f"FP64 oracle, all {sub.agents.n} agents x first {sub.params.n_steps} steps x "
-                      f"{sub.scene.n} points ({n:.3g} interactions) in {dt:.2f} s"}
+            "sample": f"FP64 oracle, the full workload: {pb.agents.n} agents x {pb.params.n_steps} steps x "
+                      f"{pb.scene.n} points ({n:.3g} interactions) in {dt:.2f} s"}
+
+
+def perception_pass(ctx, dev, reps=20):
+    """Depth image (640x480) -> points -> 1 cm voxel centres, timed with HIP events.
+    Algorithmic bytes: depth read + points written, points read + centres written."""
+    import torch
+    from paper_2606_12579_amd import scenes
+    fr = scenes.config3_frame()
+    d = torch.as_tensor(fr.depth, device=dev)
+    n = d.numel()
+    pts = tuple(torch.empty(n, dtype=torch.float32, device=dev) for _ in range(3))
+    cap = 65536
+    vox = tuple(torch.empty(cap, dtype=torch.float32, device=dev) for _ in range(3)) + \
+        (torch.zeros(1, dtype=torch.int64, device=dev),)
+    for _ in range(3):
+        ctx.depth_to_points(d, fr.K, fr.T_wc, out=pts)
+        ctx.voxel_downsample(*pts, fr.voxel, fr.box_lo, fr.dims, capacity=cap, out=vox)
+    torch.cuda.synchronize()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    t_bp, t_vx = 0.0, 0.0
+    for _ in range(reps):
+        e[0].record()
+        ctx.depth_to_points(d, fr.K, fr.T_wc, out=pts)
+        e[1].record()
+        ctx.voxel_downsample(*pts, fr.voxel, fr.box_lo, fr.dims, capacity=cap, out=vox)
+        e[2].record()
+        torch.cuda.synchronize()
+        t_bp += e[0].elapsed_time(e[1])
+        t_vx += e[1].elapsed_time(e[2])
+    nv = int(vox[3].item())
+    bp_bytes = 4 * n + 12 * n
+    vx_bytes = 12 * n + 12 * nv
+    return {"frame": "640x480 z-depth, 20 boxes on a plane, 1 cm voxels", "points": n, "voxels": nv,
+            "depth_to_points_ms": t_bp / reps, "voxel_downsample_ms": t_vx / reps,
+            "depth_to_points_GBps": bp_bytes / (t_bp / reps * 1e-3) / 1e9,
+            "voxel_downsample_GBps": vx_bytes / (t_vx / reps * 1e-3) / 1e9,
+            "bytes_note": "algorithmic: depth 4 B + points 12 B per pixel; points 12 B per point + centres 12 B"}
 
 
 def main():
@@ -48,6 +82,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--replans", type=int, default=2000, help="back-to-back replans for the latency percentiles")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU (oracle) baseline")
+    ap.add_argument("--no-perception", action="store_true", help="skip the perception-pass timing")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the rollout shards scenes and agents with no per-step traffic, "
@@ -133,6 +168,15 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32, "traffic": None},
     }
+    if not args.no_perception:
+        res["perception"] = perception_pass(ctx, dev)
+    # a plain device copy of known size: reference for the HBM byte counters of a profiled run
+    ref = torch.empty(64 << 20, dtype=torch.float32, device=dev)
+    ref2 = torch.empty_like(ref)
+    ref2.copy_(ref)
+    torch.cuda.synchronize()
+    res["copy_reference_bytes"] = 2 * ref.numel() * 4
+    del ref, ref2
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(pb)
     ctx.close()

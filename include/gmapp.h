@@ -158,6 +158,22 @@ gmapp_status gmapp_set_tiling(gmapp_ctx *ctx, const gmapp_tiling *tiling);
 gmapp_status gmapp_get_tiling(gmapp_ctx *ctx, int64_t n_points, int32_t n_agents, int32_t n_steps, int32_t n_seg,
                               int32_t cutoff, gmapp_tiling *out);
 
+/* Adjoint rollout: gradients of sum_i grad_total[i] C_i, with C_i agent i's total
+ * cost (Eq. 16) after the rollout of gmapp_rollout, with respect to each agent's
+ * k_a, d_a, k_f (Eqs. 2, 7) and rotation vector omega (Eq. 3).  One launch runs
+ * the forward rollout storing the agent state every ckpt_every steps, then, for
+ * each segment from last to first, recomputes the segment and sweeps it
+ * backwards (reverse mode, FP32).  The hard cut-off (cutoff 0) is differentiated
+ * almost everywhere; use the C1 taper (cutoff 1) for gradients that match finite
+ * differences.  grad_total: device [N_a]; g_k_a, g_d_a, g_k_f: device [N_a];
+ * g_omega: device [N_a][3].  Checkpoints and per-step records live in LDS:
+ * (N_k / ckpt_every) checkpoints of 80 bytes and ckpt_every records of 48 bytes
+ * per agent of a workgroup; ECAPACITY if they do not fit. */
+gmapp_status gmapp_rollout_backward(gmapp_ctx *ctx, const gmapp_scene *scene, const gmapp_agents *agents,
+                                    const gmapp_query *query, const gmapp_params *params, const float *grad_total,
+                                    int32_t ckpt_every, float *g_k_a, float *g_d_a, float *g_k_f, float *g_omega,
+                                    void *stream);
+
 /* Back-projection of a z-depth image into world points (Sec. IV-B / V-A: the
  * perception pipeline's coordinate transform).  Pixel (u, v) = column, row with
  * depth z = depth[v * w + u] (metres) maps to the camera point

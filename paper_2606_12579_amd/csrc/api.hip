@@ -286,4 +286,28 @@ gmapp_status gmapp_voxel_downsample(gmapp_ctx *ctx, const float *x, const float 
                                        reinterpret_cast<long long *>(n_out_dev), static_cast<hipStream_t>(stream));
 }
 
+gmapp_status gmapp_rollout_backward(gmapp_ctx *ctx, const gmapp_scene *scene, const gmapp_agents *agents,
+                                    const gmapp_query *query, const gmapp_params *params, const float *grad_total,
+                                    int32_t ckpt_every, float *g_k_a, float *g_d_a, float *g_k_f, float *g_omega,
+                                    void *stream)
+{
+    gmapp_status st = check_ctx(ctx);
+    if (st) return st;
+    if ((st = check_scene(ctx, scene)) || (st = check_agents(ctx, agents)) || (st = check_params(ctx, params, true)))
+        return st;
+    if (!query) return fail(ctx, GMAPP_EINVAL, "query is NULL");
+    for (int a = 0; a < 3; ++a)
+        if (!finite(query->p0[a]) || !finite(query->v0[a]) || !finite(query->goal[a]))
+            return fail(ctx, GMAPP_EINVAL, "query start/velocity/goal must be finite");
+    if (!finite(query->t0)) return fail(ctx, GMAPP_EINVAL, "query t0 must be finite");
+    if (ckpt_every < 1 || ckpt_every > 1024) return fail(ctx, GMAPP_EINVAL, "ckpt_every must be in [1, 1024]");
+    if (scene->n_seg > gm::kMaxSegments)
+        return fail(ctx, GMAPP_ECAPACITY, "at most %d segments are supported", gm::kMaxSegments);
+    if (agents->n_agents > 0 && (!grad_total || !g_k_a || !g_d_a || !g_k_f || !g_omega))
+        return fail(ctx, GMAPP_EINVAL, "grad_total and the gradient outputs must be non-NULL");
+    return gm::launch_adjoint(ctx, dev_scene(scene), dev_agents(agents), dev_params(params, query), grad_total,
+                              ckpt_every, g_k_a, g_d_a, g_k_f, g_omega, static_cast<hipStream_t>(stream));
+}
+
 }  // extern "C"
+

@@ -136,6 +136,10 @@ gmapp_status launch_rollout(gmapp_ctx *ctx, const Scn &sc, const Agt &ag, const 
                             const Probe *probe, const Tiling &t, hipStream_t stream);
 Tiling choose_tiling(const gmapp_ctx *ctx, long long n_points, int n_agents, int n_steps, int n_seg, int cutoff);
 
+// adjoint (adjoint.hip)
+gmapp_status launch_adjoint(gmapp_ctx *ctx, const Scn &sc, const Agt &ag, const Prm &pr, const float *grad_total,
+                            int ckpt_every, float *g_ka, float *g_da, float *g_kf, float *g_om, hipStream_t stream);
+
 // perception (perception.hip)
 gmapp_status launch_depth_to_points(gmapp_ctx *ctx, const float *depth, int w, int h, const float K[4],
                                     const Mat34 &T, float *x, float *y, float *z, hipStream_t stream);

@@ -5,7 +5,7 @@
 //
 // The voxel pass is bandwidth/latency bound.  It works on a dense count grid
 // over the caller's workspace box (which is also the bounding-box filter):
-//   1. clear the grid,  2. one atomic increment per point,
+//   1. clear the grid,  2. mark each point's cell (atomic increments when min_count > 1),
 //   3. per 1024-cell block: count the cells holding >= min_count points,
 //   4. exclusive scan of the block counts (one workgroup),
 //   5. per block: local scan and write the occupied cells' centres.
@@ -61,12 +61,18 @@ __device__ __forceinline__ long long cell_of(float px, float py, float pz, const
     return ((long long)fz * g.dims[1] + (long long)fy) * g.dims[0] + (long long)fx;
 }
 
+// occupancy (min_count 1: a plain store of 1, racing writers store the same value)
+// or counts (atomic increments)
+template <bool COUNT>
 __global__ void k_count(const float *__restrict__ x, const float *__restrict__ y, const float *__restrict__ z,
                         long long n, VoxGrid g, unsigned *__restrict__ grid)
 {
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
         const long long c = cell_of(x[i], y[i], z[i], g);
-        if (c >= 0) atomicAdd(&grid[c], 1u);
+        if (c >= 0) {
+            if constexpr (COUNT) atomicAdd(&grid[c], 1u);
+            else grid[c] = 1u;
+        }
     }
 }
 
@@ -205,7 +211,8 @@ gmapp_status launch_voxel_downsample(gmapp_ctx *ctx, const float *x, const float
     hipLaunchKernelGGL(k_zero_u32, dim3(zb), dim3(256), 0, stream, grid, cells);
     if (n > 0) {
         const int pb = (int)std::min<long long>((n + 255) / 256, 8192);
-        hipLaunchKernelGGL(k_count, dim3(pb), dim3(256), 0, stream, x, y, z, n, g, grid);
+        if (min_count > 1) hipLaunchKernelGGL(k_count<true>, dim3(pb), dim3(256), 0, stream, x, y, z, n, g, grid);
+        else hipLaunchKernelGGL(k_count<false>, dim3(pb), dim3(256), 0, stream, x, y, z, n, g, grid);
     }
     hipLaunchKernelGGL(k_block_counts, dim3((unsigned)nb), dim3(256), 0, stream, grid, cells, min_count, bsum);
     hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, stream, bsum, nb, n_out_dev);

@@ -38,141 +38,14 @@
 // The last workgroup to finish applies the selection rule and clears the
 // exchange area for the next launch.
 #include "gmapp_internal.h"
+#include "pairs.h"
 
 #include <algorithm>
 #include <cmath>
-#include <type_traits>
 
 namespace gm {
 
-namespace {
-
-constexpr float kTiny = 1e-30f;                 // keeps |d|^2 > 0 (agent on a sphere centre)
-constexpr float kFar = 1e18f;                   // padding point: beyond any cut-off, never the minimum
-constexpr unsigned long long kWatchdogTicks = 400000000ull;  // 4 s of the 100 MHz real-time clock
-
-__device__ __forceinline__ void kahan_add(float &s, float &c, float x)
-{
-    float y = x - c;
-    float t = s + y;
-    c = (t - s) - y;
-    s = t;
-}
-
-// One agent-sphere interaction (factored Eq. 2), accumulated into G, S, min r2.
-template <int CUT>
-__device__ __forceinline__ void interact(float qx, float qy, float qz, float psx, float psy, float psz, float wx,
-                                         float wy, float wz, float R, float eps, float rd, float tb_a, float tb_b,
-                                         float &G, float &Sx, float &Sy, float &Sz, float &m2)
-{
-    float dx = psx - qx, dy = psy - qy, dz = psz - qz;
-    float r2 = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, kTiny)));
-    float ri = __builtin_amdgcn_rsqf(r2);
-    float rho = fmaxf(fmaf(r2, ri, -R), eps);
-    float h = __builtin_amdgcn_rcpf(rho * r2);          // 1 / (rho |d|^2)
-    if constexpr (CUT == 0) {
-        h = (rho <= rd) ? h : 0.0f;
-    } else {                                            // C1 smoothstep taper
-        float s = __builtin_amdgcn_fmed3f(fmaf(-rho, tb_a, tb_b), 0.0f, 1.0f);
-        h *= (s * s) * fmaf(-2.0f, s, 3.0f);
-    }
-    G = fmaf(h, r2, G);
-    float dw = fmaf(dz, wz, fmaf(dy, wy, dx * wx));
-    float sc = h * dw;
-    Sx = fmaf(sc, dx, Sx);
-    Sy = fmaf(sc, dy, Sy);
-    Sz = fmaf(sc, dz, Sz);
-    m2 = fminf(m2, r2);
-}
-
-// Points [b, e) of the LDS copy, slice `sl` of L (round-robin).
-template <int L, int CUT>
-__device__ __forceinline__ void interact_run(const float *__restrict__ lx, const float *__restrict__ ly,
-                                             const float *__restrict__ lz, int b, int e, int sl, float psx,
-                                             float psy, float psz, float wx, float wy, float wz, float R,
-                                             float eps, float rd, float tb_a, float tb_b, float &G, float &Sx,
-                                             float &Sy, float &Sz, float &m2)
-{
-    const int n = e - b;
-    const int full = n / L;
-    int j = b + sl;
-#pragma unroll 4
-    for (int i = 0; i < full; ++i, j += L)
-        interact<CUT>(lx[j], ly[j], lz[j], psx, psy, psz, wx, wy, wz, R, eps, rd, tb_a, tb_b, G, Sx, Sy, Sz, m2);
-    if (sl < n - full * L)
-        interact<CUT>(lx[j], ly[j], lz[j], psx, psy, psz, wx, wy, wz, R, eps, rd, tb_a, tb_b, G, Sx, Sy, Sz, m2);
-}
-
-__device__ __forceinline__ unsigned ld_agent(const unsigned *p)
-{
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void st_agent(unsigned *p, unsigned v)
-{
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ void st64_agent(unsigned long long *p, unsigned long long v)
-{
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ unsigned long long ld64_agent(const unsigned long long *p)
-{
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-// exchange word: float bits | step tag << 32
-__device__ __forceinline__ unsigned long long xword(float v, unsigned tag)
-{
-    return (unsigned long long)__float_as_uint(v) | ((unsigned long long)tag << 32);
-}
-__device__ __forceinline__ float xval(unsigned long long q) { return __uint_as_float((unsigned)q); }
-__device__ __forceinline__ unsigned xtag(unsigned long long q) { return (unsigned)(q >> 32); }
-
-// Sum / min over the lanes of one agent (lanes congruent mod AW) of a wavefront,
-// leaving the identical result in every such lane: rotations by 8, 4, 2, 1 inside
-// 16-lane rows (DPP), then the xor-16 swizzle and the 32-lane swap.  Each stage
-// adds a partner whose own partner holds an equal value, so commutativity makes
-// every lane's result bit-identical.
-template <int AW, bool MIN>
-__device__ __forceinline__ float agent_allreduce(float x)
-{
-    auto op = [](float a, float b) { return MIN ? fminf(a, b) : a + b; };
-    auto dpp = [](float v, auto ctrl) {
-        return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), decltype(ctrl)::value, 0xF, 0xF, false));
-    };
-    if constexpr (AW <= 8) x = op(x, dpp(x, std::integral_constant<int, 0x128>{}));   // row_ror:8
-    if constexpr (AW <= 4) x = op(x, dpp(x, std::integral_constant<int, 0x124>{}));   // row_ror:4
-    if constexpr (AW <= 2) x = op(x, dpp(x, std::integral_constant<int, 0x122>{}));   // row_ror:2
-    if constexpr (AW <= 1) x = op(x, dpp(x, std::integral_constant<int, 0x121>{}));   // row_ror:1
-    if constexpr (AW <= 16) x = op(x, __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(x), 0x401F)));
-    if constexpr (AW <= 32) {
-        auto sw = __builtin_amdgcn_permlane32_swap(__float_as_int(x), __float_as_int(x), false, false);
-        x = op(__int_as_float(sw[0]), __int_as_float(sw[1]));
-    }
-    return x;
-}
-
-// k_f |w| P_w (omega G - S) added to F (w = relative velocity, uniform over the segment)
-__device__ __forceinline__ void project_add(float ux, float uy, float uz, float kf, float wx, float wy, float wz,
-                                            float G, float Sx, float Sy, float Sz, float &Fx, float &Fy, float &Fz)
-{
-    const float w2 = fmaf(uz, uz, fmaf(uy, uy, ux * ux));
-    if (w2 > 0.0f) {
-        const float cx = fmaf(wx, G, -Sx), cy = fmaf(wy, G, -Sy), cz = fmaf(wz, G, -Sz);
-        const float ri = __builtin_amdgcn_rsqf(w2);
-        const float wc = fmaf(uz, cz, fmaf(uy, cy, ux * cx)) * (ri * ri);
-        const float f = kf * (w2 * ri);
-        Fx = fmaf(f, fmaf(-ux, wc, cx), Fx);
-        Fy = fmaf(f, fmaf(-uy, wc, cy), Fy);
-        Fz = fmaf(f, fmaf(-uz, wc, cz), Fz);
-    }
-}
-
-struct Agent {
-    float ka, da, kf, rd, R, wx, wy, wz, tb_a, tb_b;
-};
-
-}  // namespace
+using namespace dev;
 
 // Launch-time layout of the shard in LDS.
 struct Lay {
@@ -271,89 +144,11 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
     const long long sb = n_pts * s / S, se = n_pts * (s + 1) / S;
     const long long n_shard = se - sb;
 
-    // segment runs of this shard: [begin, end) relative to sb and the run's
-    // velocity (0 for static points).  A table that is not non-decreasing still
-    // yields runs covering the shard exactly once.
+    // segment runs of this shard, and the split of every agent's slices over them
     if (tid == 0) {
-        int nr = 0;
-        if (sc.n_seg == 0) {
-            if (n_shard > 0) {
-                runs[0] = make_int4(0, (int)n_shard, 0, 0);
-                rvel[0] = make_float4(0.f, 0.f, 0.f, 0.f);
-                nr = 1;
-            }
-        } else {
-            auto clampi = [&](long long v) { return min(max(v, 0ll), n_pts); };
-            int lo = 0, hi = sc.n_seg;             // first segment whose end > sb
-            while (lo < hi) {
-                int mid = (lo + hi) >> 1;
-                if (clampi(sc.seg_begin[mid + 1]) > sb) hi = mid; else lo = mid + 1;
-            }
-            int si = lo;
-            long long c = sb;
-            while (c < se && nr < lay.runs_cap - 1) {
-                long long re;
-                float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (si < sc.n_seg) {
-                    long long b_s = clampi(sc.seg_begin[si]), e_s = clampi(sc.seg_begin[si + 1]);
-                    if (b_s <= c) {
-                        re = min(e_s, se);
-                        v = make_float4(sc.seg_vel[3 * si], sc.seg_vel[3 * si + 1], sc.seg_vel[3 * si + 2], 0.f);
-                    } else {
-                        re = min(b_s, se);
-                    }
-                } else {
-                    re = se;
-                }
-                if (re <= c) re = se;
-                runs[nr] = make_int4((int)(c - sb), (int)(re - sb), 0, 0);
-                rvel[nr] = v;
-                ++nr;
-                c = re;
-                while (si < sc.n_seg && clampi(sc.seg_begin[si + 1]) <= c) ++si;
-            }
-            if (c < se) {                           // out of slots (malformed table): rest static
-                runs[nr] = make_int4((int)(c - sb), (int)n_shard, 0, 0);
-                rvel[nr] = make_float4(0.f, 0.f, 0.f, 0.f);
-                ++nr;
-            }
-        }
-        // split the L slices of every agent over the runs in proportion to their
-        // length (at least one slice each), so that each lane walks one run only
-        int split = (nr > 0 && nr <= L) ? 1 : 0;
-        if (split) {
-            int used = 0;
-            for (int r = 0; r < nr; ++r) {
-                const long long len = runs[r].y - runs[r].x;
-                runs[r].w = max(1, (int)(len * L / max(n_shard, 1ll)));
-                used += runs[r].w;
-            }
-            while (used > L) {                      // give back slices where they cost least
-                int best = -1;
-                for (int r = 0; r < nr; ++r)
-                    if (runs[r].w > 1 && (best < 0 || (long long)(runs[r].y - runs[r].x) * runs[best].w <
-                                                       (long long)(runs[best].y - runs[best].x) * runs[r].w))
-                        best = r;
-                --runs[best].w;
-                --used;
-            }
-            while (used < L) {                      // add slices where the points per slice are highest
-                int best = 0;
-                for (int r = 1; r < nr; ++r)
-                    if ((long long)(runs[r].y - runs[r].x) * runs[best].w >
-                        (long long)(runs[best].y - runs[best].x) * runs[r].w)
-                        best = r;
-                ++runs[best].w;
-                ++used;
-            }
-            int first = 0;
-            for (int r = 0; r < nr; ++r) {
-                runs[r].z = first;
-                first += runs[r].w;
-            }
-        }
+        int split = 0;
+        s_nruns = build_runs(sc, n_pts, sb, se, runs, rvel, lay.runs_cap, L, split);
         s_split = split;
-        s_nruns = nr;
     }
     const bool resident = lay.resident && n_shard <= (long long)lay.cap;
     if (resident)
@@ -366,15 +161,7 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
     const bool split = resident && s_split;
     int my_j0 = 0, my_n = 0, my_stride = 1;
     float4 my_v = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (split) {
-        int r = 0;
-        while (r + 1 < n_runs && runs[r + 1].z <= slice) ++r;
-        const int4 rr = runs[r];
-        my_j0 = rr.x + (slice - rr.z);
-        my_stride = rr.w;
-        my_n = (rr.y > my_j0) ? (rr.y - my_j0 + rr.w - 1) / rr.w : 0;
-        my_v = rvel[r];
-    }
+    if (split) lane_run(runs, rvel, n_runs, slice, my_j0, my_n, my_stride, my_v);
 
     // agent state
     float px, py, pz, vx, vy, vz, t_fixed = 0.0f;

@@ -92,6 +92,8 @@ def load_library(path: str = LIB_PATH):
         "gmapp_force_probe": (ctypes.c_int32, [vp, P(Scene), P(Agents), vp, vp, ctypes.c_float, P(Params), vp, vp,
                                                vp]),
         "gmapp_set_tiling": (ctypes.c_int32, [vp, P(Tiling)]),
+        "gmapp_rollout_backward": (ctypes.c_int32, [vp, P(Scene), P(Agents), P(Query), P(Params), vp, ctypes.c_int32,
+                                                    vp, vp, vp, vp, vp]),
         "gmapp_depth_to_points": (ctypes.c_int32, [vp, vp, ctypes.c_int32, ctypes.c_int32, P(ctypes.c_float),
                                                    P(ctypes.c_float), vp, vp, vp, vp]),
         "gmapp_voxel_downsample": (ctypes.c_int32, [vp, vp, vp, vp, ctypes.c_int64, ctypes.c_float, P(ctypes.c_float),
@@ -299,6 +301,22 @@ class Context:
         self._raise(st)
         return f, r
 
+    def rollout_backward(self, scene: DeviceScene, agents: DeviceAgents, query, params, grad_total, ckpt_every=50,
+                         stream=None):
+        """gmapp_rollout_backward: d(sum_i grad_total[i] C_i) / d(k_a, d_a, k_f, omega) per agent."""
+        import torch
+        na, dev = agents.n, self.device
+        _check_tensor(grad_total, "grad_total", na, torch.float32, dev)
+        g = {k: torch.empty(na, dtype=torch.float32, device=dev) for k in ("k_a", "d_a", "k_f")}
+        g["omega"] = torch.empty((na, 3), dtype=torch.float32, device=dev)
+        sc, ag = _scene_struct(scene, dev), _agents_struct(agents, dev)
+        q, p = make_query(query), make_params(params)
+        st = self.lib.gmapp_rollout_backward(self.handle, ctypes.byref(sc), ctypes.byref(ag), ctypes.byref(q),
+                                             ctypes.byref(p), _ptr(grad_total), int(ckpt_every), _ptr(g["k_a"]),
+                                             _ptr(g["d_a"]), _ptr(g["k_f"]), _ptr(g["omega"]), self._stream(stream))
+        self._raise(st)
+        return g
+
     # ------------------------------------------------------------------ perception
     def depth_to_points(self, depth, K, T_wc, out=None, stream=None):
         """gmapp_depth_to_points: depth [h, w] (device float32) -> x, y, z [h*w] (NaN for invalid pixels)."""
@@ -339,3 +357,47 @@ class Context:
         self._raise(st)
         return out
 
+
+
+class _RolloutCost:
+    """torch.autograd.Function: total costs C_i of the rollout as a differentiable
+    function of the per-agent k_a, d_a, k_f and omega (forward: gmapp_rollout;
+    backward: gmapp_rollout_backward with state checkpoints every `ckpt_every` steps)."""
+
+    _fn = None
+
+    @classmethod
+    def get(cls):
+        if cls._fn is None:
+            import torch
+
+            class Fn(torch.autograd.Function):
+                @staticmethod
+                def forward(fctx, gctx, scene, r_d, r_a, query, params, ckpt_every, k_a, d_a, k_f, omega):
+                    agents = DeviceAgents(k_a.detach().contiguous(), d_a.detach().contiguous(),
+                                          k_f.detach().contiguous(), r_d, r_a, omega.detach().contiguous())
+                    out = gctx.rollout(scene, agents, query, params, traj=False, min_clear=False)
+                    fctx.save_for_backward(k_a, d_a, k_f, omega)
+                    fctx.meta = (gctx, scene, r_d, r_a, query, params, ckpt_every)
+                    fctx.mark_non_differentiable(out["best"])
+                    return out["cost"][:, 4].clone(), out["best"]
+
+                @staticmethod
+                def backward(fctx, g_total, g_best):
+                    k_a, d_a, k_f, omega = fctx.saved_tensors
+                    gctx, scene, r_d, r_a, query, params, ckpt_every = fctx.meta
+                    agents = DeviceAgents(k_a.detach().contiguous(), d_a.detach().contiguous(),
+                                          k_f.detach().contiguous(), r_d, r_a, omega.detach().contiguous())
+                    g = gctx.rollout_backward(scene, agents, query, params, g_total.contiguous().float(), ckpt_every)
+                    return (None, None, None, None, None, None, None, g["k_a"], g["d_a"], g["k_f"], g["omega"])
+
+            cls._fn = Fn
+        return cls._fn
+
+
+def rollout_cost(gctx: Context, scene: DeviceScene, agents: DeviceAgents, query, params, ckpt_every=50):
+    """Differentiable total costs [N_a] (and the selected agent) with respect to
+    agents.k_a, agents.d_a, agents.k_f and agents.omega (tensors that may require grad)."""
+    Fn = _RolloutCost.get()
+    return Fn.apply(gctx, scene, agents.r_d, agents.r_a, query, params, int(ckpt_every), agents.k_a, agents.d_a,
+                    agents.k_f, agents.omega)

@@ -158,6 +158,86 @@ gmapp_status gmapp_set_tiling(gmapp_ctx *ctx, const gmapp_tiling *tiling);
 gmapp_status gmapp_get_tiling(gmapp_ctx *ctx, int64_t n_points, int32_t n_agents, int32_t n_steps, int32_t n_seg,
                               int32_t cutoff, gmapp_tiling *out);
 
+/* ------------------------------------------------------------------------
+ * Many planning problems per launch.  Each job is one planning cycle of its own
+ * scene, agents, query and parameters (the rollout, costs and selection rule of
+ * gmapp_rollout), optionally restricted to the step range [k_begin, k_end) so
+ * that a long horizon can be advanced a quantum of steps per launch: the agents'
+ * integration state (position, velocity and their compensation terms, the last
+ * two net forces, the running cost sums) is kept in `state` between launches.
+ * Costs, min_clear and the selection are written when a launch reaches the end
+ * of the horizon (k_end = N_k + 1); trajectory rows k_begin..k_end-1 (and row 0
+ * when k_begin = 1) are written by every launch.  Results do not depend on the
+ * other jobs of the launch, on the step ranges or on the tuning, except through
+ * FP32 summation order (tuning changes which lanes sum which points).
+ */
+#define GMAPP_STATE_FLOATS 28
+#define GMAPP_BATCH_MAX_JOBS 16384
+#define GMAPP_BATCH_MAX_SEGMENTS 64 /* moving segments per scene in a batched launch */
+
+typedef struct {
+    gmapp_scene scene;
+    gmapp_agents agents;
+    gmapp_query query;
+    gmapp_params params;
+    gmapp_outputs out;
+    float *state;    /* device [N_a][GMAPP_STATE_FLOATS]; required unless k_begin = 1 and k_end = N_k + 1 */
+    int32_t k_begin; /* first step of this launch, 1 <= k_begin <= N_k */
+    int32_t k_end;   /* one past the last step, k_begin < k_end <= N_k + 1 */
+} gmapp_job;
+
+/* Tuning of the batched kernel.  Zero fields mean "choose" (the autotuned values
+ * when gmapp_autotune_batch has run on this context, else built-in defaults).
+ *   tile_points: points per LDS tile; worlds of at most this many points stay
+ *                resident in LDS for a whole item (64 .. 12288);
+ *   wg_per_cu:   persistent workgroups per CU (1..4, capped by what fits);
+ *   balance:     an item may take at most 1/balance of the launch's balanced
+ *                per-workgroup share of work (1..64);
+ *   item_shape:  1..4: every wave runs 1, 2, 4 or 8 agents (8 waves per item);
+ *                5..8: the workgroup's 512 lanes run 1, 2, 4 or 8 agents. */
+typedef struct {
+    int32_t tile_points, wg_per_cu, balance, item_shape;
+} gmapp_batch_tuning;
+
+/* One persistent launch over n_jobs jobs (1..GMAPP_BATCH_MAX_JOBS, at most
+ * GMAPP_BATCH_MAX_SEGMENTS segments per scene).  Workgroups pull (job, agent
+ * block) items from a device queue, longest items first.  The job table is staged
+ * through pinned host memory owned by the context. */
+gmapp_status gmapp_rollout_batch(gmapp_ctx *ctx, const gmapp_job *jobs, int32_t n_jobs, void *stream);
+/* Force a batch tuning on this context (NULL restores the automatic choice). */
+gmapp_status gmapp_set_batch_tuning(gmapp_ctx *ctx, const gmapp_batch_tuning *t);
+/* The tuning batched launches on this context use (zero item_shape = per job). */
+gmapp_status gmapp_get_batch_tuning(gmapp_ctx *ctx, gmapp_batch_tuning *out);
+
+/* A control cycle as an instantiated HIP graph: a copy of the job table from
+ * pinned host memory, then the batched kernel; each launch replays it.  The
+ * batch owns its pinned and device tables (max_jobs entries) and fixes the
+ * kernel tuning at creation.  gmapp_batch_set_jobs waits for the previous replay
+ * to finish reading the pinned table, plans the items and updates the copy node;
+ * gmapp_batch_launch enqueues one replay on `stream`.  A batch belongs to one
+ * context and shares its workspace (calls ordered on one stream). */
+typedef struct gmapp_batch gmapp_batch;
+gmapp_status gmapp_batch_create(gmapp_ctx *ctx, int32_t max_jobs, gmapp_batch **out);
+gmapp_status gmapp_batch_set_jobs(gmapp_batch *b, const gmapp_job *jobs, int32_t n_jobs);
+gmapp_status gmapp_batch_launch(gmapp_batch *b, void *stream);
+void gmapp_batch_destroy(gmapp_batch *b);
+
+/* Autotuner.  gmapp_autotune_rollout times the valid tilings of gmapp_rollout on
+ * a proxy of the problem (its first min(proxy_steps, N_k) steps, outputs into the
+ * context workspace) and caches the fastest for the problem's shape class
+ * (N_O rounded up to a power of two, N_a, N_k rounded up to a power of two,
+ * static or moving, cut-off mode); later rollouts of that class use it unless a
+ * tiling is forced.  gmapp_autotune_batch times tile size, workgroups per CU and
+ * balance for the given jobs, each shortened in proportion to its step count
+ * (the longest to proxy_steps), and keeps the fastest for later batched launches
+ * and batches created afterwards.  best / best_ms (host, may be NULL) receive the
+ * choice and its proxy time.  Both synchronise the stream. */
+gmapp_status gmapp_autotune_rollout(gmapp_ctx *ctx, const gmapp_scene *scene, const gmapp_agents *agents,
+                                    const gmapp_query *query, const gmapp_params *params, int32_t proxy_steps,
+                                    gmapp_tiling *best, float *best_ms, void *stream);
+gmapp_status gmapp_autotune_batch(gmapp_ctx *ctx, const gmapp_job *jobs, int32_t n_jobs, int32_t proxy_steps,
+                                  gmapp_batch_tuning *best, float *best_ms, void *stream);
+
 /* Adjoint rollout: gradients of sum_i grad_total[i] C_i, with C_i agent i's total
  * cost (Eq. 16) after the rollout of gmapp_rollout, with respect to each agent's
  * k_a, d_a, k_f (Eqs. 2, 7) and rotation vector omega (Eq. 3).  One launch runs

@@ -18,6 +18,10 @@ __global__ void k_fill_u32(unsigned *p, size_t n, unsigned v)
 
 bool finite(float x) { return std::isfinite(x); }
 
+}  // namespace
+
+namespace gm {
+
 gmapp_status check_ctx(gmapp_ctx *ctx)
 {
     if (!ctx) return GMAPP_EINVAL;
@@ -69,6 +73,16 @@ gmapp_status check_params(gmapp_ctx *ctx, const gmapp_params *p, bool need_steps
     return GMAPP_OK;
 }
 
+gmapp_status check_query(gmapp_ctx *ctx, const gmapp_query *query)
+{
+    if (!query) return fail(ctx, GMAPP_EINVAL, "query is NULL");
+    for (int a = 0; a < 3; ++a)
+        if (!finite(query->p0[a]) || !finite(query->v0[a]) || !finite(query->goal[a]))
+            return fail(ctx, GMAPP_EINVAL, "query start/velocity/goal must be finite");
+    if (!finite(query->t0)) return fail(ctx, GMAPP_EINVAL, "query t0 must be finite");
+    return GMAPP_OK;
+}
+
 gm::Scn dev_scene(const gmapp_scene *sc)
 {
     gm::Scn s;
@@ -104,11 +118,24 @@ gm::Prm dev_params(const gmapp_params *p, const gmapp_query *q)
     return r;
 }
 
+}  // namespace gm
+
+using namespace gm;
+
+namespace {
+
 gm::Tiling tiling_for(gmapp_ctx *ctx, long long n_points, int n_agents, int n_steps, int n_seg, int cutoff)
 {
     gm::Tiling t = gm::choose_tiling(ctx, n_points, n_agents, n_steps, n_seg, cutoff);
+    const gmapp_tiling *use = nullptr;
     if (ctx->forced) {
-        const gmapp_tiling &f = ctx->forced_tiling;
+        use = &ctx->forced_tiling;
+    } else {
+        auto it = ctx->tuned.find(gm::tune_key(n_points, n_agents, n_steps, n_seg, cutoff));
+        if (it != ctx->tuned.end()) use = &it->second;
+    }
+    if (use) {
+        const gmapp_tiling &f = *use;
         if (f.group > 0) t.wg = f.group == 2 ? 1 : 0;
         if (f.agents > 0) t.A = f.agents;
         if (f.waves > 0) t.W = f.waves;
@@ -168,6 +195,8 @@ void gmapp_destroy(gmapp_ctx *ctx)
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
     if (ctx->arena) (void)hipFree(ctx->arena);
+    if (ctx->tab_host) (void)hipHostFree(ctx->tab_host);
+    if (ctx->tab_copied) (void)hipEventDestroy(ctx->tab_copied);
     delete ctx;
 }
 
@@ -206,11 +235,7 @@ gmapp_status gmapp_rollout(gmapp_ctx *ctx, const gmapp_scene *scene, const gmapp
     if (st) return st;
     if ((st = check_scene(ctx, scene)) || (st = check_agents(ctx, agents)) || (st = check_params(ctx, params, true)))
         return st;
-    if (!query) return fail(ctx, GMAPP_EINVAL, "query is NULL");
-    for (int a = 0; a < 3; ++a)
-        if (!finite(query->p0[a]) || !finite(query->v0[a]) || !finite(query->goal[a]))
-            return fail(ctx, GMAPP_EINVAL, "query start/velocity/goal must be finite");
-    if (!finite(query->t0)) return fail(ctx, GMAPP_EINVAL, "query t0 must be finite");
+    if ((st = check_query(ctx, query))) return st;
     if (!out || !out->best) return fail(ctx, GMAPP_EINVAL, "outputs.best is NULL");
     if (agents->n_agents > 0 && !out->cost) return fail(ctx, GMAPP_EINVAL, "outputs.cost is NULL");
     gm::Tiling t = tiling_for(ctx, scene->n_points, agents->n_agents, params->n_steps, scene->n_seg, params->cutoff);
@@ -295,11 +320,7 @@ gmapp_status gmapp_rollout_backward(gmapp_ctx *ctx, const gmapp_scene *scene, co
     if (st) return st;
     if ((st = check_scene(ctx, scene)) || (st = check_agents(ctx, agents)) || (st = check_params(ctx, params, true)))
         return st;
-    if (!query) return fail(ctx, GMAPP_EINVAL, "query is NULL");
-    for (int a = 0; a < 3; ++a)
-        if (!finite(query->p0[a]) || !finite(query->v0[a]) || !finite(query->goal[a]))
-            return fail(ctx, GMAPP_EINVAL, "query start/velocity/goal must be finite");
-    if (!finite(query->t0)) return fail(ctx, GMAPP_EINVAL, "query t0 must be finite");
+    if ((st = check_query(ctx, query))) return st;
     if (ckpt_every < 1 || ckpt_every > 1024) return fail(ctx, GMAPP_EINVAL, "ckpt_every must be in [1, 1024]");
     if (scene->n_seg > gm::kMaxSegments)
         return fail(ctx, GMAPP_ECAPACITY, "at most %d segments are supported", gm::kMaxSegments);

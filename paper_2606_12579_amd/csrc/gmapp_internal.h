@@ -6,7 +6,9 @@
 
 #include <cstdarg>
 #include <cstdint>
+#include <cstddef>
 #include <cstdio>
+#include <map>
 #include <string>
 
 #include "../../include/gmapp.h"
@@ -88,6 +90,50 @@ constexpr int kMaxWorkgroups = 65536;
 constexpr size_t kCounterWords = (size_t)kMaxGroups * 16;
 constexpr size_t kSyncWords = kCounterWords + 64;     // counters + done + status (+ pad)
 constexpr size_t kXchgBytes = (size_t)16 << 20;       // rollout exchange area
+// sync words [0, kCounterWords): per-job completion counters of the batched launch;
+// kCounterWords: rollout done counter; +16: watchdog status; +32, +33: batch queue
+constexpr size_t kBatchQueueWord = kCounterWords + 32;
+constexpr int kMaxBatchJobs = 16384;
+constexpr int kBatchWaves = 8;                        // waves per workgroup of the batched kernel
+constexpr int kBatchMaxSegments = 64;                 // moving segments per scene in a batched launch
+constexpr int kStateFloats = 28;                      // resumable agent state, floats per agent
+
+// one job of a batched launch (device copy in the job table)
+struct BatchJob {
+    Scn sc;
+    Agt ag;
+    Prm pr;
+    Out out;
+    float *state;       // [N_a][kStateFloats]
+    int k_begin, k_end; // steps [k_begin, k_end) of 1..N_k run in this launch
+    int item_base;      // first work item of the job
+    int n_items;
+    int wg_items;       // 0: every wave is an agent group of aw agents; 1: the workgroup holds aw agents
+    int aw;             // agents per group: 1, 2, 4, 8
+};
+
+struct BatchTable {
+    int n_jobs, n_items, pad[2];
+    BatchJob jobs[1];   // n_jobs entries (the table is allocated for its capacity)
+};
+constexpr size_t batch_table_bytes(int n_jobs)
+{
+    return offsetof(BatchTable, jobs) + (size_t)(n_jobs > 0 ? n_jobs : 1) * sizeof(BatchJob);
+}
+
+struct BatchLay {
+    int cap;            // LDS points (tile size; worlds up to cap points stay resident)
+    int runs_cap;       // segment runs
+};
+
+struct BatchLaunch {
+    const void *fn;
+    unsigned grid;
+    int block;
+    size_t shm;
+    BatchLay lay;
+    unsigned *queue, *done;
+};
 
 }  // namespace gm
 
@@ -104,6 +150,14 @@ struct gmapp_ctx {
     size_t scratch_bytes = 0;
     bool forced = false;
     gmapp_tiling forced_tiling{0, 0, 0, 0, 0, 0};
+    std::map<unsigned long long, gmapp_tiling> tuned;   // autotuned rollout tilings by shape class
+    bool batch_forced = false;
+    gmapp_batch_tuning batch_forced_tuning{0, 0, 0, 0};
+    bool batch_tuned = false;
+    gmapp_batch_tuning batch_tuned_tuning{0, 0, 0, 0};
+    void *tab_host = nullptr;     // pinned staging of the batched job table
+    size_t tab_host_bytes = 0;
+    hipEvent_t tab_copied = nullptr;   // recorded after the last table copy
     std::string err;
 };
 
@@ -149,5 +203,32 @@ gmapp_status launch_voxel_downsample(gmapp_ctx *ctx, const float *x, const float
                                      long long capacity, long long *n_out_dev, hipStream_t stream);
 gmapp_status check_tiling(gmapp_ctx *ctx, const Tiling &t, long long n_points, int n_seg, int cutoff);
 size_t rollout_lds_bytes(const Tiling &t, long long n_points, int n_seg);
+
+// shape class of the rollout autotuner's cache: N_O and N_k rounded up to powers of two
+inline unsigned long long tune_key(long long n_points, int n_agents, int n_steps, int n_seg, int cutoff)
+{
+    auto lg = [](long long v) {
+        unsigned long long b = 0;
+        while ((1ll << b) < v && b < 62) ++b;
+        return b;
+    };
+    return (lg(n_points) << 56) | (lg(n_steps) << 48) | ((unsigned long long)(n_seg > 0) << 47) |
+           ((unsigned long long)(cutoff & 1) << 46) | (unsigned long long)(unsigned)n_agents;
+}
+
+// batched launch (batch.hip)
+size_t batch_lds_bytes(const BatchLay &lay);
+gmapp_status batch_launch_shape(gmapp_ctx *ctx, const BatchLay &lay, int wg_per_cu, BatchLaunch &out);
+gmapp_status launch_batch(gmapp_ctx *ctx, const BatchTable *tab_dev, const BatchLaunch &l, hipStream_t stream);
+
+// argument checks and device views shared by the entry points (api.hip)
+gmapp_status check_ctx(gmapp_ctx *ctx);
+gmapp_status check_scene(gmapp_ctx *ctx, const gmapp_scene *sc);
+gmapp_status check_agents(gmapp_ctx *ctx, const gmapp_agents *ag);
+gmapp_status check_params(gmapp_ctx *ctx, const gmapp_params *p, bool need_steps);
+gmapp_status check_query(gmapp_ctx *ctx, const gmapp_query *q);
+Scn dev_scene(const gmapp_scene *sc);
+Agt dev_agents(const gmapp_agents *ag);
+Prm dev_params(const gmapp_params *p, const gmapp_query *q);
 
 }  // namespace gm

@@ -70,6 +70,22 @@ class Tiling(ctypes.Structure):
         return (self.agents, self.waves, self.shards, self.tile_points, self.layout, self.group)
 
 
+class Job(ctypes.Structure):
+    _fields_ = [("scene", Scene), ("agents", Agents), ("query", Query), ("params", Params), ("out", Outputs),
+                ("state", ctypes.c_void_p), ("k_begin", ctypes.c_int32), ("k_end", ctypes.c_int32)]
+
+
+class BatchTuning(ctypes.Structure):
+    _fields_ = [("tile_points", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32), ("balance", ctypes.c_int32),
+                ("item_shape", ctypes.c_int32)]
+
+    def as_tuple(self):
+        return (self.tile_points, self.wg_per_cu, self.balance, self.item_shape)
+
+
+STATE_FLOATS = 28
+
+
 _lib = None
 
 
@@ -101,6 +117,17 @@ def load_library(path: str = LIB_PATH):
                                                     vp]),
         "gmapp_get_tiling": (ctypes.c_int32, [vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                               ctypes.c_int32, P(Tiling)]),
+        "gmapp_rollout_batch": (ctypes.c_int32, [vp, P(Job), ctypes.c_int32, vp]),
+        "gmapp_set_batch_tuning": (ctypes.c_int32, [vp, P(BatchTuning)]),
+        "gmapp_get_batch_tuning": (ctypes.c_int32, [vp, P(BatchTuning)]),
+        "gmapp_batch_create": (ctypes.c_int32, [vp, ctypes.c_int32, P(vp)]),
+        "gmapp_batch_set_jobs": (ctypes.c_int32, [vp, P(Job), ctypes.c_int32]),
+        "gmapp_batch_launch": (ctypes.c_int32, [vp, vp]),
+        "gmapp_batch_destroy": (None, [vp]),
+        "gmapp_autotune_rollout": (ctypes.c_int32, [vp, P(Scene), P(Agents), P(Query), P(Params), ctypes.c_int32,
+                                                    P(Tiling), P(ctypes.c_float), vp]),
+        "gmapp_autotune_batch": (ctypes.c_int32, [vp, P(Job), ctypes.c_int32, ctypes.c_int32, P(BatchTuning),
+                                                  P(ctypes.c_float), vp]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
@@ -209,6 +236,77 @@ def _agents_struct(ag: DeviceAgents, device) -> Agents:
     return Agents(_ptr(ag.k_a), _ptr(ag.d_a), _ptr(ag.k_f), _ptr(ag.r_d), _ptr(ag.r_a), _ptr(ag.omega), n)
 
 
+@dataclasses.dataclass
+class BatchJob:
+    """One job of a batched launch: device scene and agents, host query and
+    params, device outputs (dict as returned by Context.outputs), optional state
+    tensor [N_a, STATE_FLOATS] and the step range [k_begin, k_end)."""
+    scene: DeviceScene
+    agents: DeviceAgents
+    query: object
+    params: object
+    out: dict
+    state: object = None
+    k_begin: int = 1
+    k_end: int = 0          # 0 = N_k + 1
+
+
+def _outputs_check(out, na, nk, dev):
+    import torch
+    _check_tensor(out.get("traj"), "traj", na * (nk + 1) * 3, torch.float32, dev)
+    _check_tensor(out["cost"], "cost", na * 5, torch.float32, dev)
+    _check_tensor(out.get("min_clear"), "min_clear", na * nk, torch.float32, dev)
+    _check_tensor(out["best"], "best", 1, torch.int32, dev)
+
+
+def _job_struct(j: BatchJob, dev) -> Job:
+    import torch
+    na, nk = j.agents.n, int(j.params.n_steps)
+    _outputs_check(j.out, na, nk, dev)
+    _check_tensor(j.state, "state", na * STATE_FLOATS, torch.float32, dev)
+    o = Outputs(_ptr(j.out.get("traj")), _ptr(j.out["cost"]), _ptr(j.out.get("min_clear")), _ptr(j.out["best"]))
+    k_end = int(j.k_end) if j.k_end else nk + 1
+    return Job(_scene_struct(j.scene, dev), _agents_struct(j.agents, dev), make_query(j.query),
+               make_params(j.params), o, _ptr(j.state), int(j.k_begin), k_end)
+
+
+def _jobs_array(jobs, dev):
+    arr = (Job * len(jobs))()
+    for i, j in enumerate(jobs):
+        arr[i] = _job_struct(j, dev)
+    return arr
+
+
+class Batch:
+    """An instantiated control-cycle graph (gmapp_batch_*): set_jobs, then launch."""
+
+    def __init__(self, ctx: "Context", max_jobs: int):
+        self.ctx = ctx
+        h = ctypes.c_void_p()
+        ctx._raise(ctx.lib.gmapp_batch_create(ctx.handle, int(max_jobs), ctypes.byref(h)))
+        self.handle = h
+        self._keep = None
+
+    def set_jobs(self, jobs):
+        arr = _jobs_array(jobs, self.ctx.device)
+        self.ctx._raise(self.ctx.lib.gmapp_batch_set_jobs(self.handle, arr, len(jobs)))
+        self._keep = jobs
+
+    def launch(self, stream=None):
+        self.ctx._raise(self.ctx.lib.gmapp_batch_launch(self.handle, self.ctx._stream(stream)))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.ctx.lib.gmapp_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Context:
     """One library context (device arena + tiling policy) on one HIP device."""
 
@@ -259,6 +357,56 @@ class Context:
         self._raise(self.lib.gmapp_get_tiling(self.handle, int(n_points), int(n_agents), int(n_steps), int(n_seg),
                                               int(cutoff), ctypes.byref(t)))
         return t.as_tuple()
+
+    # ------------------------------------------------------------------ batched launches
+    def outputs(self, n_agents, n_steps, traj=True, min_clear=True):
+        """Freshly allocated output tensors for one problem."""
+        import torch
+        dev = self.device
+        return {
+            "traj": torch.empty((n_agents, n_steps + 1, 3), dtype=torch.float32, device=dev) if traj else None,
+            "cost": torch.empty((n_agents, 5), dtype=torch.float32, device=dev),
+            "min_clear": torch.empty((n_agents, n_steps), dtype=torch.float32, device=dev) if min_clear else None,
+            "best": torch.empty(1, dtype=torch.int32, device=dev),
+        }
+
+    def rollout_batch(self, jobs, stream=None):
+        """gmapp_rollout_batch over a list of BatchJob."""
+        arr = _jobs_array(jobs, self.device)
+        self._raise(self.lib.gmapp_rollout_batch(self.handle, arr, len(jobs), self._stream(stream)))
+
+    def batch(self, max_jobs):
+        return Batch(self, max_jobs)
+
+    def set_batch_tuning(self, tile_points=0, wg_per_cu=0, balance=0, item_shape=0):
+        t = BatchTuning(tile_points, wg_per_cu, balance, item_shape)
+        self._raise(self.lib.gmapp_set_batch_tuning(self.handle, ctypes.byref(t)))
+
+    def clear_batch_tuning(self):
+        self._raise(self.lib.gmapp_set_batch_tuning(self.handle, None))
+
+    def get_batch_tuning(self):
+        t = BatchTuning()
+        self._raise(self.lib.gmapp_get_batch_tuning(self.handle, ctypes.byref(t)))
+        return t.as_tuple()
+
+    def autotune_rollout(self, scene: DeviceScene, agents: DeviceAgents, query, params, proxy_steps=32, stream=None):
+        """gmapp_autotune_rollout: returns (tiling tuple, proxy ms) and caches the choice."""
+        t, ms = Tiling(), ctypes.c_float()
+        sc, ag = _scene_struct(scene, self.device), _agents_struct(agents, self.device)
+        q, p = make_query(query), make_params(params)
+        self._raise(self.lib.gmapp_autotune_rollout(self.handle, ctypes.byref(sc), ctypes.byref(ag), ctypes.byref(q),
+                                                    ctypes.byref(p), int(proxy_steps), ctypes.byref(t),
+                                                    ctypes.byref(ms), self._stream(stream)))
+        return t.as_tuple(), float(ms.value)
+
+    def autotune_batch(self, jobs, proxy_steps=16, stream=None):
+        """gmapp_autotune_batch: returns (tuning tuple, proxy ms) and keeps the choice."""
+        arr = _jobs_array(jobs, self.device)
+        t, ms = BatchTuning(), ctypes.c_float()
+        self._raise(self.lib.gmapp_autotune_batch(self.handle, arr, len(jobs), int(proxy_steps), ctypes.byref(t),
+                                                  ctypes.byref(ms), self._stream(stream)))
+        return t.as_tuple(), float(ms.value)
 
     # ------------------------------------------------------------------ rollout
     def rollout(self, scene: DeviceScene, agents: DeviceAgents, query, params, traj=True, min_clear=True,

@@ -238,6 +238,83 @@ gmapp_status gmapp_autotune_rollout(gmapp_ctx *ctx, const gmapp_scene *scene, co
 gmapp_status gmapp_autotune_batch(gmapp_ctx *ctx, const gmapp_job *jobs, int32_t n_jobs, int32_t proxy_steps,
                                   gmapp_batch_tuning *best, float *best_ms, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Replanning server: a request loop on its own host thread that admits requests
+ * while device memory (a budget allocated once at creation) and slots allow,
+ * uploads their worlds and agents once, and runs control cycles in which every
+ * active request advances by `quantum_steps` steps (gmapp_batch graph replays;
+ * agent state stays on the device between cycles).  Requests that arrive while
+ * others run join at the next cycle (continuous batching); a request's result
+ * is the rollout and selection of gmapp_rollout for its problem.  Uploads of
+ * newly admitted requests overlap the running cycle.  The server owns its
+ * context while it exists: make no other calls on that context meanwhile.
+ */
+typedef struct gmapp_server gmapp_server;
+
+typedef struct {
+    uint64_t memory_budget; /* device bytes for admitted requests (0 = 4 GiB) */
+    int32_t max_active;     /* requests on the device at once, 1..GMAPP_BATCH_MAX_JOBS (0 = 256) */
+    int32_t quantum_steps;  /* steps per request per cycle (0 = 50) */
+    int32_t max_queue;      /* waiting requests before submit refuses with ECAPACITY (0 = 65536) */
+} gmapp_server_config;
+
+/* A replanning request.  All arrays are host memory owned by the caller and must
+ * stay valid until the request's completion has been polled (inputs are copied
+ * to the device at admission, outputs written before completion).  Device bytes used while
+ * active: 12 N_O + 16 n_seg + 4 + 32 N_a (agents) + 20 N_a + 4 (costs, choice)
+ * + 112 N_a (state) + 12 N_a (N_k + 1) if traj is requested, each piece rounded
+ * up to 256 B. */
+typedef struct {
+    const float *x, *y, *z;     /* [N_O] */
+    int64_t n_points;
+    float r_obs;
+    int32_t n_seg;              /* <= GMAPP_BATCH_MAX_SEGMENTS */
+    const int32_t *seg_begin;   /* [n_seg + 1] */
+    const float *seg_vel;       /* [n_seg][3] */
+    const float *k_a, *d_a, *k_f, *r_d, *r_a; /* [N_a] */
+    const float *omega;         /* [N_a][3] */
+    int32_t n_agents;
+    gmapp_query query;
+    gmapp_params params;
+    double deadline_s;          /* finish within this many seconds of submission, else ETIMEOUT (0 = none) */
+    float *cost;                /* out [N_a][5] or NULL */
+    float *traj;                /* out [N_a][N_k + 1][3] or NULL (then no device trajectory either) */
+} gmapp_request;
+
+typedef struct {
+    int64_t id;
+    gmapp_status status;        /* OK, ETIMEOUT (deadline passed) or ECANCELLED */
+    int32_t best;               /* i*, -1 for N_a = 0 or when status != OK */
+    double queue_s;             /* submission to admission (-1 if never admitted) */
+    double latency_s;           /* submission to completion */
+} gmapp_completion;
+
+typedef struct {
+    int64_t submitted, completed, rejected, expired, cancelled, cycles;
+    double p50_s, p99_s, max_s, mean_s; /* latency of completed requests */
+    double busy_s;                      /* time spent in cycles */
+    double interactions_per_s;          /* N_a N_k N_O of completed requests / busy_s */
+    double cycle_mean_s;
+    int32_t max_active_seen;
+    uint64_t peak_bytes;
+} gmapp_server_stats;
+
+gmapp_status gmapp_server_create(gmapp_ctx *ctx, const gmapp_server_config *cfg, gmapp_server **out);
+/* Queue a request; *id receives its id.  EINVAL for a malformed request or one
+ * that can never fit the budget, ECAPACITY when the queue is full. */
+gmapp_status gmapp_server_submit(gmapp_server *s, const gmapp_request *req, int64_t *id);
+/* Up to max completions, waiting up to wait_ms for the first; returns the count (>= 0). */
+int32_t gmapp_server_poll(gmapp_server *s, gmapp_completion *out, int32_t max, int32_t wait_ms);
+/* Cancel a waiting or active request (it completes with ECANCELLED); EINVAL if unknown or finished. */
+gmapp_status gmapp_server_cancel(gmapp_server *s, int64_t id);
+/* Wait until no request is waiting or active (ETIMEOUT after timeout_ms; < 0 = no limit). */
+gmapp_status gmapp_server_drain(gmapp_server *s, int32_t timeout_ms);
+/* Counters and latency percentiles so far; returns the first device error the
+ * loop met (its requests completed with that status), else GMAPP_OK. */
+gmapp_status gmapp_server_get_stats(gmapp_server *s, gmapp_server_stats *out);
+/* Stops the loop after the running cycle; requests not finished are dropped. */
+void gmapp_server_destroy(gmapp_server *s);
+
 /* Adjoint rollout: gradients of sum_i grad_total[i] C_i, with C_i agent i's total
  * cost (Eq. 16) after the rollout of gmapp_rollout, with respect to each agent's
  * k_a, d_a, k_f (Eqs. 2, 7) and rotation vector omega (Eq. 3).  One launch runs

@@ -86,6 +86,37 @@ class BatchTuning(ctypes.Structure):
 STATE_FLOATS = 28
 
 
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("memory_budget", ctypes.c_uint64), ("max_active", ctypes.c_int32),
+                ("quantum_steps", ctypes.c_int32), ("max_queue", ctypes.c_int32)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("z", ctypes.c_void_p), ("n_points", ctypes.c_int64),
+                ("r_obs", ctypes.c_float), ("n_seg", ctypes.c_int32), ("seg_begin", ctypes.c_void_p),
+                ("seg_vel", ctypes.c_void_p), ("k_a", ctypes.c_void_p), ("d_a", ctypes.c_void_p),
+                ("k_f", ctypes.c_void_p), ("r_d", ctypes.c_void_p), ("r_a", ctypes.c_void_p),
+                ("omega", ctypes.c_void_p), ("n_agents", ctypes.c_int32), ("query", Query), ("params", Params),
+                ("deadline_s", ctypes.c_double), ("cost", ctypes.c_void_p), ("traj", ctypes.c_void_p)]
+
+
+class Completion(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int64), ("status", ctypes.c_int32), ("best", ctypes.c_int32),
+                ("queue_s", ctypes.c_double), ("latency_s", ctypes.c_double)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("rejected", ctypes.c_int64),
+                ("expired", ctypes.c_int64), ("cancelled", ctypes.c_int64), ("cycles", ctypes.c_int64),
+                ("p50_s", ctypes.c_double), ("p99_s", ctypes.c_double), ("max_s", ctypes.c_double),
+                ("mean_s", ctypes.c_double), ("busy_s", ctypes.c_double), ("interactions_per_s", ctypes.c_double),
+                ("cycle_mean_s", ctypes.c_double), ("max_active_seen", ctypes.c_int32),
+                ("peak_bytes", ctypes.c_uint64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 _lib = None
 
 
@@ -128,6 +159,13 @@ def load_library(path: str = LIB_PATH):
                                                     P(Tiling), P(ctypes.c_float), vp]),
         "gmapp_autotune_batch": (ctypes.c_int32, [vp, P(Job), ctypes.c_int32, ctypes.c_int32, P(BatchTuning),
                                                   P(ctypes.c_float), vp]),
+        "gmapp_server_create": (ctypes.c_int32, [vp, P(ServerConfig), P(vp)]),
+        "gmapp_server_submit": (ctypes.c_int32, [vp, P(Request), P(ctypes.c_int64)]),
+        "gmapp_server_poll": (ctypes.c_int32, [vp, P(Completion), ctypes.c_int32, ctypes.c_int32]),
+        "gmapp_server_cancel": (ctypes.c_int32, [vp, ctypes.c_int64]),
+        "gmapp_server_drain": (ctypes.c_int32, [vp, ctypes.c_int32]),
+        "gmapp_server_get_stats": (ctypes.c_int32, [vp, P(ServerStats)]),
+        "gmapp_server_destroy": (None, [vp]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
@@ -307,6 +345,76 @@ class Batch:
             pass
 
 
+class Server:
+    """gmapp_server_*: the replanning request loop.  submit() takes a scenes.Problem
+    (host arrays), keeps its arrays alive until its completion is polled, and
+    returns the request id; poll() returns completions with the host results."""
+
+    def __init__(self, ctx: "Context", memory_budget=0, max_active=0, quantum_steps=0, max_queue=0):
+        self.ctx = ctx
+        cfg = ServerConfig(int(memory_budget), int(max_active), int(quantum_steps), int(max_queue))
+        h = ctypes.c_void_p()
+        ctx._raise(ctx.lib.gmapp_server_create(ctx.handle, ctypes.byref(cfg), ctypes.byref(h)))
+        self.handle = h
+        self.live = {}
+
+    def submit(self, problem, deadline_s=0.0, traj=False):
+        sc, ag, prm = problem.scene, problem.agents, problem.params
+        f32 = lambda a: np.ascontiguousarray(a, dtype=np.float32)
+        keep = {"x": f32(sc.x), "y": f32(sc.y), "z": f32(sc.z)}
+        n_seg = int(sc.n_seg)
+        if n_seg > 0:
+            keep["seg_begin"] = np.ascontiguousarray(sc.seg_begin, dtype=np.int32)
+            keep["seg_vel"] = f32(sc.seg_vel)
+        for nm in ("k_a", "d_a", "k_f", "r_d", "r_a", "omega"):
+            keep[nm] = f32(getattr(ag, nm))
+        na, nk = int(ag.n), int(prm.n_steps)
+        keep["cost"] = np.full((na, 5), np.nan, np.float32)
+        keep["traj"] = np.zeros((na, nk + 1, 3), np.float32) if traj else None
+        p = lambda k: None if keep.get(k) is None else keep[k].ctypes.data
+        r = Request(p("x"), p("y"), p("z"), int(sc.n), float(sc.r_obs), n_seg, p("seg_begin"), p("seg_vel"),
+                    p("k_a"), p("d_a"), p("k_f"), p("r_d"), p("r_a"), p("omega"), na, make_query(problem.query),
+                    make_params(prm), float(deadline_s), p("cost"), p("traj"))
+        rid = ctypes.c_int64()
+        self.ctx._raise(self.ctx.lib.gmapp_server_submit(self.handle, ctypes.byref(r), ctypes.byref(rid)))
+        self.live[rid.value] = keep
+        return rid.value
+
+    def poll(self, max_n=256, wait_ms=0):
+        buf = (Completion * max_n)()
+        n = self.ctx.lib.gmapp_server_poll(self.handle, buf, int(max_n), int(wait_ms))
+        out = []
+        for c in buf[:n]:
+            keep = self.live.pop(c.id, {})
+            out.append({"id": c.id, "status": c.status, "best": c.best, "queue_s": c.queue_s,
+                        "latency_s": c.latency_s, "cost": keep.get("cost"), "traj": keep.get("traj")})
+        return out
+
+    def cancel(self, rid):
+        self.ctx._raise(self.ctx.lib.gmapp_server_cancel(self.handle, int(rid)))
+
+    def drain(self, timeout_ms=-1):
+        return self.ctx.lib.gmapp_server_drain(self.handle, int(timeout_ms))
+
+    def stats(self):
+        st = ServerStats()
+        rc = self.ctx.lib.gmapp_server_get_stats(self.handle, ctypes.byref(st))
+        d = st.as_dict()
+        d["fault"] = rc
+        return d
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.ctx.lib.gmapp_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Context:
     """One library context (device arena + tiling policy) on one HIP device."""
 
@@ -377,6 +485,9 @@ class Context:
 
     def batch(self, max_jobs):
         return Batch(self, max_jobs)
+
+    def server(self, memory_budget=0, max_active=0, quantum_steps=0, max_queue=0):
+        return Server(self, memory_budget, max_active, quantum_steps, max_queue)
 
     def set_batch_tuning(self, tile_points=0, wg_per_cu=0, balance=0, item_shape=0):
         t = BatchTuning(tile_points, wg_per_cu, balance, item_shape)

@@ -43,7 +43,8 @@ def _check(pb, gpu, ref, w, rel=5e-3, label=""):
     err = np.abs(gpu - exp)
     bound = rel * np.maximum(np.abs(exp), 1e-3 * scale[None, :]) + 1e-9
     worst = (err / bound).max(0)
-    print(f"{label} adjoint worst err/bound per column {dict(zip(NAMES, np.round(worst, 3)))}", flush=True)
+    print(f"{label} adjoint worst err/bound per column " + ", ".join(f"{n} {v:.2e}" for n, v in zip(NAMES, worst)),
+          flush=True)
     assert (err <= bound).all(), (label, worst)
 
 

@@ -20,6 +20,39 @@ PEAK_FP32 = 157.3e12          # MI355X FP32 vector peak, FLOP/s
 FLOP_PER_INTERACTION = 25     # algorithmic FP32 work of one (agent, sphere, step) evaluation
 
 
+def kernel_sources_sha1(names=("rollout.hip", "pairs.h", "gmapp_internal.h")):
+    """Fingerprint of the sources of the rollout kernel (the HBM counters below are
+    valid only for the kernel they were taken on)."""
+    import hashlib
+    h = hashlib.sha1()
+    for n in names:
+        with open(os.path.join(ROOT, "paper_2606_12579_amd", "csrc", n), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(path=os.path.join(ROOT, "profiles", "rollout_config2_hbm_counters.md")):
+    """HBM bytes per k_rollout launch from the committed rocprofv3 --pmc summary
+    (FETCH_SIZE and WRITE_SIZE, each scaled by the same counter on a copy of known
+    size); None when the summary is missing or the kernel changed since."""
+    try:
+        text = open(path).read()
+    except OSError:
+        return None
+    vals = {}
+    for line in text.splitlines():
+        if ":" in line and line.strip().startswith(("fetch_bytes_per_launch", "write_bytes_per_launch",
+                                                    "kernel_source_sha1")):
+            k, v = line.strip().split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("kernel_source_sha1") != kernel_sources_sha1():
+        return None
+    try:
+        return float(vals["fetch_bytes_per_launch"]) + float(vals["write_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def _percentile(xs, q):
     import numpy as np
     return float(np.percentile(np.asarray(xs), q)) if xs else None
@@ -75,6 +108,78 @@ def perception_pass(ctx, dev, reps=20):
             "bytes_note": "algorithmic: depth 4 B + points 12 B per pixel; points 12 B per point + centres 12 B"}
 
 
+def batched_vs_per_scene(ctx, dev, reqs, proxy_steps=16):
+    """The 512-request mix (N_O in [1k, 200k], N_a in {16, 64, 256}, N_k in [100, 1000]):
+    one batched persistent launch (autotuned) against one gmapp_rollout launch per
+    scene, both over device-resident inputs, timed with HIP events on one stream."""
+    import numpy as np
+    import torch
+    from paper_2606_12579_amd import gmapp
+    jobs = []
+    for r in reqs:
+        pb = r.problem
+        jobs.append(gmapp.BatchJob(gmapp.scene_to_device(pb.scene, dev), gmapp.agents_to_device(pb.agents, dev),
+                                   pb.query, pb.params, ctx.outputs(pb.agents.n, pb.params.n_steps, traj=False,
+                                                                    min_clear=False)))
+    work = float(sum(r.problem.agents.n * r.problem.params.n_steps * r.problem.scene.n for r in reqs))
+    stream = torch.cuda.current_stream(dev)
+    t_tune = time.perf_counter()
+    tuning, proxy_ms = ctx.autotune_batch(jobs, proxy_steps=proxy_steps, stream=stream)
+    t_tune = time.perf_counter() - t_tune
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    ctx.rollout_batch(jobs, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    batched_s = e0.elapsed_time(e1) * 1e-3
+    batched_cost = [j.out["cost"].clone() for j in jobs]
+    # one launch per scene (automatic tiling), same outputs
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for j in jobs:
+        ctx.rollout(j.scene, j.agents, j.query, j.params, out=j.out, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    single_s = e0.elapsed_time(e1) * 1e-3
+    # the two paths agree (FP32 summation order only)
+    d = max(float((a - j.out["cost"]).abs().max()) for a, j in zip(batched_cost, jobs) if j.agents.n)
+    return {"requests": len(reqs), "interactions": work,
+            "batched_interactions_per_s": work / batched_s, "batched_s": batched_s,
+            "per_scene_interactions_per_s": work / single_s, "per_scene_s": single_s,
+            "speedup": single_s / batched_s, "batched_frac_fp32_peak": work * FLOP_PER_INTERACTION / batched_s / PEAK_FP32,
+            "tuning": {"tile_points": tuning[0], "wg_per_cu": tuning[1], "balance": tuning[2]},
+            "autotune_s": t_tune, "autotune_best_proxy_ms": proxy_ms, "max_cost_diff_batched_vs_per_scene": d}
+
+
+def serving(ctx, reqs, quantum=50, budget=8 << 30):
+    """The same 512 requests arriving as a Poisson stream (1 kHz) into the
+    replanning server: admission by device memory, control cycles of `quantum`
+    steps, latency from submission to results on the host."""
+    srv = ctx.server(memory_budget=budget, max_active=512, quantum_steps=quantum)
+    try:
+        ids = []
+        t0 = time.perf_counter()
+        for r in reqs:
+            while time.perf_counter() - t0 < r.arrival_s:
+                pass
+            ids.append(srv.submit(r.problem))
+        got = 0
+        while got < len(ids):
+            got += len(srv.poll(max_n=512, wait_ms=1000))
+        wall = time.perf_counter() - t0
+        st = srv.stats()
+    finally:
+        srv.close()
+    work = float(sum(r.problem.agents.n * r.problem.params.n_steps * r.problem.scene.n for r in reqs))
+    return {"requests": len(reqs), "arrival_rate_hz": 1000.0, "quantum_steps": quantum,
+            "p50_latency_ms": st["p50_s"] * 1e3, "p99_latency_ms": st["p99_s"] * 1e3,
+            "max_latency_ms": st["max_s"] * 1e3, "completed": st["completed"], "cycles": st["cycles"],
+            "mean_cycle_ms": st["cycle_mean_s"] * 1e3, "interactions_per_s_busy": st["interactions_per_s"],
+            "interactions_per_s_wall": work / wall, "wall_s": wall, "max_active": st["max_active_seen"],
+            "peak_device_bytes": st["peak_bytes"], "fault": st["fault"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -83,6 +188,9 @@ def main():
     ap.add_argument("--replans", type=int, default=2000, help="back-to-back replans for the latency percentiles")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU (oracle) baseline")
     ap.add_argument("--no-perception", action="store_true", help="skip the perception-pass timing")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 512-request batched / served mix")
+    ap.add_argument("--no-autotune", action="store_true", help="use the built-in tiling choice")
+    ap.add_argument("--batch-requests", type=int, default=512, help="requests of the batched / served mix")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the rollout shards scenes and agents with no per-step traffic, "
@@ -101,6 +209,10 @@ def main():
     ag = gmapp.agents_to_device(pb.agents, dev)
     na, nk, no = pb.agents.n, pb.params.n_steps, pb.scene.n
     out = ctx.rollout(sc, ag, pb.query, pb.params)          # allocates the outputs once
+    t_tune = time.perf_counter()
+    if not args.no_autotune:                                # cached for this shape class by the library
+        ctx.autotune_rollout(sc, ag, pb.query, pb.params, proxy_steps=64)
+    t_tune = time.perf_counter() - t_tune
     tiling = ctx.get_tiling(no, na, nk, pb.scene.n_seg, pb.params.cutoff)
     stream = torch.cuda.current_stream(dev)
     for _ in range(args.warmup):
@@ -143,7 +255,8 @@ def main():
             q.p0 = pin[:3].numpy().copy()
         q.t0 = float(np.float32((r + 1) * 1e-3))
         q.incumbent = b
-    p50, p99 = _percentile(lat, 50) * 1e3, _percentile(lat, 99) * 1e3
+    p50 = _percentile(lat, 50) * 1e3 if lat else None
+    p99 = _percentile(lat, 99) * 1e3 if lat else None
 
     res = {
         "metric": "agent-step-point interactions/s + p99 replan latency at 1e-4 m pos err",
@@ -160,22 +273,33 @@ def main():
         "data": "synthetic",
         "config": {"workload": "moving 10-sphere/10-box scene, N_O=50000 points, N_a=64 agents, N_k=500 steps, "
                                "dt=1 ms (one planning cycle per step)",
-                   "n_points": no, "n_agents": na, "n_steps": nk, "tiling": list(tiling)},
+                   "n_points": no, "n_agents": na, "n_steps": nk, "tiling": list(tiling),
+                   "tiling_source": "built-in" if args.no_autotune else "autotuned", "autotune_s": t_tune},
         "p50_replan_ms": p50,
         "p99_replan_ms": p99,
         "replans": args.replans,
         "kernel_ms_mean": avg_kernel_s * 1e3,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32, "traffic": None},
+                     "frac": achieved / PEAK_FP32, "traffic": measured_traffic(),
+                     "kernel_source_sha1": kernel_sources_sha1()},
     }
     if not args.no_perception:
         res["perception"] = perception_pass(ctx, dev)
+    if not args.no_batch:
+        reqs = scenes.config5(n_scenes=args.batch_requests)
+        print(f"# batched mix: {len(reqs)} requests generated", file=sys.stderr, flush=True)
+        res["batched"] = batched_vs_per_scene(ctx, dev, reqs)
+        print(f"# batched: {res['batched']['batched_s']:.3f} s vs per-scene {res['batched']['per_scene_s']:.3f} s",
+              file=sys.stderr, flush=True)
+        res["serving"] = serving(ctx, reqs)
+        print(f"# serving: p99 {res['serving']['p99_latency_ms']:.1f} ms", file=sys.stderr, flush=True)
     # a plain device copy of known size: reference for the HBM byte counters of a profiled run
-    ref = torch.empty(64 << 20, dtype=torch.float32, device=dev)
+    # (an elementwise kernel, so that the counters see it: reads 256 MiB, writes 256 MiB)
+    ref = torch.ones(64 << 20, dtype=torch.float32, device=dev)
     ref2 = torch.empty_like(ref)
-    ref2.copy_(ref)
+    torch.mul(ref, 1.0, out=ref2)
     torch.cuda.synchronize()
-    res["copy_reference_bytes"] = 2 * ref.numel() * 4
+    res["copy_reference_bytes"] = {"read": ref.numel() * 4, "write": ref.numel() * 4}
     del ref, ref2
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(pb)

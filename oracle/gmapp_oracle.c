@@ -12,7 +12,7 @@
  * no blocking, no fusion, no algebraic rewriting of the force law.  Agents are
  * independent, so the only parallelism is an OpenMP loop over agents.
  *
- * Readings where the paper is silent or ambiguous (all listed in the design doc):
+ * Readings where the paper is silent or ambiguous:
  *   - current vector (Eq. 3) parameterised by the agent's rotation vector:
  *     c = omega - n (n . omega), n the unit vector between agent and sphere centre;
  *   - clamped surface distance of Alg. 1: rho = max(|d| - (r_O + r_a), eps), used

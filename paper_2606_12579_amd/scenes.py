@@ -32,7 +32,7 @@ import numpy as np
 F32 = np.float32
 
 # ---------------------------------------------------------------------------
-# default parameters (the paper prints no values; the readings are in the design doc)
+# default parameters (the paper prints no values for these; chosen readings)
 MASS = 1.0
 K_A = 400.0
 D_A = 2.0 * math.sqrt(2.0 * K_A * MASS)  # critical damping of the half-kick dynamics

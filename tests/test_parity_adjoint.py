@@ -37,7 +37,8 @@ def _gpu_grads(ctx, pb, w, ckpt=50):
 
 
 def _check(pb, gpu, ref, w, rel=5e-3, label=""):
-    """Per parameter column: |g_gpu - g_or| <= rel * max(|g_or|, 1e-3 max_i |g_or_i|)."""
+    """Per parameter column: |g_gpu - g_or| <= rel * max(|g_or|, 1e-3 max_i |g_or_i|): FP32 reverse-mode
+    rounding grows with the horizon, the floor covers near-zero entries."""
     exp = ref[:, 1:] * w[:, None]
     scale = np.abs(exp).max(0)
     err = np.abs(gpu - exp)

@@ -108,6 +108,37 @@ def perception_pass(ctx, dev, reps=20):
             "bytes_note": "algorithmic: depth 4 B + points 12 B per pixel; points 12 B per point + centres 12 B"}
 
 
+def adjoint_pass(ctx, dev, reps=3):
+    """128 agents, 400 steps, 20,000 static sphere points, C1 taper: the forward
+    rollout and the adjoint (checkpoints every 50 steps, recompute + reverse sweep)
+    timed with HIP events. Work unit: N_a N_k N_O interactions of the forward pass."""
+    import torch
+    from paper_2606_12579_amd import gmapp, scenes
+    pb = scenes.config4()
+    sc, ag = gmapp.scene_to_device(pb.scene, dev), gmapp.agents_to_device(pb.agents, dev)
+    w = torch.ones(pb.agents.n, dtype=torch.float32, device=dev)
+    out = ctx.rollout(sc, ag, pb.query, pb.params, traj=False, min_clear=False)
+    ctx.rollout_backward(sc, ag, pb.query, pb.params, w, 50)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream(dev)
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    f_ms, b_ms = [], []
+    for _ in range(reps):
+        e[0].record(stream)
+        ctx.rollout(sc, ag, pb.query, pb.params, out=out, stream=stream)
+        e[1].record(stream)
+        ctx.rollout_backward(sc, ag, pb.query, pb.params, w, 50, stream=stream)
+        e[2].record(stream)
+        torch.cuda.synchronize()
+        f_ms.append(e[0].elapsed_time(e[1]))
+        b_ms.append(e[1].elapsed_time(e[2]))
+    inter = float(pb.agents.n) * pb.params.n_steps * pb.scene.n
+    f, b = min(f_ms), min(b_ms)
+    return {"workload": "N_a=128, N_k=400, N_O=20000 static, C1 taper, checkpoint every 50 steps",
+            "forward_ms": f, "backward_ms": b, "backward_over_forward": b / f,
+            "forward_interactions_per_s": inter / (f * 1e-3), "backward_interactions_per_s": inter / (b * 1e-3)}
+
+
 def batched_vs_per_scene(ctx, dev, reqs, proxy_steps=16):
     """The 512-request mix (N_O in [1k, 200k], N_a in {16, 64, 256}, N_k in [100, 1000]):
     one batched persistent launch (autotuned) against one gmapp_rollout launch per
@@ -190,6 +221,7 @@ def main():
     ap.add_argument("--no-perception", action="store_true", help="skip the perception-pass timing")
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-request batched / served mix")
     ap.add_argument("--no-autotune", action="store_true", help="use the built-in tiling choice")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
     ap.add_argument("--batch-requests", type=int, default=512, help="requests of the batched / served mix")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -285,6 +317,8 @@ def main():
     }
     if not args.no_perception:
         res["perception"] = perception_pass(ctx, dev)
+    if not args.no_adjoint:
+        res["adjoint"] = adjoint_pass(ctx, dev)
     if not args.no_batch:
         reqs = scenes.config5(n_scenes=args.batch_requests)
         print(f"# batched mix: {len(reqs)} requests generated", file=sys.stderr, flush=True)

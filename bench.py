@@ -101,11 +101,43 @@ def perception_pass(ctx, dev, reps=20):
     nv = int(vox[3].item())
     bp_bytes = 4 * n + 12 * n
     vx_bytes = 12 * n + 12 * nv
-    return {"frame": "640x480 z-depth, 20 boxes on a plane, 1 cm voxels", "points": n, "voxels": nv,
-            "depth_to_points_ms": t_bp / reps, "voxel_downsample_ms": t_vx / reps,
-            "depth_to_points_GBps": bp_bytes / (t_bp / reps * 1e-3) / 1e9,
-            "voxel_downsample_GBps": vx_bytes / (t_vx / reps * 1e-3) / 1e9,
-            "bytes_note": "algorithmic: depth 4 B + points 12 B per pixel; points 12 B per point + centres 12 B"}
+    res = {"frame": "640x480 z-depth, 20 boxes on a plane, 1 cm voxels", "points": n, "voxels": nv,
+           "depth_to_points_ms": t_bp / reps, "voxel_downsample_ms": t_vx / reps,
+           "depth_to_points_GBps": bp_bytes / (t_bp / reps * 1e-3) / 1e9,
+           "voxel_downsample_GBps": vx_bytes / (t_vx / reps * 1e-3) / 1e9,
+           "bytes_note": "algorithmic: depth 4 B + points 12 B per pixel; points 12 B per point + centres 12 B"}
+    # multi-view: B frames from B poses in one launch, then one fused voxel pass (the HBM-bound regime)
+    B = 64
+    T = torch.as_tensor(scenes.config3_poses(B), device=dev)
+    db = d.unsqueeze(0).repeat(B, 1, 1).contiguous()
+    nb = db.numel()
+    ptsb = tuple(torch.empty(nb, dtype=torch.float32, device=dev) for _ in range(3))
+    capb = 1 << 18
+    voxb = tuple(torch.empty(capb, dtype=torch.float32, device=dev) for _ in range(3)) + \
+        (torch.zeros(1, dtype=torch.int64, device=dev),)
+    for _ in range(2):
+        ctx.depth_to_points_batch(db, fr.K, T, out=ptsb)
+        ctx.voxel_downsample(*ptsb, fr.voxel, fr.box_lo, fr.dims, capacity=capb, out=voxb)
+    torch.cuda.synchronize()
+    t_bp, t_vx = [], []
+    for _ in range(5):
+        e[0].record()
+        ctx.depth_to_points_batch(db, fr.K, T, out=ptsb)
+        e[1].record()
+        ctx.voxel_downsample(*ptsb, fr.voxel, fr.box_lo, fr.dims, capacity=capb, out=voxb)
+        e[2].record()
+        torch.cuda.synchronize()
+        t_bp.append(e[0].elapsed_time(e[1]))
+        t_vx.append(e[1].elapsed_time(e[2]))
+    nvb = int(voxb[3].item())
+    assert nvb <= capb
+    tb, tv = min(t_bp), min(t_vx)
+    res["multiview"] = {"frames": B, "points": nb, "fused_voxels": nvb, "depth_to_points_ms": tb,
+                        "voxel_downsample_ms": tv,
+                        "depth_to_points_GBps": 16 * nb / (tb * 1e-3) / 1e9,
+                        "voxel_downsample_GBps": (12 * nb + 12 * nvb) / (tv * 1e-3) / 1e9,
+                        "hbm_peak_GBps": 8000.0}
+    return res
 
 
 def adjoint_pass(ctx, dev, reps=3):

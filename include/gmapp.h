@@ -341,6 +341,16 @@ gmapp_status gmapp_rollout_backward(gmapp_ctx *ctx, const gmapp_scene *scene, co
 gmapp_status gmapp_depth_to_points(gmapp_ctx *ctx, const float *depth, int32_t w, int32_t h, const float K[4],
                                    const float T_wc[12], float *x, float *y, float *z, void *stream);
 
+/* The same back-projection for n_frames images of one camera (intrinsics K,
+ * host) taken from n_frames poses (multi-view fusion into one world cloud):
+ * depth: device [n_frames][h][w]; T_wc: device [n_frames][12], row-major [R | t]
+ * per frame (poses are not checked for finiteness); frame f's pixel (u, v) goes
+ * to x, y, z [f w h + v w + u] (device).  Feeding the n_frames w h points to
+ * gmapp_voxel_downsample gives the fused voxel-centre cloud. */
+gmapp_status gmapp_depth_to_points_batch(gmapp_ctx *ctx, const float *depth, int32_t n_frames, int32_t w, int32_t h,
+                                         const float K[4], const float *T_wc, float *x, float *y, float *z,
+                                         void *stream);
+
 /* Uniform voxel lattice of the sphere world (Sec. IV-B; voxel size 2 r_O in
  * Sec. V-A, voxel-centre clouds): the cell of a point is floor((p - lo) / voxel)
  * per axis (FP32); points outside the box lo + [0, dims * voxel) or non-finite are

@@ -282,6 +282,25 @@ gmapp_status gmapp_depth_to_points(gmapp_ctx *ctx, const float *depth, int32_t w
     return gm::launch_depth_to_points(ctx, depth, w, h, K, T, x, y, z, static_cast<hipStream_t>(stream));
 }
 
+gmapp_status gmapp_depth_to_points_batch(gmapp_ctx *ctx, const float *depth, int32_t n_frames, int32_t w, int32_t h,
+                                         const float K[4], const float *T_wc, float *x, float *y, float *z,
+                                         void *stream)
+{
+    gmapp_status st = check_ctx(ctx);
+    if (st) return st;
+    if (w < 0 || h < 0 || n_frames < 0) return fail(ctx, GMAPP_EINVAL, "image size and frame count must be >= 0");
+    if ((long long)w * h * n_frames > (1ll << 40)) return fail(ctx, GMAPP_ECAPACITY, "more than 2^40 pixels");
+    if ((long long)w * h > (long long)INT32_MAX) return fail(ctx, GMAPP_ECAPACITY, "image exceeds 2^31 - 1 pixels");
+    if (!K) return fail(ctx, GMAPP_EINVAL, "K must be non-NULL");
+    for (int i = 0; i < 4; ++i)
+        if (!finite(K[i])) return fail(ctx, GMAPP_EINVAL, "intrinsics must be finite");
+    if (K[0] == 0.f || K[1] == 0.f) return fail(ctx, GMAPP_EINVAL, "focal lengths must be non-zero");
+    if ((long long)w * h * n_frames > 0 && (!depth || !T_wc || !x || !y || !z))
+        return fail(ctx, GMAPP_EINVAL, "depth, poses and output pointers must be non-NULL");
+    return gm::launch_depth_to_points_batch(ctx, depth, n_frames, w, h, K, T_wc, x, y, z,
+                                            static_cast<hipStream_t>(stream));
+}
+
 gmapp_status gmapp_voxel_downsample(gmapp_ctx *ctx, const float *x, const float *y, const float *z, int64_t n,
                                     float voxel, const float lo[3], const int32_t dims[3], int32_t min_count,
                                     float *ox, float *oy, float *oz, int64_t capacity, int64_t *n_out_dev,

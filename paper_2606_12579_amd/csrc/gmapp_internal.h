@@ -197,6 +197,9 @@ gmapp_status launch_adjoint(gmapp_ctx *ctx, const Scn &sc, const Agt &ag, const 
 // perception (perception.hip)
 gmapp_status launch_depth_to_points(gmapp_ctx *ctx, const float *depth, int w, int h, const float K[4],
                                     const Mat34 &T, float *x, float *y, float *z, hipStream_t stream);
+gmapp_status launch_depth_to_points_batch(gmapp_ctx *ctx, const float *depth, int n_frames, int w, int h,
+                                          const float K[4], const float *T_dev, float *x, float *y, float *z,
+                                          hipStream_t stream);
 size_t voxel_workspace_bytes(long long cells);
 gmapp_status launch_voxel_downsample(gmapp_ctx *ctx, const float *x, const float *y, const float *z, long long n,
                                      const VoxGrid &g, unsigned min_count, float *ox, float *oy, float *oz,

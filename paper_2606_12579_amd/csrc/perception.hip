@@ -13,7 +13,9 @@
 // z) without any sort, and the count of occupied cells stays on the device.
 #include "gmapp_internal.h"
 
+#include <algorithm>
 #include <cmath>
+#include <cstdint>
 
 namespace gm {
 namespace {
@@ -40,6 +42,67 @@ __global__ void k_depth_to_points(const float *__restrict__ depth, int w, int h,
         x[i] = X;
         y[i] = Y;
         z[i] = Z;
+    }
+}
+
+// Many frames of one camera, each with its own pose (device [n_frames][12]); four
+// consecutive pixels per thread (w * h divisible by 4, 16-byte aligned arrays),
+// so that the depth read and the three coordinate writes are 16-byte accesses.
+__global__ void k_depth_to_points_v4(const float4 *__restrict__ depth, long long n4, int w, int wh, float fx, float fy,
+                                     float cx, float cy, const float *__restrict__ T, float4 *__restrict__ x,
+                                     float4 *__restrict__ y, float4 *__restrict__ z)
+{
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n4; i += (long long)gridDim.x * blockDim.x) {
+        const long long p = 4 * i;
+        const int f = (int)(p / wh);
+        const int q = (int)(p - (long long)f * wh);
+        const float *t = T + 12 * (size_t)f;
+        const float4 d4 = depth[i];
+        const float dd[4] = {d4.x, d4.y, d4.z, d4.w};
+        float ox[4], oy[4], oz[4];
+        int v = q / w, u = q - v * w;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const float d = dd[k];
+            float X = NAN, Y = NAN, Z = NAN;
+            if (d > 0.0f && d < INFINITY) {
+                const float xc = ((float)u - cx) * d / fx;
+                const float yc = ((float)v - cy) * d / fy;
+                X = fmaf(t[0], xc, fmaf(t[1], yc, fmaf(t[2], d, t[3])));
+                Y = fmaf(t[4], xc, fmaf(t[5], yc, fmaf(t[6], d, t[7])));
+                Z = fmaf(t[8], xc, fmaf(t[9], yc, fmaf(t[10], d, t[11])));
+            }
+            ox[k] = X; oy[k] = Y; oz[k] = Z;
+            if (++u == w) { u = 0; ++v; }
+        }
+        x[i] = make_float4(ox[0], ox[1], ox[2], ox[3]);
+        y[i] = make_float4(oy[0], oy[1], oy[2], oy[3]);
+        z[i] = make_float4(oz[0], oz[1], oz[2], oz[3]);
+    }
+}
+
+// Any shape: one pixel per thread.
+__global__ void k_depth_to_points_n(const float *__restrict__ depth, long long n, int w, int wh, float fx, float fy,
+                                    float cx, float cy, const float *__restrict__ T, float *__restrict__ x,
+                                    float *__restrict__ y, float *__restrict__ z)
+{
+    for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < n; p += (long long)gridDim.x * blockDim.x) {
+        const int f = (int)(p / wh);
+        const int q = (int)(p - (long long)f * wh);
+        const int v = q / w, u = q - v * w;
+        const float *t = T + 12 * (size_t)f;
+        const float d = depth[p];
+        float X = NAN, Y = NAN, Z = NAN;
+        if (d > 0.0f && d < INFINITY) {
+            const float xc = ((float)u - cx) * d / fx;
+            const float yc = ((float)v - cy) * d / fy;
+            X = fmaf(t[0], xc, fmaf(t[1], yc, fmaf(t[2], d, t[3])));
+            Y = fmaf(t[4], xc, fmaf(t[5], yc, fmaf(t[6], d, t[7])));
+            Z = fmaf(t[8], xc, fmaf(t[9], yc, fmaf(t[10], d, t[11])));
+        }
+        x[p] = X;
+        y[p] = Y;
+        z[p] = Z;
     }
 }
 
@@ -186,6 +249,28 @@ gmapp_status launch_depth_to_points(gmapp_ctx *ctx, const float *depth, int w, i
     const int blocks = (int)std::min<long long>((n + 255) / 256, 4096);
     hipLaunchKernelGGL(k_depth_to_points, dim3(blocks), dim3(256), 0, stream, depth, w, h, K[0], K[1], K[2], K[3], T,
                        x, y, z);
+    GM_HIP(ctx, hipGetLastError());
+    return GMAPP_OK;
+}
+
+gmapp_status launch_depth_to_points_batch(gmapp_ctx *ctx, const float *depth, int n_frames, int w, int h,
+                                          const float K[4], const float *T_dev, float *x, float *y, float *z,
+                                          hipStream_t stream)
+{
+    const long long wh = (long long)w * h, n = wh * n_frames;
+    if (n == 0) return GMAPP_OK;
+    auto aligned = [](const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; };
+    if (wh % 4 == 0 && aligned(depth) && aligned(x) && aligned(y) && aligned(z)) {
+        const long long n4 = n / 4;
+        const int blocks = (int)std::min<long long>((n4 + 255) / 256, 16384);
+        hipLaunchKernelGGL(k_depth_to_points_v4, dim3(blocks), dim3(256), 0, stream,
+                           reinterpret_cast<const float4 *>(depth), n4, w, (int)wh, K[0], K[1], K[2], K[3], T_dev,
+                           reinterpret_cast<float4 *>(x), reinterpret_cast<float4 *>(y), reinterpret_cast<float4 *>(z));
+    } else {
+        const int blocks = (int)std::min<long long>((n + 255) / 256, 16384);
+        hipLaunchKernelGGL(k_depth_to_points_n, dim3(blocks), dim3(256), 0, stream, depth, n, w, (int)wh, K[0], K[1],
+                           K[2], K[3], T_dev, x, y, z);
+    }
     GM_HIP(ctx, hipGetLastError());
     return GMAPP_OK;
 }

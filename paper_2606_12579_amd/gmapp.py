@@ -146,6 +146,8 @@ def load_library(path: str = LIB_PATH):
         "gmapp_voxel_downsample": (ctypes.c_int32, [vp, vp, vp, vp, ctypes.c_int64, ctypes.c_float, P(ctypes.c_float),
                                                     P(ctypes.c_int32), ctypes.c_int32, vp, vp, vp, ctypes.c_int64, vp,
                                                     vp]),
+        "gmapp_depth_to_points_batch": (ctypes.c_int32, [vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                                         P(ctypes.c_float), vp, vp, vp, vp, vp]),
         "gmapp_get_tiling": (ctypes.c_int32, [vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                               ctypes.c_int32, P(Tiling)]),
         "gmapp_rollout_batch": (ctypes.c_int32, [vp, P(Job), ctypes.c_int32, vp]),
@@ -592,6 +594,26 @@ class Context:
         Tc = (ctypes.c_float * 12)(*[float(v) for v in np.asarray(T_wc, np.float32).reshape(12)])
         st = self.lib.gmapp_depth_to_points(self.handle, _ptr(depth), int(w), int(h), Kc, Tc, _ptr(out[0]),
                                             _ptr(out[1]), _ptr(out[2]), self._stream(stream))
+        self._raise(st)
+        return out
+
+    def depth_to_points_batch(self, depth, K, T_wc, out=None, stream=None):
+        """gmapp_depth_to_points_batch: depth [B, h, w] and poses T_wc [B, 3, 4] (device float32)
+        -> x, y, z [B*h*w]."""
+        import torch
+        if depth.dim() != 3:
+            raise ValueError("depth must be [frames, h, w]")
+        b, h, w = depth.shape
+        n = b * h * w
+        _check_tensor(depth, "depth", n, torch.float32, self.device)
+        _check_tensor(T_wc, "T_wc", 12 * b, torch.float32, self.device)
+        if out is None:
+            out = tuple(torch.empty(n, dtype=torch.float32, device=self.device) for _ in range(3))
+        for i, t in enumerate(out):
+            _check_tensor(t, f"out[{i}]", n, torch.float32, self.device)
+        Kc = (ctypes.c_float * 4)(*[float(v) for v in np.asarray(K, np.float32).reshape(4)])
+        st = self.lib.gmapp_depth_to_points_batch(self.handle, _ptr(depth), int(b), int(w), int(h), Kc, _ptr(T_wc),
+                                                  _ptr(out[0]), _ptr(out[1]), _ptr(out[2]), self._stream(stream))
         self._raise(st)
         return out
 

@@ -276,6 +276,22 @@ def config3_agents(seed: int = 2, n_agents: int = 256, n_steps: int = 1000):
     return default_agents(rng, n_agents), _query((-0.5, 0.0, 0.35), (0.5, 0.0, 0.35)), Params(n_steps=n_steps)
 
 
+def config3_poses(n: int, seed: int = 5, shift: float = 0.05, yaw: float = 0.05) -> np.ndarray:
+    """n camera-to-world poses [n, 3, 4] around the config-3 camera (1 m above the
+    plane, looking down): yaw about the vertical by U[-yaw, yaw] rad and a horizontal
+    shift by U[-shift, shift] m per axis; the first pose is the config-3 pose."""
+    rng = np.random.default_rng(seed)
+    base = np.diag([1.0, -1.0, -1.0])
+    out = np.zeros((n, 3, 4))
+    for i in range(n):
+        a = 0.0 if i == 0 else rng.uniform(-yaw, yaw)
+        t = np.zeros(2) if i == 0 else rng.uniform(-shift, shift, 2)
+        Rz = np.array([[math.cos(a), -math.sin(a), 0.0], [math.sin(a), math.cos(a), 0.0], [0.0, 0.0, 1.0]])
+        out[i, :, :3] = Rz @ base
+        out[i, :, 3] = [t[0], t[1], 1.0]
+    return out.astype(F32)
+
+
 def config4(seed: int = 3, n_points: int = 20_000, n_agents: int = 128, n_steps: int = 400) -> Problem:
     rng = np.random.default_rng(seed)
     objs = [(rng.uniform(0.3, 0.7, 3), rng.uniform(0.05, 0.15)) for _ in range(5)]

@@ -262,3 +262,42 @@ def test_batch_validation(ctx, mix_refs):
     with pytest.raises(gmapp.GmappError) as ei:
         ctx.rollout_batch(_jobs(ctx, [many]))
     assert ei.value.status == gmapp.ECAPACITY
+
+
+def _perturbed(pb, i, k):
+    """Agent i of pb with its rotation vector moved by k FP32 ulps in each component."""
+    sub = copy.deepcopy(pb)
+    sub.agents = pb.agents.subset([i])
+    w = sub.agents.omega.astype(np.float32)
+    sub.agents.omega = np.nextafter(w, np.float32(np.inf) if k > 0 else np.float32(-np.inf)).astype(np.float32) \
+        if k else w
+    return sub
+
+
+def test_config5_ill_conditioned_agent(ctx):
+    """An agent that runs into an obstacle (clamped distance rho = eps) is
+    ill-conditioned: moving its rotation vector by one FP32 ulp moves the exact
+    (FP64) trajectory by more than the 1e-4 m tolerance. Such an agent is checked
+    against that FP64 envelope instead: the GPU trajectory must stay within a few
+    envelopes of the nominal oracle trajectory, and its divergence from the oracle
+    must start only after the agent has reached the clamp."""
+    pb = scenes.config5(n_scenes=4)[3].problem              # N_O = 160,579, N_a = 256, N_k = 885
+    agent = 102
+    jobs = _jobs(ctx, [pb])
+    ctx.clear_batch_tuning()
+    ctx.rollout_batch(jobs)
+    gpu = _host(jobs[0])
+    nom = oracle.rollout(_perturbed(pb, agent, 0))
+    env = 0.0
+    for k in (1, -1):
+        env = max(env, float(np.abs(oracle.rollout(_perturbed(pb, agent, k)).traj - nom.traj).max()))
+    err_k = np.abs(gpu["traj"][agent].astype(np.float64) - nom.traj[0]).max(1)
+    err = float(err_k.max())
+    first_div = int(np.argmax(err_k > 1e-5)) if (err_k > 1e-5).any() else -1
+    clamp_k = np.nonzero(nom.min_clear[0] <= float(np.float32(pb.params.eps)) * 1.0001)[0]
+    first_clamp = int(clamp_k[0]) + 1 if clamp_k.size else -1
+    _log(f"ill-conditioned agent: envelope {env:.2e} m, GPU error {err:.2e} m, first step off by > 1e-5: "
+         f"{first_div}, first clamped step: {first_clamp}")
+    assert env > 1e-4, "the agent is expected to be ill-conditioned"
+    assert first_clamp > 0 and (first_div < 0 or first_div >= first_clamp)
+    assert err <= max(1e-4, 10 * env)

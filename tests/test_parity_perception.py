@@ -43,6 +43,46 @@ def test_depth_to_points(ctx):
     assert (err <= 4e-7 * np.abs(ref[ok]) + 2e-7).all(), err.max()
 
 
+def test_depth_to_points_batch(ctx):
+    """Several frames with their own poses in one launch, against the oracle's
+    back-projection of each frame: the vectorised path (w h divisible by 4) and the
+    one-pixel-per-thread path (a ragged 7 x 5 image)."""
+    import torch
+    fr = scenes.config3_frame()
+    T = scenes.config3_poses(3)
+    for depth in (np.stack([fr.depth, fr.depth * np.float32(1.01), fr.depth]),
+                  np.stack([fr.depth[:5, :7], fr.depth[10:15, 20:27], fr.depth[30:35, 40:47]])):
+        depth = np.ascontiguousarray(depth)
+        depth[1, 0, :5] = [0.0, -1.0, np.nan, np.inf, 0.7]                # invalid pixels
+        ref = np.concatenate([op.back_project(depth[f], fr.K, T[f]) for f in range(3)])
+        x, y, z = ctx.depth_to_points_batch(torch.as_tensor(depth, device="cuda"), fr.K,
+                                            torch.as_tensor(T, device="cuda"))
+        torch.cuda.synchronize()
+        got = np.stack([x.cpu().numpy(), y.cpu().numpy(), z.cpu().numpy()], 1).astype(np.float64)
+        assert np.array_equal(np.isnan(got), np.isnan(ref))
+        ok = ~np.isnan(ref[:, 0])
+        err = np.abs(got[ok] - ref[ok])
+        assert (err <= 4e-7 * np.abs(ref[ok]) + 2e-7).all(), err.max()
+
+
+def test_fused_voxels_multiview(ctx):
+    """The voxel pass over the points of 4 frames (multi-view fusion) gives exactly
+    the oracle's occupied cells of the concatenated FP32 points."""
+    import torch
+    fr = scenes.config3_frame()
+    T = scenes.config3_poses(4)
+    P = np.concatenate([op.back_project(fr.depth, fr.K, T[f]) for f in range(4)]).astype(np.float32)
+    cells = op.voxel_cells(P[:, 0], P[:, 1], P[:, 2], fr.voxel, fr.box_lo, fr.dims, 2)
+    C = op.voxel_centres(cells, fr.voxel, fr.box_lo, fr.dims).astype(np.float32)
+    t = [torch.as_tensor(np.ascontiguousarray(P[:, a]), device="cuda") for a in range(3)]
+    ox, oy, oz, n = ctx.voxel_downsample(*t, fr.voxel, fr.box_lo, fr.dims, min_count=2, capacity=65536)
+    torch.cuda.synchronize()
+    n = int(n.item())
+    assert n == len(cells)
+    G = np.stack([ox[:n].cpu().numpy(), oy[:n].cpu().numpy(), oz[:n].cpu().numpy()], 1)
+    assert np.array_equal(G, C)
+
+
 def test_voxel_exact_on_oracle_points(ctx):
     """Same FP32 points on both sides: identical occupied cells, centres = FP32 rounding of the exact centres."""
     import torch

@@ -5,8 +5,12 @@
 //   2. for each checkpoint segment, last to first: recompute the segment's steps
 //      from its checkpoint, keeping (p^(k), v^(k-1), F^(k)) per step in LDS, then
 //      sweep the steps backwards carrying the adjoints of p and v.
-// Agent groups span the workgroup (AW agents, 64 W / AW lanes each); the points
-// are not sharded, so every reduction stays inside the workgroup.
+// Agent groups span the workgroup (AW agents, 64 W / AW lanes each).  When there
+// are fewer groups than CUs, the points are split over S shards (workgroups of one
+// cooperative launch, placed on one XCD): every per-step reduction is then
+// completed by a tagged exchange through the context arena (as in the forward
+// kernel), and all shards add the partials in shard order, so they carry
+// bit-identical agent states and adjoints.
 //
 // Reverse step k (adjoints lp = dL/dp^(k+1), lv = dL/dv^(k)):
 //   lv' = lv + dt lp;  lF = (dt / 2m) lv' + (jerk term of Eq. 20 on F^(k))
@@ -36,13 +40,16 @@ struct AdjLay {
 };
 
 struct AdjPlan {
-    size_t cx, cy, cz, runs, rvel, red, ckpt, tape, total;
+    size_t cx, cy, cz, runs, rvel, red, xt, ckpt, tape, total;
 };
+
+constexpr int kAdjWords = 16;   // exchange words per agent and shard: up to 3 sums + the nearest sphere
 
 // ckpt: [n_ckpt][AW][5] float4 (p, cp, v, cv, F1 | F2 packed as 5 x float4 of 18 floats)
 // tape: [C][AW][3] float4 (p^(k), v^(k-1), F^(k))
 // red : [2][W][AW][4] float4
-__host__ __device__ inline AdjPlan adj_plan(const AdjLay &l, int W, int AW)
+// xt  : [S][AW][4] float4 gathered shard partials (S > 1)
+__host__ __device__ inline AdjPlan adj_plan(const AdjLay &l, int W, int AW, int S)
 {
     AdjPlan p;
     const size_t plane = ((size_t)l.cap * 4 + 15) / 16 * 16;
@@ -50,7 +57,8 @@ __host__ __device__ inline AdjPlan adj_plan(const AdjLay &l, int W, int AW)
     p.runs = 3 * plane;
     p.rvel = p.runs + (size_t)l.runs_cap * 16;
     p.red = p.rvel + (size_t)l.runs_cap * 16;
-    p.ckpt = p.red + (size_t)2 * W * AW * 4 * 16;
+    p.xt = p.red + (size_t)2 * W * AW * 4 * 16;
+    p.ckpt = p.xt + (S > 1 ? (size_t)S * AW * 4 * 16 : 0);
     p.tape = p.ckpt + (size_t)l.n_ckpt * AW * 5 * 16;
     p.total = p.tape + (size_t)l.C * AW * 3 * 16;
     return p;
@@ -142,12 +150,13 @@ __device__ __forceinline__ void interact_rev(float qx, float qy, float qz, float
 }
 
 template <int AW, int W, int CUT>
-__global__ __launch_bounds__(64 * W) void k_adjoint(Scn sc, Agt ag, Prm pr, AdjOut io, AdjLay lay)
+__global__ __launch_bounds__(64 * W) void k_adjoint(Scn sc, Agt ag, Prm pr, AdjOut io, AdjLay lay, Xch xc)
 {
     constexpr int NT = 64 * W;
     constexpr int L = NT / AW;
     extern __shared__ float4 lds4[];
-    const AdjPlan lp = adj_plan(lay, W, AW);
+    const int S = xc.S, G = xc.G;
+    const AdjPlan lp = adj_plan(lay, W, AW, S);
     char *lds = reinterpret_cast<char *>(lds4);
     float *lx = reinterpret_cast<float *>(lds + lp.cx);
     float *ly = reinterpret_cast<float *>(lds + lp.cy);
@@ -155,15 +164,30 @@ __global__ __launch_bounds__(64 * W) void k_adjoint(Scn sc, Agt ag, Prm pr, AdjO
     int4 *runs = reinterpret_cast<int4 *>(lds + lp.runs);
     float4 *rvel = reinterpret_cast<float4 *>(lds + lp.rvel);
     float4 *red = reinterpret_cast<float4 *>(lds + lp.red);
+    float4 *xt = reinterpret_cast<float4 *>(lds + lp.xt);
     float4 *ckpt = reinterpret_cast<float4 *>(lds + lp.ckpt);
     float4 *tape = reinterpret_cast<float4 *>(lds + lp.tape);
-    __shared__ int s_nruns, s_split;
+    __shared__ int s_nruns, s_split, s_last;
+
+    // workgroup -> (group g, shard s); the S shards of a group share an XCD
+    int g, s;
+    if (S > 1) {
+        const int nwg = gridDim.x;                // multiple of 8
+        const int lin = (blockIdx.x & 7) * (nwg >> 3) + (blockIdx.x >> 3);
+        g = lin / S;
+        s = lin % S;
+    } else {
+        g = blockIdx.x;
+        s = 0;
+    }
+    if (g >= G) return;                           // padding workgroup (not counted in `done`)
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int a_w = tid % AW;
     const int slice = tid / AW;
-    const bool writer = slice == 0;               // tid < AW, in wave 0
-    const int agent = blockIdx.x * AW + a_w;
+    const bool lead = slice == 0;                 // tid < AW, in wave 0: the agent's lane for tape and checkpoints
+    const bool writer = lead && s == 0;
+    const int agent = g * AW + a_w;
     const bool valid = agent < ag.n;
     const int ai = valid ? agent : 0;
     Agent P;
@@ -180,16 +204,18 @@ __global__ __launch_bounds__(64 * W) void k_adjoint(Scn sc, Agt ag, Prm pr, AdjO
 
     long long n_pts = sc.n_cap;
     if (sc.n_dev) n_pts = min(max(*sc.n_dev, 0ll), sc.n_cap);
-    const long long n_shard = n_pts;
+    const long long sb = n_pts * s / S, se = n_pts * (s + 1) / S;
+    const long long n_shard = se - sb;
+    const float *gx_ = sc.x + sb, *gy_ = sc.y + sb, *gz_ = sc.z + sb;   // this shard's points
     if (tid == 0) {
         int split = 0;
-        s_nruns = build_runs(sc, n_pts, 0, n_pts, runs, rvel, lay.runs_cap, L, split);
+        s_nruns = build_runs(sc, n_pts, sb, se, runs, rvel, lay.runs_cap, L, split);
         s_split = split;
     }
     const bool resident = lay.resident && n_shard <= (long long)lay.cap;
     if (resident)
         for (int i = tid; i < (int)n_shard; i += NT) {
-            lx[i] = sc.x[i]; ly[i] = sc.y[i]; lz[i] = sc.z[i];
+            lx[i] = gx_[i]; ly[i] = gy_[i]; lz[i] = gz_[i];
         }
     __syncthreads();
     const int n_runs = s_nruns;
@@ -202,6 +228,8 @@ __global__ __launch_bounds__(64 * W) void k_adjoint(Scn sc, Agt ag, Prm pr, AdjO
     const float gx = pr.goal[0], gy = pr.goal[1], gz = pr.goal[2];
     const int N = pr.n_steps, C = lay.C;
     int par = 0;
+    unsigned ev = 0;                              // exchange tag: one per reduction, the same sequence in all shards
+    const unsigned long long t_start = __builtin_amdgcn_s_memrealtime();
 
     // workgroup reduction: sum of up to 3 float4 and the nearest sphere (m2, d)
     auto wg_reduce = [&](float4 *v, int nsum, float &m2, float &mx, float &my, float &mz) {
@@ -227,6 +255,65 @@ __global__ __launch_bounds__(64 * W) void k_adjoint(Scn sc, Agt ag, Prm pr, AdjO
             }
             const float4 q = rb[(r * AW + a_w) * 4 + 3];
             if (nearer(q.x, q.y, q.z, q.w, m.x, m.y, m.z, m.w)) m = q;
+        }
+        if (S > 1) {                              // complete the reduction over the shards
+            const unsigned tag = ++ev;
+            if (wave == 0) {
+                if (lane < AW) {
+                    unsigned long long *slot =
+                        xc.partial + (((size_t)((tag & 1) * G + g) * S + s) * AW + lane) * kAdjWords;
+                    for (int i = 0; i < nsum; ++i) {
+                        st64_agent(slot + 4 * i, xword(v[i].x, tag));
+                        st64_agent(slot + 4 * i + 1, xword(v[i].y, tag));
+                        st64_agent(slot + 4 * i + 2, xword(v[i].z, tag));
+                        st64_agent(slot + 4 * i + 3, xword(v[i].w, tag));
+                    }
+                    st64_agent(slot + 4 * nsum, xword(m.x, tag));
+                    st64_agent(slot + 4 * nsum + 1, xword(m.y, tag));
+                    st64_agent(slot + 4 * nsum + 2, xword(m.z, tag));
+                    st64_agent(slot + 4 * nsum + 3, xword(m.w, tag));
+                }
+                const int nw = 4 * (nsum + 1);
+                for (int l = lane; l < S * AW; l += 64) {
+                    const unsigned long long *slot =
+                        xc.partial + (((size_t)((tag & 1) * G + g) * S + l / AW) * AW + l % AW) * kAdjWords;
+                    unsigned long long q[kAdjWords];
+                    unsigned spins = 0;
+                    while (true) {
+                        q[nw - 1] = ld64_agent(slot + nw - 1);
+                        if (xtag(q[nw - 1]) == tag) {
+                            bool all = true;
+                            for (int i = 0; i < nw - 1; ++i) {
+                                q[i] = ld64_agent(slot + i);
+                                all = all && xtag(q[i]) == tag;
+                            }
+                            if (all) break;
+                        }
+                        __builtin_amdgcn_s_sleep(2);
+                        if ((++spins & 63u) == 0) {
+                            if (ld_agent(xc.status) != 0u) break;
+                            if (__builtin_amdgcn_s_memrealtime() - t_start > kWatchdogTicks) {
+                                st_agent(xc.status, 1u);
+                                break;
+                            }
+                        }
+                    }
+                    for (int i = 0; i < nsum + 1; ++i)
+                        xt[l * 4 + i] = make_float4(xval(q[4 * i]), xval(q[4 * i + 1]), xval(q[4 * i + 2]),
+                                                    xval(q[4 * i + 3]));
+                }
+            }
+            __syncthreads();
+            for (int i = 0; i < nsum; ++i) v[i] = xt[a_w * 4 + i];      // shard 0, then the others in order
+            m = xt[a_w * 4 + nsum];
+            for (int r = 1; r < S; ++r) {
+                for (int i = 0; i < nsum; ++i) {
+                    const float4 q = xt[(r * AW + a_w) * 4 + i];
+                    v[i].x += q.x; v[i].y += q.y; v[i].z += q.z; v[i].w += q.w;
+                }
+                const float4 q = xt[(r * AW + a_w) * 4 + nsum];
+                if (nearer(q.x, q.y, q.z, q.w, m.x, m.y, m.z, m.w)) m = q;
+            }
         }
         m2 = m.x; mx = m.y; my = m.z; mz = m.w;
         par ^= 1;
@@ -257,7 +344,7 @@ __global__ __launch_bounds__(64 * W) void k_adjoint(Scn sc, Agt ag, Prm pr, AdjO
                 if (!resident) {
                     __syncthreads();
                     for (int i = tid; i < tn; i += NT) {
-                        lx[i] = sc.x[tb + i]; ly[i] = sc.y[tb + i]; lz[i] = sc.z[tb + i];
+                        lx[i] = gx_[tb + i]; ly[i] = gy_[tb + i]; lz[i] = gz_[tb + i];
                     }
                     __syncthreads();
                 }
@@ -310,7 +397,7 @@ __global__ __launch_bounds__(64 * W) void k_adjoint(Scn sc, Agt ag, Prm pr, AdjO
         kahan_add(pz, cpz, pr.dt * vz);
     };
     for (int k = 1; k <= N; ++k) {
-        if ((k - 1) % C == 0 && writer) {
+        if ((k - 1) % C == 0 && lead) {
             float4 *c5 = ckpt + ((size_t)((k - 1) / C) * AW + a_w) * 5;
             c5[0] = make_float4(px, py, pz, cpx);
             c5[1] = make_float4(cpy, cpz, vx, vy);
@@ -349,12 +436,12 @@ __global__ __launch_bounds__(64 * W) void k_adjoint(Scn sc, Agt ag, Prm pr, AdjO
         const float Fbx = F1x, Fby = F1y, Fbz = F1z;   // F^(k0 - 1)
         for (int k = k0; k <= k1; ++k) {
             float4 *tp = tape + ((size_t)(k - k0) * AW + a_w) * 3;
-            if (writer) {
+            if (lead) {
                 tp[0] = make_float4(px, py, pz, 0.f);
                 tp[1] = make_float4(vx, vy, vz, 0.f);
             }
             step(k, false);
-            if (writer) tp[2] = make_float4(F1x, F1y, F1z, 0.f);
+            if (lead) tp[2] = make_float4(F1x, F1y, F1z, 0.f);
         }
         __syncthreads();
         for (int k = k1; k >= k0; --k) {
@@ -471,16 +558,34 @@ __global__ __launch_bounds__(64 * W) void k_adjoint(Scn sc, Agt ag, Prm pr, AdjO
         __syncthreads();                           // the tape is rewritten by the next segment
     }
     if (writer && valid) {
-        io.g_ka[agent] = gka;
-        io.g_da[agent] = gda;
-        io.g_kf[agent] = gkf;
-        io.g_om[3 * agent] = gox;
-        io.g_om[3 * agent + 1] = goy;
-        io.g_om[3 * agent + 2] = goz;
+        const bool bad = S > 1 && ld_agent(xc.status) != 0u;   // the watchdog cut an exchange short
+        io.g_ka[agent] = bad ? NAN : gka;
+        io.g_da[agent] = bad ? NAN : gda;
+        io.g_kf[agent] = bad ? NAN : gkf;
+        io.g_om[3 * agent] = bad ? NAN : gox;
+        io.g_om[3 * agent + 1] = bad ? NAN : goy;
+        io.g_om[3 * agent + 2] = bad ? NAN : goz;
+    }
+    if (S > 1) {                                  // the last workgroup clears the exchange area
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __syncthreads();
+        if (tid == 0) {
+            const unsigned prev = __hip_atomic_fetch_add(xc.done, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            s_last = (prev == (unsigned)(G * S - 1)) ? 1 : 0;
+        }
+        __syncthreads();
+        if (!s_last) return;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        const size_t words = (size_t)2 * G * S * AW * kAdjWords;
+        for (size_t i = tid; i < words; i += NT) st64_agent(xc.partial + i, 0ull);
+        if (tid == 0) {
+            st_agent(xc.status, 0u);
+            st_agent(xc.done, 0u);
+        }
     }
 }
 
-using AFn = void (*)(Scn, Agt, Prm, AdjOut, AdjLay);
+using AFn = void (*)(Scn, Agt, Prm, AdjOut, AdjLay, Xch);
 
 template <int AW, int W>
 AFn pick_adj_cut(int cut)
@@ -510,30 +615,66 @@ gmapp_status launch_adjoint(gmapp_ctx *ctx, const Scn &sc, const Agt &ag, const 
 {
     if (ag.n == 0) return GMAPP_OK;
     const int cus = ctx->n_cu > 0 ? ctx->n_cu : 256;
-    int AW = 1, W = 8;
-    while (AW < 4 && (ag.n + AW - 1) / AW > 2 * cus) AW *= 2;
-    AdjLay lay;
-    lay.runs_cap = 2 * sc.n_seg + 2;
-    lay.C = ckpt_every;
-    lay.n_ckpt = (pr.n_steps + ckpt_every - 1) / ckpt_every;
-    lay.resident = 1;
-    lay.cap = (int)std::max<long long>(sc.n_cap, 1);
+    constexpr int W = 8;
     constexpr size_t budget = 160 * 1024;
-    if (adj_plan(lay, W, AW).total > budget) {
-        lay.resident = 0;
-        lay.cap = 2048;
+    int AW = 1;
+    while (AW < 4 && (ag.n + AW - 1) / AW > 2 * cus) AW *= 2;
+    const int G = (ag.n + AW - 1) / AW;
+    AFn fn = pick_adjoint(AW, W, pr.cutoff);
+    AdjOut io{grad_total, g_ka, g_da, g_kf, g_om};
+    // layout for S shards: each shard resident in LDS when it fits, else streamed tiles
+    auto layout = [&](int S) {
+        AdjLay l;
+        l.runs_cap = 2 * sc.n_seg + 2;
+        l.C = ckpt_every;
+        l.n_ckpt = (pr.n_steps + ckpt_every - 1) / ckpt_every;
+        l.resident = 1;
+        l.cap = (int)std::max<long long>((sc.n_cap + S - 1) / S, 1);
+        if (adj_plan(l, W, AW, S).total > budget) {
+            l.resident = 0;
+            l.cap = 2048;
+        }
+        return l;
+    };
+    // shards: fill the chip when there are fewer groups than CUs, within co-residency
+    int S = 1;
+    while (S < 8 && (long long)G * S * 2 <= cus && sc.n_cap / (S * 2) >= 256) S *= 2;
+    for (; S > 1; S /= 2) {
+        const AdjLay l = layout(S);
+        const size_t shm = adj_plan(l, W, AW, S).total;
+        if (shm > budget) continue;
+        GM_HIP(ctx, hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+        int per_cu = 0;
+        GM_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(fn), 64 * W,
+                                                                 shm));
+        const long long nwg = ((long long)G * S + 7) / 8 * 8;
+        const size_t xbytes = (size_t)2 * G * S * AW * kAdjWords * sizeof(unsigned long long);
+        if ((long long)per_cu * cus >= nwg && xbytes <= kXchgBytes) break;
     }
-    if (adj_plan(lay, W, AW).total > budget)
+    const AdjLay lay = layout(S);
+    if (adj_plan(lay, W, AW, S).total > budget)
         return fail(ctx, GMAPP_ECAPACITY, "checkpoints of %d steps x %d segments exceed LDS; raise ckpt_every",
                     ckpt_every, lay.n_ckpt);
-    AFn fn = pick_adjoint(AW, W, pr.cutoff);
-    const size_t shm = adj_plan(lay, W, AW).total;
-    AdjOut io{grad_total, g_ka, g_da, g_kf, g_om};
-    const int G = (ag.n + AW - 1) / AW;
-    void *args[] = {(void *)&sc, (void *)&ag, (void *)&pr, (void *)&io, (void *)&lay};
+    const size_t shm = adj_plan(lay, W, AW, S).total;
+    Xch xc;
+    xc.partial = ctx->xchg;
+    xc.flags = ctx->sync;
+    xc.done = ctx->sync + kCounterWords;
+    xc.status = ctx->sync + kCounterWords + 16;
+    xc.S = S;
+    xc.G = G;
+    void *args[] = {(void *)&sc, (void *)&ag, (void *)&pr, (void *)&io, (void *)&lay, (void *)&xc};
     GM_HIP(ctx, hipFuncSetAttribute(reinterpret_cast<const void *>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
                                     (int)shm));
-    GM_HIP(ctx, hipLaunchKernel(reinterpret_cast<const void *>(fn), dim3((unsigned)G), dim3(64 * W), args, shm, stream));
+    if (S > 1) {
+        const long long nwg = ((long long)G * S + 7) / 8 * 8;
+        GM_HIP(ctx, hipLaunchCooperativeKernel(reinterpret_cast<const void *>(fn), dim3((unsigned)nwg), dim3(64 * W),
+                                               args, (unsigned)shm, stream));
+    } else {
+        GM_HIP(ctx, hipLaunchKernel(reinterpret_cast<const void *>(fn), dim3((unsigned)G), dim3(64 * W), args, shm,
+                                    stream));
+    }
     return GMAPP_OK;
 }
 

@@ -49,9 +49,14 @@ def _check(pb, gpu, ref, w, rel=5e-3, label=""):
     assert (err <= bound).all(), (label, worst)
 
 
-@pytest.mark.parametrize("case", ["static", "moving", "ckpt7", "hard_cutoff_far"])
+@pytest.mark.parametrize("case", ["static", "moving", "ckpt7", "hard_cutoff_far", "sharded"])
 def test_adjoint_small(ctx, case):
+    """Small problems against the dual-number oracle; "sharded" has few agents and
+    2,000 moving points, so the points are split over several workgroups that
+    exchange every reduction."""
     pb = scenes.tiny(12, n_points=120, n_agents=6, n_steps=90, cutoff=1, moving=(case == "moving"))
+    if case == "sharded":
+        pb = scenes.tiny(14, n_points=2000, n_agents=8, n_steps=90, cutoff=1, moving=True)
     pb.agents.k_f[:] = 0.02
     ckpt = 7 if case == "ckpt7" else 50
     if case == "hard_cutoff_far":

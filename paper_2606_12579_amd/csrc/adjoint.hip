@@ -279,16 +279,11 @@ __global__ __launch_bounds__(64 * W) void k_adjoint(Scn sc, Agt ag, Prm pr, AdjO
                         xc.partial + (((size_t)((tag & 1) * G + g) * S + l / AW) * AW + l % AW) * kAdjWords;
                     unsigned long long q[kAdjWords];
                     unsigned spins = 0;
-                    while (true) {
-                        q[nw - 1] = ld64_agent(slot + nw - 1);
-                        if (xtag(q[nw - 1]) == tag) {
-                            bool all = true;
-                            for (int i = 0; i < nw - 1; ++i) {
-                                q[i] = ld64_agent(slot + i);
-                                all = all && xtag(q[i]) == tag;
-                            }
-                            if (all) break;
-                        }
+                    while (true) {                   // all words of the slot in flight together
+                        bool all = true;
+                        for (int i = 0; i < nw; ++i) q[i] = ld64_agent(slot + i);
+                        for (int i = 0; i < nw; ++i) all = all && xtag(q[i]) == tag;
+                        if (all) break;
                         __builtin_amdgcn_s_sleep(2);
                         if ((++spins & 63u) == 0) {
                             if (ld_agent(xc.status) != 0u) break;

@@ -35,7 +35,7 @@ namespace {
 
 constexpr int kW = kBatchWaves;
 
-// dynamic LDS: x | y | z [cap] · red float4 [2][W][8] · runs int4 [runs_cap] · rvel float4 [runs_cap] · sel [64 W] x 8 B
+// dynamic LDS: points [cap][3] (x, y, z interleaved) · red float4 [2][W][8] · runs int4 [runs_cap] · rvel float4 [runs_cap] · sel [64 W] x 8 B
 struct BPlan {
     size_t cx, cy, cz, red, runs, rvel, sel, total;
 };
@@ -54,7 +54,7 @@ __host__ __device__ inline BPlan b_plan(const BatchLay &l)
 }
 
 struct Lds {
-    float *x, *y, *z;
+    float *pt;          // points, interleaved x, y, z per point
     float4 *red;
     int4 *runs;
     float4 *rvel;
@@ -101,7 +101,7 @@ __device__ __forceinline__ void run_item(const BatchJob &jb, int a0, const Lds &
     }
     if (resident)
         for (int i = tid; i < (int)n_pts; i += NT) {
-            m.x[i] = sc.x[i]; m.y[i] = sc.y[i]; m.z[i] = sc.z[i];
+            m.pt[3 * i] = sc.x[i]; m.pt[3 * i + 1] = sc.y[i]; m.pt[3 * i + 2] = sc.z[i];
         }
     __syncthreads();
     const int n_runs = n_runs_sh;
@@ -143,10 +143,11 @@ __device__ __forceinline__ void run_item(const BatchJob &jb, int a0, const Lds &
             if (active) {
                 const float psx = fmaf(-t, my_v.x, px), psy = fmaf(-t, my_v.y, py), psz = fmaf(-t, my_v.z, pz);
                 float Gs = 0, Sx = 0, Sy = 0, Sz = 0;
-                int j = my_j0;
+                const float *q = m.pt + 3 * my_j0;
+                const int step3 = 3 * my_stride;
 #pragma unroll 4
-                for (int i = 0; i < my_n; ++i, j += my_stride)
-                    interact<CUT>(m.x[j], m.y[j], m.z[j], psx, psy, psz, P.wx, P.wy, P.wz, P.R, pr.eps, P.rd, P.tb_a,
+                for (int i = 0; i < my_n; ++i, q += step3)
+                    interact<CUT>(q[0], q[1], q[2], psx, psy, psz, P.wx, P.wy, P.wz, P.R, pr.eps, P.rd, P.tb_a,
                                   P.tb_b, Gs, Sx, Sy, Sz, m2);
                 project_add(vx - my_v.x, vy - my_v.y, vz - my_v.z, P.kf, P.wx, P.wy, P.wz, Gs, Sx, Sy, Sz, Fx, Fy,
                             Fz);
@@ -158,7 +159,7 @@ __device__ __forceinline__ void run_item(const BatchJob &jb, int a0, const Lds &
                 if (!resident) {
                     __syncthreads();
                     for (int i = tid; i < tn; i += NT) {
-                        m.x[i] = sc.x[tb + i]; m.y[i] = sc.y[tb + i]; m.z[i] = sc.z[tb + i];
+                        m.pt[3 * i] = sc.x[tb + i]; m.pt[3 * i + 1] = sc.y[tb + i]; m.pt[3 * i + 2] = sc.z[tb + i];
                     }
                     __syncthreads();
                 }
@@ -171,7 +172,7 @@ __device__ __forceinline__ void run_item(const BatchJob &jb, int a0, const Lds &
                     const float4 ov = m.rvel[r];
                     const float psx = fmaf(-t, ov.x, px), psy = fmaf(-t, ov.y, py), psz = fmaf(-t, ov.z, pz);
                     float Gs = 0, Sx = 0, Sy = 0, Sz = 0;
-                    interact_run<L, CUT>(m.x, m.y, m.z, b - t0r, e - t0r, slice, psx, psy, psz, P.wx, P.wy, P.wz,
+                    interact_run_aos<L, CUT>(m.pt, b - t0r, e - t0r, slice, psx, psy, psz, P.wx, P.wy, P.wz,
                                          P.R, pr.eps, P.rd, P.tb_a, P.tb_b, Gs, Sx, Sy, Sz, m2);
                     project_add(vx - ov.x, vy - ov.y, vz - ov.z, P.kf, P.wx, P.wy, P.wz, Gs, Sx, Sy, Sz, Fx, Fy, Fz);
                 }
@@ -291,9 +292,7 @@ __global__ __launch_bounds__(64 * kW) __attribute__((amdgpu_waves_per_eu(4, 8)))
     const BPlan lp = b_plan(lay);
     char *lds = reinterpret_cast<char *>(lds4);
     Lds m;
-    m.x = reinterpret_cast<float *>(lds + lp.cx);
-    m.y = reinterpret_cast<float *>(lds + lp.cy);
-    m.z = reinterpret_cast<float *>(lds + lp.cz);
+    m.pt = reinterpret_cast<float *>(lds + lp.cx);
     m.red = reinterpret_cast<float4 *>(lds + lp.red);
     m.runs = reinterpret_cast<int4 *>(lds + lp.runs);
     m.rvel = reinterpret_cast<float4 *>(lds + lp.rvel);

@@ -63,6 +63,24 @@ __device__ __forceinline__ void interact_run(const float *__restrict__ lx, const
         interact<CUT>(lx[j], ly[j], lz[j], psx, psy, psz, wx, wy, wz, R, eps, rd, tb_a, tb_b, G, Sx, Sy, Sz, m2);
 }
 
+// The same over an interleaved (x, y, z per point) LDS copy: one address per
+// point, the three coordinates at immediate offsets.
+template <int L, int CUT>
+__device__ __forceinline__ void interact_run_aos(const float *__restrict__ lp, int b, int e, int sl, float psx,
+                                                 float psy, float psz, float wx, float wy, float wz, float R,
+                                                 float eps, float rd, float tb_a, float tb_b, float &G, float &Sx,
+                                                 float &Sy, float &Sz, float &m2)
+{
+    const int n = e - b;
+    const int full = n / L;
+    const float *q = lp + 3 * (b + sl);
+#pragma unroll 4
+    for (int i = 0; i < full; ++i, q += 3 * L)
+        interact<CUT>(q[0], q[1], q[2], psx, psy, psz, wx, wy, wz, R, eps, rd, tb_a, tb_b, G, Sx, Sy, Sz, m2);
+    if (sl < n - full * L)
+        interact<CUT>(q[0], q[1], q[2], psx, psy, psz, wx, wy, wz, R, eps, rd, tb_a, tb_b, G, Sx, Sy, Sz, m2);
+}
+
 __device__ __forceinline__ unsigned ld_agent(const unsigned *p)
 {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

@@ -55,7 +55,8 @@ struct Lay {
 };
 
 // Dynamic LDS layout of k_rollout, in bytes (16-byte aligned pieces):
-//   x | y | z [cap]  ·  red float4 [2][W][AW]  ·  tot float4 [groups][AW]  ·  xt float4 [groups][S*AW]
+//   points [cap][3] (x, y, z interleaved)  ·  red float4 [2][W][AW]  ·  tot float4 [groups][AW]
+//   ·  xt float4 [groups][S*AW]
 //   ·  runs int4 [runs_cap]  ·  rvel float4 [runs_cap]  ·  sel (float, int) [NT]
 struct LdsPlan {
     size_t cx, cy, cz, red, tot, xt, runs, rvel, sel, total;
@@ -65,7 +66,7 @@ __host__ __device__ inline LdsPlan lds_plan(const Lay &l, int W, int WS, int AW,
     LdsPlan p;
     const size_t plane = ((size_t)l.cap * 4 + 15) / 16 * 16;
     const int groups = W / WS;                    // agent groups per workgroup
-    p.cx = 0; p.cy = plane; p.cz = 2 * plane;
+    p.cx = 0; p.cy = plane; p.cz = 2 * plane;   // [cx, cx + 3 plane): the points, interleaved x, y, z
     p.red = 3 * plane;                            // [2][W][AW] wave partials (WS > 1)
     p.tot = p.red + (WS > 1 ? (size_t)2 * W * AW * 16 : 0);   // [groups][AW] group totals (WS > 1)
     p.xt = p.tot + (WS > 1 ? (size_t)groups * AW * 16 : 0);
@@ -90,9 +91,7 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
     const int S = xc.S, G = xc.G;                // G: workgroups per shard
     const LdsPlan lp = lds_plan(lay, W, WS, AW, S);
     char *lds = reinterpret_cast<char *>(lds4);
-    float *lx = reinterpret_cast<float *>(lds + lp.cx);
-    float *ly = reinterpret_cast<float *>(lds + lp.cy);
-    float *lz = reinterpret_cast<float *>(lds + lp.cz);
+    float *lpt = reinterpret_cast<float *>(lds + lp.cx);          // points interleaved: x, y, z per point
     int4 *runs = reinterpret_cast<int4 *>(lds + lp.runs);      // [runs_cap]: begin, end, first slice, slices
     float4 *rvel = reinterpret_cast<float4 *>(lds + lp.rvel);  // [runs_cap]
     __shared__ int s_last, s_nruns, s_split;
@@ -153,7 +152,7 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
     const bool resident = lay.resident && n_shard <= (long long)lay.cap;
     if (resident)
         for (int i = tid; i < (int)n_shard; i += NT) {
-            lx[i] = sc.x[sb + i]; ly[i] = sc.y[sb + i]; lz[i] = sc.z[sb + i];
+            lpt[3 * i] = sc.x[sb + i]; lpt[3 * i + 1] = sc.y[sb + i]; lpt[3 * i + 2] = sc.z[sb + i];
         }
     __syncthreads();
     const int n_runs = s_nruns;
@@ -197,11 +196,12 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
         if (split) {
             const float psx = fmaf(-t, my_v.x, px), psy = fmaf(-t, my_v.y, py), psz = fmaf(-t, my_v.z, pz);
             float Gs = 0, Sx = 0, Sy = 0, Sz = 0;
-            int j = my_j0;
+            const float *q = lpt + 3 * my_j0;
+            const int step3 = 3 * my_stride;
 #pragma unroll 4
-            for (int i = 0; i < my_n; ++i, j += my_stride)
-                interact<CUT>(lx[j], ly[j], lz[j], psx, psy, psz, P.wx, P.wy, P.wz, P.R, pr.eps, P.rd, P.tb_a, P.tb_b,
-                              Gs, Sx, Sy, Sz, m2);
+            for (int i = 0; i < my_n; ++i, q += step3)
+                interact<CUT>(q[0], q[1], q[2], psx, psy, psz, P.wx, P.wy, P.wz, P.R, pr.eps, P.rd, P.tb_a, P.tb_b, Gs,
+                              Sx, Sy, Sz, m2);
             project_add(vx - my_v.x, vy - my_v.y, vz - my_v.z, P.kf, P.wx, P.wy, P.wz, Gs, Sx, Sy, Sz, Fx, Fy, Fz);
         }
         const int tile = resident ? (int)max(n_shard, 1ll) : lay.cap;
@@ -210,7 +210,7 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
             if (!resident) {
                 __syncthreads();
                 for (int i = tid; i < tn; i += NT) {
-                    lx[i] = sc.x[tb + i]; ly[i] = sc.y[tb + i]; lz[i] = sc.z[tb + i];
+                    lpt[3 * i] = sc.x[tb + i]; lpt[3 * i + 1] = sc.y[tb + i]; lpt[3 * i + 2] = sc.z[tb + i];
                 }
                 __syncthreads();
             }
@@ -223,7 +223,7 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
                 // agent position relative to the moving segment
                 const float psx = fmaf(-t, ov.x, px), psy = fmaf(-t, ov.y, py), psz = fmaf(-t, ov.z, pz);
                 float Gs = 0, Sx = 0, Sy = 0, Sz = 0;
-                interact_run<L, CUT>(lx, ly, lz, b - t0r, e - t0r, slice, psx, psy, psz, P.wx, P.wy, P.wz, P.R,
+                interact_run_aos<L, CUT>(lpt, b - t0r, e - t0r, slice, psx, psy, psz, P.wx, P.wy, P.wz, P.R,
                                      pr.eps, P.rd, P.tb_a, P.tb_b, Gs, Sx, Sy, Sz, m2);
                 project_add(vx - ov.x, vy - ov.y, vz - ov.z, P.kf, P.wx, P.wy, P.wz, Gs, Sx, Sy, Sz, Fx, Fy, Fz);
             }
@@ -260,18 +260,16 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
                     st64_agent(slot + 2, xword(Fz, tag));
                     st64_agent(slot + 3, xword(m2, tag));
                 }
-                // each lane watches the last word of (shard, agent) slots, then reads and checks all four
+                // each lane polls the four words of one (shard, agent) slot until all carry this step's tag
                 for (int l = lane; l < S * AW; l += 64) {
                     const unsigned long long *slot =
                         xc.partial + 4 * (((size_t)(par * GW + gw) * S + l / AW) * AW + l % AW);
                     unsigned long long q0, q1, q2, q3;
                     unsigned spins = 0;
-                    while (true) {
+                    while (true) {                       // the four loads are in flight together
+                        q0 = ld64_agent(slot); q1 = ld64_agent(slot + 1); q2 = ld64_agent(slot + 2);
                         q3 = ld64_agent(slot + 3);
-                        if (xtag(q3) == tag) {
-                            q0 = ld64_agent(slot); q1 = ld64_agent(slot + 1); q2 = ld64_agent(slot + 2);
-                            if (xtag(q0) == tag && xtag(q1) == tag && xtag(q2) == tag) break;
-                        }
+                        if (xtag(q0) == tag && xtag(q1) == tag && xtag(q2) == tag && xtag(q3) == tag) break;
                         __builtin_amdgcn_s_sleep(2);
                         if ((++spins & 63u) == 0) {
                             if (ld_agent(xc.status) != 0u) break;

@@ -47,6 +47,10 @@ namespace gm {
 
 using namespace dev;
 
+// Words per (shard, agent) exchange slot: Fx, Fy, Fz, min r2 (the rest pads the slot
+// to its own 128-byte line).
+constexpr int kSlotWords = 4;
+
 // Launch-time layout of the shard in LDS.
 struct Lay {
     int resident;   // 1 = the whole shard is loaded once, 0 = streamed tiles
@@ -254,7 +258,7 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
             const unsigned tag = (unsigned)k;
             if (lead) {
                 if (lane < AW) {
-                    unsigned long long *slot = xc.partial + 4 * (((size_t)(par * GW + gw) * S + s) * AW + lane);
+                    unsigned long long *slot = xc.partial + kSlotWords * (((size_t)(par * GW + gw) * S + s) * AW + lane);
                     st64_agent(slot, xword(Fx, tag));
                     st64_agent(slot + 1, xword(Fy, tag));
                     st64_agent(slot + 2, xword(Fz, tag));
@@ -263,7 +267,7 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
                 // each lane polls the four words of one (shard, agent) slot until all carry this step's tag
                 for (int l = lane; l < S * AW; l += 64) {
                     const unsigned long long *slot =
-                        xc.partial + 4 * (((size_t)(par * GW + gw) * S + l / AW) * AW + l % AW);
+                        xc.partial + kSlotWords * (((size_t)(par * GW + gw) * S + l / AW) * AW + l % AW);
                     unsigned long long q0, q1, q2, q3;
                     unsigned spins = 0;
                     while (true) {                       // the four loads are in flight together
@@ -405,7 +409,7 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
         if (tid == 0 && ld_agent(xc.status) != 0u && pb.rho_min) pb.rho_min[0] = NAN;
     }
     if (S > 1) {
-        const size_t words = (size_t)2 * GW * S * AW * 4;
+        const size_t words = (size_t)2 * GW * S * AW * kSlotWords;
         for (size_t i = tid; i < words; i += NT) st64_agent(xc.partial + i, 0ull);
     }
     if (tid == 0) {
@@ -568,7 +572,7 @@ gmapp_status launch_rollout(gmapp_ctx *ctx, const Scn &sc, const Agt &ag, const 
     if (t.S > 1) nwg = (nwg + 7) / 8 * 8;
     if (nwg > kMaxWorkgroups)
         return fail(ctx, GMAPP_ECAPACITY, "%lld workgroups exceed the limit %d", nwg, kMaxWorkgroups);
-    const size_t need_partial = (size_t)2 * G * gpw * t.S * t.A * 4 * sizeof(unsigned long long);
+    const size_t need_partial = (size_t)2 * G * gpw * t.S * t.A * kSlotWords * sizeof(unsigned long long);
     if (t.S > 1 && need_partial > kXchgBytes)
         return fail(ctx, GMAPP_ECAPACITY, "exchange area needs %zu bytes, the context holds %zu", need_partial,
                     kXchgBytes);

@@ -254,6 +254,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-request batched / served mix")
     ap.add_argument("--no-autotune", action="store_true", help="use the built-in tiling choice")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
+    ap.add_argument("--quantum", type=int, default=100, help="steps per request per server cycle")
     ap.add_argument("--batch-requests", type=int, default=512, help="requests of the batched / served mix")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -357,7 +358,7 @@ def main():
         res["batched"] = batched_vs_per_scene(ctx, dev, reqs)
         print(f"# batched: {res['batched']['batched_s']:.3f} s vs per-scene {res['batched']['per_scene_s']:.3f} s",
               file=sys.stderr, flush=True)
-        res["serving"] = serving(ctx, reqs)
+        res["serving"] = serving(ctx, reqs, quantum=args.quantum)
         print(f"# serving: p99 {res['serving']['p99_latency_ms']:.1f} ms", file=sys.stderr, flush=True)
     # a plain device copy of known size: reference for the HBM byte counters of a profiled run
     # (an elementwise kernel, so that the counters see it: reads 256 MiB, writes 256 MiB)

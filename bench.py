@@ -254,7 +254,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-request batched / served mix")
     ap.add_argument("--no-autotune", action="store_true", help="use the built-in tiling choice")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
-    ap.add_argument("--quantum", type=int, default=100, help="steps per request per server cycle")
+    ap.add_argument("--quantum", type=int, default=50, help="steps per request per server cycle")
     ap.add_argument("--batch-requests", type=int, default=512, help="requests of the batched / served mix")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:

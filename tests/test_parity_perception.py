@@ -179,3 +179,37 @@ def test_rollout_on_device_sphere_world(ctx):
            "min_clear": out["min_clear"].cpu().numpy()[idx], "best": int(out["best"].item())}
     err = gu.compare_rollout(pb, gpu, ref)
     print(f"config3 rollout on {len(C)} voxel centres: pos err {err:.2e}", flush=True)
+
+
+def test_batched_rollout_on_device_sphere_world(ctx):
+    """Perception -> batched planning without a host sync: two jobs of one
+    launch read N_O from the voxel pass's device counter (capacity-sized arrays),
+    one of them in two step ranges resumed from the device state."""
+    import torch
+    from paper_2606_12579_amd import gmapp
+    fr = scenes.config3_frame()
+    P = op.back_project(fr.depth, fr.K, fr.T_wc).astype(np.float32)
+    cells = op.voxel_cells(P[:, 0], P[:, 1], P[:, 2], fr.voxel, fr.box_lo, fr.dims)
+    C = op.voxel_centres(cells, fr.voxel, fr.box_lo, fr.dims).astype(np.float32)
+    t = [torch.as_tensor(np.ascontiguousarray(P[:, a]), device="cuda") for a in range(3)]
+    ox, oy, oz, n = ctx.voxel_downsample(*t, fr.voxel, fr.box_lo, fr.dims, capacity=32768)
+    agents, q, prm = scenes.config3_agents(n_agents=24, n_steps=60)
+    sc = gmapp.DeviceScene(ox, oy, oz, scenes.R_OBS, n_points_dev=n)
+    ag = gmapp.agents_to_device(agents)
+    q2 = copy.deepcopy(q)
+    q2.p0 = np.asarray(q.p0, np.float32) + np.float32(0.05)
+    st = torch.zeros((agents.n, gmapp.STATE_FLOATS), dtype=torch.float32, device="cuda")
+    jobs = [gmapp.BatchJob(sc, ag, q, prm, ctx.outputs(agents.n, prm.n_steps)),
+            gmapp.BatchJob(sc, ag, q2, prm, ctx.outputs(agents.n, prm.n_steps), st, 1, 25)]
+    ctx.clear_batch_tuning()
+    ctx.rollout_batch(jobs)
+    jobs[1].k_begin, jobs[1].k_end = 25, prm.n_steps + 1
+    ctx.rollout_batch([jobs[1]])
+    torch.cuda.synchronize()
+    idx = np.arange(0, 24, 5)
+    for query, j in ((q, jobs[0]), (q2, jobs[1])):
+        pb = scenes.Problem(scenes.Scene(C[:, 0].copy(), C[:, 1].copy(), C[:, 2].copy(), scenes.R_OBS),
+                            agents.subset(idx), query, prm)
+        ref = oracle.rollout(pb)
+        gpu = {k: (v.cpu().numpy()[idx] if k != "best" else None) for k, v in j.out.items()}
+        gu.compare_rollout(pb, gpu, ref)

@@ -59,7 +59,7 @@ struct Lay {
 };
 
 // Dynamic LDS layout of k_rollout, in bytes (16-byte aligned pieces):
-//   points [cap][3] (x, y, z interleaved)  ·  red float4 [2][W][AW]  ·  tot float4 [groups][AW]
+//   points [cap][3] (x, y, z interleaved)  ·  red float4 [2][W][AW]  ·  tot float4 [groups][AW][2]
 //   ·  xt float4 [groups][S*AW]
 //   ·  runs int4 [runs_cap]  ·  rvel float4 [runs_cap]  ·  sel (float, int) [NT]
 struct LdsPlan {
@@ -73,7 +73,7 @@ __host__ __device__ inline LdsPlan lds_plan(const Lay &l, int W, int WS, int AW,
     p.cx = 0; p.cy = plane; p.cz = 2 * plane;   // [cx, cx + 3 plane): the points, interleaved x, y, z
     p.red = 3 * plane;                            // [2][W][AW] wave partials (WS > 1)
     p.tot = p.red + (WS > 1 ? (size_t)2 * W * AW * 16 : 0);   // [groups][AW] group totals (WS > 1)
-    p.xt = p.tot + (WS > 1 ? (size_t)groups * AW * 16 : 0);
+    p.xt = p.tot + (WS > 1 ? (size_t)groups * AW * 32 : 0);   // tot: new (p, v) per agent, 2 float4
     p.runs = p.xt + (S > 1 ? (size_t)groups * S * AW * 16 : 0);
     p.rvel = p.runs + (size_t)l.runs_cap * 16;
     p.sel = p.rvel + (size_t)l.runs_cap * 16;
@@ -108,7 +108,7 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
     const int slice = ((wave % WS) * 64 + lane) / AW;
     const bool lead = (wave % WS) == 0;           // the group's wave that exchanges with other shards
     float4 *red = reinterpret_cast<float4 *>(lds + lp.red);
-    float4 *tot = reinterpret_cast<float4 *>(lds + lp.tot) + (size_t)gi * AW;
+    float4 *tot = reinterpret_cast<float4 *>(lds + lp.tot) + (size_t)gi * AW * 2;
     float4 *xtw = reinterpret_cast<float4 *>(lds + lp.xt) + (size_t)gi * S * AW;  // this group's gather
 
     // workgroup -> (group g, shard s); for S > 1 the S shards of a group share an
@@ -241,106 +241,122 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
             m2 = agent_allreduce<AW, true>(m2);
         }
         const int par = k & 1;
-        // ... across the waves of a workgroup-wide group (LDS) ...
-        if constexpr (WS > 1) {
-            if (lane < AW) red[(par * W + wave) * AW + lane] = make_float4(Fx, Fy, Fz, m2);
-            __syncthreads();
-            float4 acc = red[(par * W) * AW + a_w];
-#pragma unroll
-            for (int r = 1; r < W; ++r) {
-                const float4 q = red[(par * W + r) * AW + a_w];
-                acc.x += q.x; acc.y += q.y; acc.z += q.z; acc.w = fminf(acc.w, q.w);
+
+        // running costs that do not depend on this step's force (Eqs. 17, 19, 20): p^(k), v^(k-1), F^(k-1), F^(k-2)
+        auto costs_early = [&]() {
+            const float ex = gx - px, ey = gy - py, ez = gz - pz;
+            const float dgoal = __builtin_amdgcn_sqrtf(fmaf(ez, ez, fmaf(ey, ey, ex * ex)));
+            kahan_add(sg, cg, fminf(dgoal, pr.r_cost) * inv_rc);
+            if (k >= 2) kahan_add(sp, cp, pr.dt * __builtin_amdgcn_sqrtf(fmaf(vz, vz, fmaf(vy, vy, vx * vx))));
+            if (k >= 4) {
+                const float jx = hj * (F1x - F2x), jy = hj * (F1y - F2y), jz = hj * (F1z - F2z);
+                kahan_add(sj, cj, fmaf(jz, jz, fmaf(jy, jy, jx * jx)));
             }
-            Fx = acc.x; Fy = acc.y; Fz = acc.z; m2 = acc.w;
-        }
-        // ... and over the shards (device-scope exchange by the group's lead wave)
-        if (S > 1) {
+        };
+        // device-scope exchange of the group's shard totals, summed in shard order (run by the lead wave)
+        auto exchange = [&](float &Fx_, float &Fy_, float &Fz_, float &m2_) {
             const unsigned tag = (unsigned)k;
-            if (lead) {
-                if (lane < AW) {
-                    unsigned long long *slot = xc.partial + kSlotWords * (((size_t)(par * GW + gw) * S + s) * AW + lane);
-                    st64_agent(slot, xword(Fx, tag));
-                    st64_agent(slot + 1, xword(Fy, tag));
-                    st64_agent(slot + 2, xword(Fz, tag));
-                    st64_agent(slot + 3, xword(m2, tag));
-                }
-                // each lane polls the four words of one (shard, agent) slot until all carry this step's tag
-                for (int l = lane; l < S * AW; l += 64) {
-                    const unsigned long long *slot =
-                        xc.partial + kSlotWords * (((size_t)(par * GW + gw) * S + l / AW) * AW + l % AW);
-                    unsigned long long q0, q1, q2, q3;
-                    unsigned spins = 0;
-                    while (true) {                       // the four loads are in flight together
-                        q0 = ld64_agent(slot); q1 = ld64_agent(slot + 1); q2 = ld64_agent(slot + 2);
-                        q3 = ld64_agent(slot + 3);
-                        if (xtag(q0) == tag && xtag(q1) == tag && xtag(q2) == tag && xtag(q3) == tag) break;
-                        __builtin_amdgcn_s_sleep(2);
-                        if ((++spins & 63u) == 0) {
-                            if (ld_agent(xc.status) != 0u) break;
-                            if (__builtin_amdgcn_s_memrealtime() - t_start > kWatchdogTicks) {
-                                st_agent(xc.status, 1u);
-                                break;
-                            }
+            if (lane < AW) {
+                unsigned long long *slot = xc.partial + kSlotWords * (((size_t)(par * GW + gw) * S + s) * AW + lane);
+                st64_agent(slot, xword(Fx_, tag));
+                st64_agent(slot + 1, xword(Fy_, tag));
+                st64_agent(slot + 2, xword(Fz_, tag));
+                st64_agent(slot + 3, xword(m2_, tag));
+            }
+            // each lane polls the four words of one (shard, agent) slot until all carry this step's tag
+            for (int l = lane; l < S * AW; l += 64) {
+                const unsigned long long *slot =
+                    xc.partial + kSlotWords * (((size_t)(par * GW + gw) * S + l / AW) * AW + l % AW);
+                unsigned long long q0, q1, q2, q3;
+                unsigned spins = 0;
+                while (true) {                       // the four loads are in flight together
+                    q0 = ld64_agent(slot); q1 = ld64_agent(slot + 1); q2 = ld64_agent(slot + 2);
+                    q3 = ld64_agent(slot + 3);
+                    if (xtag(q0) == tag && xtag(q1) == tag && xtag(q2) == tag && xtag(q3) == tag) break;
+                    __builtin_amdgcn_s_sleep(2);
+                    if ((++spins & 63u) == 0) {
+                        if (ld_agent(xc.status) != 0u) break;
+                        if (__builtin_amdgcn_s_memrealtime() - t_start > kWatchdogTicks) {
+                            st_agent(xc.status, 1u);
+                            break;
                         }
                     }
-                    xtw[l] = make_float4(xval(q0), xval(q1), xval(q2), xval(q3));
                 }
-                __builtin_amdgcn_wave_barrier();
-                float4 a4 = xtw[a_w];
-                for (int r = 1; r < S; ++r) {           // fixed shard order in every shard
-                    const float4 q = xtw[r * AW + a_w];
-                    a4.x += q.x; a4.y += q.y; a4.z += q.z; a4.w = fminf(a4.w, q.w);
-                }
-                Fx = a4.x; Fy = a4.y; Fz = a4.z; m2 = a4.w;
-                if constexpr (WS > 1) {
-                    if (lane < AW) tot[lane] = a4;
-                }
+                xtw[l] = make_float4(xval(q0), xval(q1), xval(q2), xval(q3));
             }
-            if constexpr (WS > 1) {
-                __syncthreads();
-                const float4 a4 = tot[a_w];
-                Fx = a4.x; Fy = a4.y; Fz = a4.z; m2 = a4.w;
-            } else {
-                __builtin_amdgcn_wave_barrier();        // xtw is rewritten next step
+            __builtin_amdgcn_wave_barrier();
+            float4 a4 = xtw[a_w];
+            for (int r = 1; r < S; ++r) {           // fixed shard order in every shard
+                const float4 q = xtw[r * AW + a_w];
+                a4.x += q.x; a4.y += q.y; a4.z += q.z; a4.w = fminf(a4.w, q.w);
             }
-        }
+            __builtin_amdgcn_wave_barrier();        // xtw is rewritten next step
+            Fx_ = a4.x; Fy_ = a4.y; Fz_ = a4.z; m2_ = a4.w;
+        };
+        // net force (Eqs. 6, 7), obstacle cost (Eq. 18), integration (Eqs. 9-11), outputs
+        auto finish = [&](float Fx_, float Fy_, float Fz_, float m2_) {
+            const float rho_min = (m2_ < INFINITY) ? fmaxf(__builtin_amdgcn_sqrtf(m2_) - P.R, pr.eps) : INFINITY;
+            if constexpr (PROBE) {
+                if (valid && s == 0 && slice == 0) {
+                    pb.f_r[3 * agent] = Fx_; pb.f_r[3 * agent + 1] = Fy_; pb.f_r[3 * agent + 2] = Fz_;
+                    if (pb.rho_min) pb.rho_min[agent] = rho_min;
+                }
+                return;
+            }
+            const float ex = gx - px, ey = gy - py, ez = gz - pz;
+            const float Ftx = fmaf(P.ka, ex, fmaf(-P.da, vx, Fx_));
+            const float Fty = fmaf(P.ka, ey, fmaf(-P.da, vy, Fy_));
+            const float Ftz = fmaf(P.ka, ez, fmaf(-P.da, vz, Fz_));
+            kahan_add(so, co, 1.0f - fminf(rho_min, pr.r_cost) * inv_rc);
+            F2x = F1x; F2y = F1y; F2z = F1z;
+            F1x = Ftx; F1y = Fty; F1z = Ftz;
+            kahan_add(vx, cvx, h * Ftx);
+            kahan_add(vy, cvy, h * Fty);
+            kahan_add(vz, cvz, h * Ftz);
+            kahan_add(px, cpx, pr.dt * vx);
+            kahan_add(py, cpy, pr.dt * vy);
+            kahan_add(pz, cpz, pr.dt * vz);
+            if (writer) {
+                if (out.traj) {
+                    float *tr = out.traj + (size_t)agent * traj_row + 3 * (size_t)k;
+                    tr[0] = px; tr[1] = py; tr[2] = pz;
+                }
+                if (out.min_clear) out.min_clear[(size_t)agent * pr.n_steps + (k - 1)] = rho_min;
+            }
+        };
 
-        const float rho_min = (m2 < INFINITY) ? fmaxf(__builtin_amdgcn_sqrtf(m2) - P.R, pr.eps) : INFINITY;
-        if constexpr (PROBE) {
-            if (valid && s == 0 && slice == 0) {
-                pb.f_r[3 * agent] = Fx; pb.f_r[3 * agent + 1] = Fy; pb.f_r[3 * agent + 2] = Fz;
-                if (pb.rho_min) pb.rho_min[agent] = rho_min;
+        if constexpr (WS > 1) {
+            // across the waves of the workgroup (LDS); the lead wave completes the step for the
+            // group and hands the new positions and velocities to the other waves
+            if (lane < AW) red[(par * W + wave) * AW + lane] = make_float4(Fx, Fy, Fz, m2);
+            __syncthreads();
+            if (lead) {
+                float4 acc = red[(par * W) * AW + a_w];
+#pragma unroll
+                for (int r = 1; r < W; ++r) {
+                    const float4 q = red[(par * W + r) * AW + a_w];
+                    acc.x += q.x; acc.y += q.y; acc.z += q.z; acc.w = fminf(acc.w, q.w);
+                }
+                Fx = acc.x; Fy = acc.y; Fz = acc.z; m2 = acc.w;
+                if constexpr (!PROBE) costs_early();       // overlaps the other shards' arrival
+                if (S > 1) exchange(Fx, Fy, Fz, m2);
+                finish(Fx, Fy, Fz, m2);
+                if (lane < AW) {
+                    tot[2 * lane] = make_float4(px, py, pz, vx);
+                    tot[2 * lane + 1] = make_float4(vy, vz, 0.f, 0.f);
+                }
             }
-            break;
-        }
-
-        // ---- net force (Eqs. 6, 7), running costs (Eqs. 17-20), integration (Eqs. 9-11)
-        const float ex = gx - px, ey = gy - py, ez = gz - pz;
-        const float Ftx = fmaf(P.ka, ex, fmaf(-P.da, vx, Fx));
-        const float Fty = fmaf(P.ka, ey, fmaf(-P.da, vy, Fy));
-        const float Ftz = fmaf(P.ka, ez, fmaf(-P.da, vz, Fz));
-        const float dgoal = __builtin_amdgcn_sqrtf(fmaf(ez, ez, fmaf(ey, ey, ex * ex)));
-        kahan_add(sg, cg, fminf(dgoal, pr.r_cost) * inv_rc);
-        kahan_add(so, co, 1.0f - fminf(rho_min, pr.r_cost) * inv_rc);
-        if (k >= 2) kahan_add(sp, cp, pr.dt * __builtin_amdgcn_sqrtf(fmaf(vz, vz, fmaf(vy, vy, vx * vx))));
-        if (k >= 4) {
-            const float jx = hj * (F1x - F2x), jy = hj * (F1y - F2y), jz = hj * (F1z - F2z);
-            kahan_add(sj, cj, fmaf(jz, jz, fmaf(jy, jy, jx * jx)));
-        }
-        F2x = F1x; F2y = F1y; F2z = F1z;
-        F1x = Ftx; F1y = Fty; F1z = Ftz;
-        kahan_add(vx, cvx, h * Ftx);
-        kahan_add(vy, cvy, h * Fty);
-        kahan_add(vz, cvz, h * Ftz);
-        kahan_add(px, cpx, pr.dt * vx);
-        kahan_add(py, cpy, pr.dt * vy);
-        kahan_add(pz, cpz, pr.dt * vz);
-        if (writer) {
-            if (out.traj) {
-                float *tr = out.traj + (size_t)agent * traj_row + 3 * (size_t)k;
-                tr[0] = px; tr[1] = py; tr[2] = pz;
+            __syncthreads();
+            if constexpr (PROBE) break;
+            if (!lead) {
+                const float4 a = tot[2 * a_w], b = tot[2 * a_w + 1];
+                px = a.x; py = a.y; pz = a.z; vx = a.w; vy = b.x; vz = b.y;
             }
-            if (out.min_clear) out.min_clear[(size_t)agent * pr.n_steps + (k - 1)] = rho_min;
+        } else {
+            if constexpr (!PROBE) costs_early();
+            if (S > 1) exchange(Fx, Fy, Fz, m2);
+            finish(Fx, Fy, Fz, m2);
+            if constexpr (PROBE) break;
         }
     }
 

@@ -20,7 +20,7 @@ PEAK_FP32 = 157.3e12          # MI355X FP32 vector peak, FLOP/s
 FLOP_PER_INTERACTION = 25     # algorithmic FP32 work of one (agent, sphere, step) evaluation
 
 
-def kernel_sources_sha1(names=("rollout.hip", "pairs.h", "gmapp_internal.h")):
+def kernel_sources_sha1(names=("rollout_kernel.h", "rollout.hip", "pairs.h", "gmapp_internal.h")):
     """Fingerprint of the sources of the rollout kernel (the HBM counters below are
     valid only for the kernel they were taken on)."""
     import hashlib
@@ -171,6 +171,34 @@ def adjoint_pass(ctx, dev, reps=3):
             "forward_interactions_per_s": inter / (f * 1e-3), "backward_interactions_per_s": inter / (b * 1e-3)}
 
 
+def heterogeneous_pass(ctx, dev, base_ms, reps=10):
+    """The headline scene and horizon (N_O=50,000 moving points, N_k=500) with a mixed
+    ensemble of 64 agents: heuristic i % 3 (rotation-vector circular field,
+    velocity-current field, APF) and alternating small / large detection radius
+    (0.05 m / 0.15 m). HIP events around each launch, same tiling as the headline."""
+    import numpy as np
+    import torch
+    from paper_2606_12579_amd import gmapp, scenes
+    pb = scenes.config2()
+    pb.agents = scenes.multi_agents(np.random.default_rng(11), pb.agents.n)
+    sc, ag = gmapp.scene_to_device(pb.scene, dev), gmapp.agents_to_device(pb.agents, dev)
+    stream = torch.cuda.current_stream(dev)
+    out = ctx.rollout(sc, ag, pb.query, pb.params, stream=stream)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for e0, e1 in ev:
+        e0.record(stream)
+        ctx.rollout(sc, ag, pb.query, pb.params, out=out, stream=stream)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    ms = float(np.mean([e0.elapsed_time(e1) for e0, e1 in ev]))
+    inter = float(pb.agents.n) * pb.params.n_steps * pb.scene.n
+    return {"workload": "config-2 scene, N_a=64 mixed (CF omega / CF velocity current / APF) x (r_d 0.05 / 0.15 m), "
+                        "N_k=500",
+            "kernel_ms_mean": ms, "interactions_per_s": inter / (ms * 1e-3),
+            "over_homogeneous": ms / base_ms, "best": int(out["best"].item())}
+
+
 def batched_vs_per_scene(ctx, dev, reqs, proxy_steps=16):
     """The 512-request mix (N_O in [1k, 200k], N_a in {16, 64, 256}, N_k in [100, 1000]):
     one batched persistent launch (autotuned) against one gmapp_rollout launch per
@@ -254,6 +282,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-request batched / served mix")
     ap.add_argument("--no-autotune", action="store_true", help="use the built-in tiling choice")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
+    ap.add_argument("--no-heterogeneous", action="store_true", help="skip the mixed-heuristic ensemble timing")
     ap.add_argument("--quantum", type=int, default=50, help="steps per request per server cycle")
     ap.add_argument("--batch-requests", type=int, default=512, help="requests of the batched / served mix")
     args = ap.parse_args()
@@ -348,6 +377,8 @@ def main():
                      "frac": achieved / PEAK_FP32, "traffic": measured_traffic(),
                      "kernel_source_sha1": kernel_sources_sha1()},
     }
+    if not args.no_heterogeneous:
+        res["heterogeneous"] = heterogeneous_pass(ctx, dev, avg_kernel_s * 1e3)
     if not args.no_perception:
         res["perception"] = perception_pass(ctx, dev)
     if not args.no_adjoint:

@@ -77,11 +77,22 @@ typedef struct {
 /* Per-agent parameters (Alg. 1 inputs and the attractor of Eq. 7): circular-field
  * gain k_f, detection radius r_d, agent radius r_a, stiffness K = k_a I, damping
  * D = d_a I, and the rotation vector omega that parameterises the current vector
- * of Eq. (3): c = omega - n (n . omega). */
+ * of Eq. (3): c = omega - n (n . omega).
+ * heuristic (Sec. III-A; NULL = every agent GMAPP_H_CF_OMEGA) selects each agent's
+ * repulsive field: GMAPP_H_CF_OMEGA the circular field above; GMAPP_H_MFI_VEL the
+ * same field with the current of Eq. (3) taken from the relative velocity w,
+ * c = w - n (n . w) (omega unused); GMAPP_H_APF the artificial potential field of
+ * Eq. (1), f = k_f (1/rho - 1/r_d) (1/rho^2) d/|d| with the surface distance rho.
+ * Heterogeneous agents run in gmapp_rollout and gmapp_force_probe; the batched,
+ * adjoint and served entry points require heuristic = NULL (EINVAL otherwise). */
+#define GMAPP_H_CF_OMEGA 0
+#define GMAPP_H_MFI_VEL 1
+#define GMAPP_H_APF 2
 typedef struct {
     const float *k_a, *d_a, *k_f, *r_d, *r_a; /* device [N_a] each */
     const float *omega;                       /* device [N_a][3] */
     int32_t n_agents;                         /* N_a >= 0 */
+    const int32_t *heuristic;                 /* device [N_a] or NULL; values 0, 1, 2 (others read as 0) */
 } gmapp_agents;
 
 /* Planning query (host values): start position p^(1), start velocity v^(0),

@@ -49,6 +49,9 @@ def _load():
         lib.oracle_pair_force.restype = None
         lib.oracle_pair_force.argtypes = [_dp, _dp, _dp, _dp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                           ctypes.c_double, ctypes.c_int, ctypes.c_double, _dp, _dp]
+        lib.oracle_pair_force_h.restype = None
+        lib.oracle_pair_force_h.argtypes = [ctypes.c_int, _dp, _dp, _dp, _dp, ctypes.c_double, ctypes.c_double,
+                                            ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_double, _dp, _dp]
         _lib = lib
     return _lib
 
@@ -71,8 +74,12 @@ def _params_row(prm) -> np.ndarray:
 
 
 def _agents_rows(ag) -> np.ndarray:
-    return np.stack([ag.k_a, ag.d_a, ag.k_f, ag.r_d, ag.r_a, ag.omega[:, 0], ag.omega[:, 1], ag.omega[:, 2]],
-                    1).astype(np.float64) if ag.n > 0 else np.zeros((0, 8))
+    if ag.n == 0:
+        return np.zeros((0, 9))
+    heur = getattr(ag, "heuristic", None)
+    heur = np.zeros(ag.n) if heur is None else np.asarray(heur, np.float64)
+    return np.stack([ag.k_a, ag.d_a, ag.k_f, ag.r_d, ag.r_a, ag.omega[:, 0], ag.omega[:, 1], ag.omega[:, 2], heur],
+                    1).astype(np.float64)
 
 
 def _scene_args(sc):
@@ -149,6 +156,8 @@ def rollout_grad(problem) -> np.ndarray:
     """[N_a, 7]: C_i, then dC_i/d(k_a, d_a, k_f, omega_x, omega_y, omega_z)."""
     lib = _load()
     sc, ag, q, prm = problem.scene, problem.agents, problem.query, problem.params
+    if getattr(ag, "heuristic", None) is not None and np.any(np.asarray(ag.heuristic) != 0):
+        raise ValueError("the dual-number gradient covers the rotation-vector circular field only")
     keep, sargs = _scene_args(sc)
     A, pA = _d(_agents_rows(ag))
     Q, pQ = _d(np.concatenate([q.p0, q.v0, q.goal, [np.float32(q.t0)]]).astype(np.float64))
@@ -187,6 +196,18 @@ def pair_force(p, w, q, omega, k_f, r_d, R, eps, cutoff=0, band=0.1):
     rho = ctypes.c_double()
     lib.oracle_pair_force(*[a[1] for a in arrs], float(k_f), float(r_d), float(R), float(eps), int(cutoff),
                           float(band), f.ctypes.data_as(_dp), ctypes.byref(rho))
+    return f, rho.value
+
+
+def pair_force_heuristic(heur, p, w, q, omega, k_f, r_d, R, eps, cutoff=0, band=0.1):
+    """One pair of Sec. III-A's heuristics: 0 rotation-vector circular field, 1 the
+    field with the relative-velocity current (Eq. 3), 2 artificial potential field (Eq. 1)."""
+    lib = _load()
+    arrs = [_d(a) for a in (p, w, q, omega)]
+    f = np.zeros(3)
+    rho = ctypes.c_double()
+    lib.oracle_pair_force_h(int(heur), *[a[1] for a in arrs], float(k_f), float(r_d), float(R), float(eps),
+                            int(cutoff), float(band), f.ctypes.data_as(_dp), ctypes.byref(rho))
     return f, rho.value
 
 

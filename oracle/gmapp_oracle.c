@@ -30,7 +30,11 @@
 #include <string.h>
 
 /* per-agent parameter row: k_a, d_a, k_f, r_d, r_a, omega_x, omega_y, omega_z */
-enum { A_KA = 0, A_DA, A_KF, A_RD, A_RA, A_WX, A_WY, A_WZ, A_N };
+enum { A_KA = 0, A_DA, A_KF, A_RD, A_RA, A_WX, A_WY, A_WZ, A_HEUR, A_N };
+/* repulsive heuristic of an agent (Sec. III-A): circular field whose current is
+ * parameterised by the agent's rotation vector, the same field with the current
+ * taken from the relative velocity (Eq. 3 as printed), artificial potential field (Eq. 1) */
+enum { H_CF_OMEGA = 0, H_MFI_VEL = 1, H_APF = 2 };
 /* global parameter row */
 enum { P_DT = 0, P_INVM, P_EPS, P_RC, P_W1, P_W2, P_W3, P_W4, P_AMAX, P_ALPHA, P_BAND, P_N };
 
@@ -87,6 +91,42 @@ void oracle_pair_force(const double p[3], const double w[3], const double q[3], 
     f[0] = s * fu[0]; f[1] = s * fu[1]; f[2] = s * fu[2];
 }
 
+/* Heuristic 2 with the current of Eq. (3) taken literally: c = w - n (n . w),
+ * the relative velocity projected onto the surface; then Eq. (2) as above. */
+static void mfi_vel_force(const double p[3], const double w[3], const double q[3], double k_f, double r_d, double R,
+                          double eps, int cutoff, double band, double f[3], double *rho_out)
+{
+    oracle_pair_force(p, w, q, w, k_f, r_d, R, eps, cutoff, band, f, rho_out);
+}
+
+/* Heuristic 1 (APF, Eq. 1): f = k_f (1/rho - 1/r_d) (1/rho^2) n for a sphere within
+ * the detection distance, n = d / |d| (d = p - q), with the distance to the sphere's
+ * surface rho = max(|d| - R, eps) in place of |d| (the distance Eq. 1's condition
+ * tests; FIRAS form).  The same cut-off weight as Eq. (2). */
+void oracle_apf_force(const double p[3], const double q[3], double k_f, double r_d, double R, double eps, int cutoff,
+                      double band, double f[3], double *rho_out)
+{
+    double d[3] = {p[0] - q[0], p[1] - q[1], p[2] - q[2]};
+    double r = norm3(d);
+    double rho = fmax(r - R, eps);
+    *rho_out = rho;
+    f[0] = f[1] = f[2] = 0.0;
+    double sigma = oracle_cutoff_weight(rho, r_d, cutoff, band);
+    if (sigma == 0.0 || r == 0.0) return;
+    double mag = sigma * k_f * (1.0 / rho - 1.0 / r_d) / (rho * rho);
+    f[0] = mag * d[0] / r; f[1] = mag * d[1] / r; f[2] = mag * d[2] / r;
+}
+
+/* The pair force of an agent with heuristic `heur`. */
+void oracle_pair_force_h(int heur, const double p[3], const double w[3], const double q[3], const double omega[3],
+                         double k_f, double r_d, double R, double eps, int cutoff, double band, double f[3],
+                         double *rho_out)
+{
+    if (heur == H_APF) oracle_apf_force(p, q, k_f, r_d, R, eps, cutoff, band, f, rho_out);
+    else if (heur == H_MFI_VEL) mfi_vel_force(p, w, q, k_f, r_d, R, eps, cutoff, band, f, rho_out);
+    else oracle_pair_force(p, w, q, omega, k_f, r_d, R, eps, cutoff, band, f, rho_out);
+}
+
 /* segment (object) index of point j; -1 when the scene is static */
 static int seg_of(long j, int n_seg, const int *seg_begin)
 {
@@ -108,6 +148,7 @@ static void repulsion_one(long n_pts, const double *px, const double *py, const 
                           double F[3], double *rho_min, double *abs_sum, double *edge_sum, long *edge_cnt)
 {
     double omega[3] = {ag[A_WX], ag[A_WY], ag[A_WZ]};
+    const int heur = (int)ag[A_HEUR];
     double R = r_obs + ag[A_RA];
     F[0] = F[1] = F[2] = 0.0;
     double rmin = INFINITY, asum = 0.0, esum = 0.0;
@@ -119,7 +160,7 @@ static void repulsion_one(long n_pts, const double *px, const double *py, const 
         double q[3] = {px[j] + t * vo[0], py[j] + t * vo[1], pz[j] + t * vo[2]};
         double w[3] = {v[0] - vo[0], v[1] - vo[1], v[2] - vo[2]};
         double f[3], rho;
-        oracle_pair_force(p, w, q, omega, ag[A_KF], ag[A_RD], R, prm[P_EPS], cutoff, prm[P_BAND], f, &rho);
+        oracle_pair_force_h(heur, p, w, q, omega, ag[A_KF], ag[A_RD], R, prm[P_EPS], cutoff, prm[P_BAND], f, &rho);
         F[0] += f[0]; F[1] += f[1]; F[2] += f[2];
         if (rho < rmin) rmin = rho;
         double fa = norm3(f);
@@ -128,7 +169,8 @@ static void repulsion_one(long n_pts, const double *px, const double *py, const 
             ecnt += 1;
             /* the force such a pair would give if classified the other way */
             double fo[3], rr;
-            oracle_pair_force(p, w, q, omega, ag[A_KF], 2.0 * ag[A_RD] + 1.0, R, prm[P_EPS], 0, 0.0, fo, &rr);
+            oracle_pair_force_h(heur, p, w, q, omega, ag[A_KF], 2.0 * ag[A_RD] + 1.0, R, prm[P_EPS], 0, 0.0, fo,
+                                &rr);
             esum += norm3(fo);
         }
     }

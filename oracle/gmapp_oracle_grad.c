@@ -18,7 +18,7 @@
 #define ND 6
 typedef struct { double v; double d[ND]; } dual;
 
-enum { A_KA = 0, A_DA, A_KF, A_RD, A_RA, A_WX, A_WY, A_WZ, A_N };
+enum { A_KA = 0, A_DA, A_KF, A_RD, A_RA, A_WX, A_WY, A_WZ, A_HEUR, A_N };   /* rotation-vector field only */
 enum { P_DT = 0, P_INVM, P_EPS, P_RC, P_W1, P_W2, P_W3, P_W4, P_AMAX, P_ALPHA, P_BAND, P_N };
 
 static dual dc(double v) { dual r; r.v = v; memset(r.d, 0, sizeof r.d); return r; }

@@ -98,7 +98,7 @@ gm::Scn dev_scene(const gmapp_scene *sc)
 
 gm::Agt dev_agents(const gmapp_agents *ag)
 {
-    return gm::Agt{ag->k_a, ag->d_a, ag->k_f, ag->r_d, ag->r_a, ag->omega, ag->n_agents};
+    return gm::Agt{ag->k_a, ag->d_a, ag->k_f, ag->r_d, ag->r_a, ag->omega, ag->n_agents, ag->heuristic};
 }
 
 gm::Prm dev_params(const gmapp_params *p, const gmapp_query *q)
@@ -343,6 +343,8 @@ gmapp_status gmapp_rollout_backward(gmapp_ctx *ctx, const gmapp_scene *scene, co
     if (ckpt_every < 1 || ckpt_every > 1024) return fail(ctx, GMAPP_EINVAL, "ckpt_every must be in [1, 1024]");
     if (scene->n_seg > gm::kMaxSegments)
         return fail(ctx, GMAPP_ECAPACITY, "at most %d segments are supported", gm::kMaxSegments);
+    if (agents->heuristic)
+        return fail(ctx, GMAPP_EINVAL, "the adjoint covers the rotation-vector circular field only (heuristic = NULL)");
     if (agents->n_agents > 0 && (!grad_total || !g_k_a || !g_d_a || !g_k_f || !g_omega))
         return fail(ctx, GMAPP_EINVAL, "grad_total and the gradient outputs must be non-NULL");
     return gm::launch_adjoint(ctx, dev_scene(scene), dev_agents(agents), dev_params(params, query), grad_total,

@@ -55,6 +55,9 @@ gmapp_status check_job(gmapp_ctx *ctx, const gmapp_job &j, int idx)
         ctx->err = "job " + std::to_string(idx) + ": " + ctx->err;
         return st;
     }
+    if (j.agents.heuristic)
+        return fail(ctx, GMAPP_EINVAL, "job %d: batched launches run the rotation-vector circular field only "
+                                       "(heuristic = NULL)", idx);
     if (j.scene.n_seg > kBatchMaxSegments)
         return fail(ctx, GMAPP_ECAPACITY, "job %d: %d segments (a batched launch takes at most %d)", idx,
                     j.scene.n_seg, kBatchMaxSegments);

@@ -29,6 +29,7 @@ struct Scn {
 struct Agt {
     const float *k_a, *d_a, *k_f, *r_d, *r_a, *omega;
     int n;
+    const int *heur;          // per-agent heuristic or nullptr (all rotation-vector field)
 };
 
 struct Prm {

@@ -148,7 +148,51 @@ __device__ __forceinline__ void project_add(float ux, float uy, float uz, float 
 
 struct Agent {
     float ka, da, kf, rd, R, wx, wy, wz, tb_a, tb_b;
+    int hz = 0;               // heuristic: 0 rotation-vector field, 1 velocity current, 2 APF
+    float ird = 0.f;          // 1 / r_d (APF)
 };
+
+// One agent-sphere interaction of the artificial potential field (Eq. 1 with the
+// surface distance rho): accumulates (1/rho - 1/r_d) / (rho^2 |d|) d, to be scaled by k_f.
+template <int CUT>
+__device__ __forceinline__ void interact_apf(float qx, float qy, float qz, float psx, float psy, float psz, float R,
+                                             float eps, float rd, float ird, float tb_a, float tb_b, float &Ax,
+                                             float &Ay, float &Az, float &m2)
+{
+    const float dx = psx - qx, dy = psy - qy, dz = psz - qz;
+    const float r2 = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, kTiny)));
+    const float ri = __builtin_amdgcn_rsqf(r2);
+    const float rho = fmaxf(fmaf(r2, ri, -R), eps);
+    const float irho = __builtin_amdgcn_rcpf(rho);
+    float c = (irho - ird) * (irho * irho) * ri;
+    if constexpr (CUT == 0) {
+        c = (rho <= rd) ? c : 0.0f;
+    } else {
+        const float s = __builtin_amdgcn_fmed3f(fmaf(-rho, tb_a, tb_b), 0.0f, 1.0f);
+        c *= (s * s) * fmaf(-2.0f, s, 3.0f);
+    }
+    Ax = fmaf(c, dx, Ax);
+    Ay = fmaf(c, dy, Ay);
+    Az = fmaf(c, dz, Az);
+    m2 = fminf(m2, r2);
+}
+
+// The APF over points [b, e) of the interleaved LDS copy, slice `sl` of L.
+template <int L, int CUT>
+__device__ __forceinline__ void interact_run_apf_aos(const float *__restrict__ lp, int b, int e, int sl, float psx,
+                                                     float psy, float psz, float R, float eps, float rd, float ird,
+                                                     float tb_a, float tb_b, float &Ax, float &Ay, float &Az,
+                                                     float &m2)
+{
+    const int n = e - b;
+    const int full = n / L;
+    const float *q = lp + 3 * (b + sl);
+#pragma unroll 4
+    for (int i = 0; i < full; ++i, q += 3 * L)
+        interact_apf<CUT>(q[0], q[1], q[2], psx, psy, psz, R, eps, rd, ird, tb_a, tb_b, Ax, Ay, Az, m2);
+    if (sl < n - full * L)
+        interact_apf<CUT>(q[0], q[1], q[2], psx, psy, psz, R, eps, rd, ird, tb_a, tb_b, Ax, Ay, Az, m2);
+}
 
 
 // Segment runs of the shard [sb, se): [begin, end) relative to sb, the run's

@@ -175,7 +175,8 @@ void gmapp_server::run()
                 j.scene = gmapp_scene{f(it.lay.x), f(it.lay.y), f(it.lay.z), r.n_points, nullptr, r.r_obs, r.n_seg,
                                       reinterpret_cast<const int32_t *>(b + it.lay.seg_begin), f(it.lay.seg_vel)};
                 j.agents = gmapp_agents{f(it.lay.agent[0]), f(it.lay.agent[1]), f(it.lay.agent[2]),
-                                        f(it.lay.agent[3]), f(it.lay.agent[4]), f(it.lay.agent[5]), r.n_agents};
+                                        f(it.lay.agent[3]), f(it.lay.agent[4]), f(it.lay.agent[5]), r.n_agents,
+                                        nullptr};
                 j.query = r.query;
                 j.params = r.params;
                 j.out = gmapp_outputs{r.traj ? f(it.lay.traj) : nullptr, f(it.lay.cost), nullptr,
@@ -259,7 +260,7 @@ gmapp_status check_request(gmapp_ctx *ctx, const gmapp_request *r)
 {
     if (!r) return fail(ctx, GMAPP_EINVAL, "request is NULL");
     gmapp_scene sc{r->x, r->y, r->z, r->n_points, nullptr, r->r_obs, r->n_seg, r->seg_begin, r->seg_vel};
-    gmapp_agents ag{r->k_a, r->d_a, r->k_f, r->r_d, r->r_a, r->omega, r->n_agents};
+    gmapp_agents ag{r->k_a, r->d_a, r->k_f, r->r_d, r->r_a, r->omega, r->n_agents, nullptr};
     gmapp_status st;
     if ((st = check_scene(ctx, &sc)) || (st = check_agents(ctx, &ag)) || (st = check_params(ctx, &r->params, true)) ||
         (st = check_query(ctx, &r->query)))

@@ -41,7 +41,10 @@ class Scene(ctypes.Structure):
 
 class Agents(ctypes.Structure):
     _fields_ = [("k_a", ctypes.c_void_p), ("d_a", ctypes.c_void_p), ("k_f", ctypes.c_void_p), ("r_d", ctypes.c_void_p),
-                ("r_a", ctypes.c_void_p), ("omega", ctypes.c_void_p), ("n_agents", ctypes.c_int32)]
+                ("r_a", ctypes.c_void_p), ("omega", ctypes.c_void_p), ("n_agents", ctypes.c_int32),
+                ("heuristic", ctypes.c_void_p)]
+
+H_CF_OMEGA, H_MFI_VEL, H_APF = 0, 1, 2
 
 
 class Query(ctypes.Structure):
@@ -220,6 +223,7 @@ class DeviceAgents:
     r_d: object
     r_a: object
     omega: object
+    heuristic: object = None    # int32 [N_a] (H_*), None = all rotation-vector field
 
     @property
     def n(self) -> int:
@@ -237,7 +241,9 @@ def scene_to_device(scene, device="cuda") -> DeviceScene:
 def agents_to_device(agents, device="cuda") -> DeviceAgents:
     import torch
     t = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32), device=device)
-    return DeviceAgents(t(agents.k_a), t(agents.d_a), t(agents.k_f), t(agents.r_d), t(agents.r_a), t(agents.omega))
+    h = getattr(agents, "heuristic", None)
+    h = None if h is None else torch.as_tensor(np.ascontiguousarray(h, dtype=np.int32), device=device)
+    return DeviceAgents(t(agents.k_a), t(agents.d_a), t(agents.k_f), t(agents.r_d), t(agents.r_a), t(agents.omega), h)
 
 
 def make_params(prm) -> Params:
@@ -273,7 +279,11 @@ def _agents_struct(ag: DeviceAgents, device) -> Agents:
     for nm in ("k_a", "d_a", "k_f", "r_d", "r_a"):
         _check_tensor(getattr(ag, nm), f"agents.{nm}", n, torch.float32, device)
     _check_tensor(ag.omega, "agents.omega", 3 * n, torch.float32, device)
-    return Agents(_ptr(ag.k_a), _ptr(ag.d_a), _ptr(ag.k_f), _ptr(ag.r_d), _ptr(ag.r_a), _ptr(ag.omega), n)
+    h = getattr(ag, "heuristic", None)
+    if h is not None:
+        _check_tensor(h, "agents.heuristic", n, torch.int32, device)
+    return Agents(_ptr(ag.k_a), _ptr(ag.d_a), _ptr(ag.k_f), _ptr(ag.r_d), _ptr(ag.r_a), _ptr(ag.omega), n,
+                  None if h is None else _ptr(h))
 
 
 @dataclasses.dataclass
@@ -678,7 +688,11 @@ class _RolloutCost:
 
 def rollout_cost(gctx: Context, scene: DeviceScene, agents: DeviceAgents, query, params, ckpt_every=50):
     """Differentiable total costs [N_a] (and the selected agent) with respect to
-    agents.k_a, agents.d_a, agents.k_f and agents.omega (tensors that may require grad)."""
+    agents.k_a, agents.d_a, agents.k_f and agents.omega (tensors that may require grad).
+    The adjoint covers the rotation-vector circular field only: agents.heuristic must be None."""
+    if getattr(agents, "heuristic", None) is not None:
+        raise GmappError(EINVAL, "rollout_cost: the adjoint runs the rotation-vector circular field only "
+                                 "(agents.heuristic must be None)")
     Fn = _RolloutCost.get()
     return Fn.apply(gctx, scene, agents.r_d, agents.r_a, query, params, int(ckpt_every), agents.k_a, agents.d_a,
                     agents.k_f, agents.omega)

@@ -68,6 +68,7 @@ class Agents:
     r_d: np.ndarray
     r_a: np.ndarray
     omega: np.ndarray  # [N_a, 3]
+    heuristic: Optional[np.ndarray] = None   # int32 [N_a]: 0 rotation-vector field, 1 velocity current, 2 APF
 
     @property
     def n(self) -> int:
@@ -75,7 +76,8 @@ class Agents:
 
     def subset(self, idx) -> "Agents":
         idx = np.asarray(idx, dtype=np.int64)
-        return Agents(*(np.ascontiguousarray(getattr(self, f.name)[idx]) for f in dataclasses.fields(self)))
+        pick = lambda a: None if a is None else np.ascontiguousarray(a[idx])
+        return Agents(*(pick(getattr(self, f.name)) for f in dataclasses.fields(self)))
 
 
 @dataclasses.dataclass
@@ -290,6 +292,22 @@ def config3_poses(n: int, seed: int = 5, shift: float = 0.05, yaw: float = 0.05)
         out[i, :, :3] = Rz @ base
         out[i, :, 3] = [t[0], t[1], 1.0]
     return out.astype(F32)
+
+
+H_CF_OMEGA, H_MFI_VEL, H_APF = 0, 1, 2
+K_F_APF = 2e-6       # APF gain: sums over point clouds with 1/rho^3 growth need a much smaller gain
+
+
+def multi_agents(rng: np.random.Generator, n: int, r_small: float = 0.05, r_large: float = 0.15) -> Agents:
+    """A heterogeneous ensemble like the paper's MULTI agents: agent i uses heuristic
+    i % 3 (rotation-vector circular field, velocity-current field, APF) and, in turn,
+    a small or a large detection radius."""
+    ag = default_agents(rng, n)
+    heur = (np.arange(n) % 3).astype(np.int32)
+    ag.r_d = np.where((np.arange(n) // 3) % 2 == 0, r_small, r_large).astype(F32)
+    ag.k_f = np.where(heur == H_APF, K_F_APF, K_F).astype(F32)
+    ag.heuristic = heur
+    return ag
 
 
 def config4(seed: int = 3, n_points: int = 20_000, n_agents: int = 128, n_steps: int = 400) -> Problem:

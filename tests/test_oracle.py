@@ -6,6 +6,7 @@ library routine (matrix powers, k-d tree nearest neighbours, ODE exponentials) o
 a symmetry.  Together they are meant to fail on a dropped term, a wrong sign,
 a wrong index or a transposed operand anywhere in the oracle.
 """
+import copy
 import math
 
 import numpy as np
@@ -393,3 +394,96 @@ def test_moving_obstacles_galilean_invariance():
     np.testing.assert_allclose(res.traj, base.traj + shift, rtol=0, atol=1e-12)
     np.testing.assert_allclose(res.vel, base.vel + u, rtol=0, atol=1e-12)
     np.testing.assert_allclose(res.min_clear, base.min_clear, rtol=1e-10)
+
+
+# ---------------------------------------------------------------- other heuristics (Sec. III-A)
+
+def _apf_potential(p, q, k_f, r_d, R):
+    """U = (k_f / 2) (1/rho - 1/r_d)^2 inside the detection distance (Khatib's FIRAS
+    potential), whose negative gradient is Eq. (1)'s force."""
+    rho = np.linalg.norm(p - q) - R
+    return 0.5 * k_f * (1.0 / rho - 1.0 / r_d) ** 2 if rho < r_d else 0.0
+
+
+def test_apf_force_is_the_potential_gradient():
+    """Eq. (1) (distance read as the surface distance rho) against central
+    differences of its potential, at random points inside the detection shell;
+    zero outside it and continuous at rho = r_d."""
+    rng = np.random.default_rng(21)
+    k_f, r_d, R, eps = 0.01, 0.1, 0.005, 1e-3
+    for _ in range(40):
+        q = rng.uniform(-1, 1, 3)
+        n = rng.standard_normal(3)
+        n /= np.linalg.norm(n)
+        rho = rng.uniform(0.01, 0.095)
+        p = q + (R + rho) * n
+        f, rho_o = oracle.pair_force_heuristic(2, p, np.zeros(3), q, np.zeros(3), k_f, r_d, R, eps)
+        assert rho_o == pytest.approx(rho, rel=1e-12)
+        h = 1e-7
+        g = np.array([(_apf_potential(p + h * e, q, k_f, r_d, R) - _apf_potential(p - h * e, q, k_f, r_d, R)) / (2 * h)
+                      for e in np.eye(3)])
+        np.testing.assert_allclose(f, -g, rtol=1e-6, atol=1e-9 * np.abs(g).max())
+        assert f @ n > 0                                     # repulsive, along the outward normal
+    q = np.zeros(3)
+    far = np.array([R + 0.2, 0.0, 0.0])
+    f, _ = oracle.pair_force_heuristic(2, far, np.zeros(3), q, np.zeros(3), k_f, r_d, R, eps)
+    assert not f.any()
+    edge = np.array([R + r_d * (1 - 1e-9), 0.0, 0.0])
+    f, _ = oracle.pair_force_heuristic(2, edge, np.zeros(3), q, np.zeros(3), k_f, r_d, R, eps)
+    assert np.linalg.norm(f) < 1e-6
+
+
+def test_velocity_current_field_closed_form():
+    """Eq. (2) with Eq. (3)'s current taken from the relative velocity w:
+    f = -(k_f |w|^2 / rho) (n . w^) (n - w^ (w^ . n)) -- no work, zero when w is
+    parallel or orthogonal to the normal, deflecting away while approaching."""
+    rng = np.random.default_rng(22)
+    k_f, r_d, R, eps = 0.01, 0.1, 0.005, 1e-3
+    for _ in range(40):
+        q = rng.uniform(-1, 1, 3)
+        n = rng.standard_normal(3)
+        n /= np.linalg.norm(n)
+        rho = rng.uniform(0.01, 0.09)
+        p = q + (R + rho) * n
+        w = rng.standard_normal(3) * rng.uniform(0.1, 2.0)
+        f, _ = oracle.pair_force_heuristic(1, p, w, q, rng.standard_normal(3), k_f, r_d, R, eps)
+        wn = np.linalg.norm(w)
+        u = w / wn
+        want = -(k_f * wn * wn / rho) * (n @ u) * (n - u * (u @ n))
+        np.testing.assert_allclose(f, want, rtol=1e-10, atol=1e-14)
+        assert abs(f @ w) <= 1e-12 * np.linalg.norm(f) * wn
+        if n @ w < 0:                                        # approaching: pushed outwards
+            assert f @ n >= -1e-15
+        for w_special in (2.0 * n, np.cross(n, rng.standard_normal(3))):
+            f0, _ = oracle.pair_force_heuristic(1, p, w_special, q, np.zeros(3), k_f, r_d, R, eps)
+            assert np.linalg.norm(f0) <= 1e-12 * k_f / rho
+
+
+def test_velocity_current_field_does_no_work():
+    """The velocity-current field is orthogonal to w as well, so the discrete energy
+    identity of the rotation-vector field holds for it too (k_a = d_a = 0, static)."""
+    pb = scenes.config1()
+    pb.agents.k_a[:] = 0
+    pb.agents.d_a[:] = 0
+    pb.agents.heuristic = np.ones(pb.agents.n, np.int32)
+    pb.query.v0[:] = [1.5, 0.3, -0.2]
+    pb.params.n_steps = 300
+    res = oracle.rollout(pb)
+    h = 0.5 * float(np.float32(pb.params.dt)) * float(np.float32(pb.params.inv_mass))
+    v2 = np.sum(res.vel ** 2, -1)
+    assert np.abs(res.force).max() > 1.0
+    np.testing.assert_allclose(v2[:, 1:] - v2[:, :-1], h * h * np.sum(res.ftot ** 2, -1), rtol=1e-7,
+                               atol=1e-12 * v2.max())
+
+
+def test_mixed_heuristics_are_independent():
+    """In a heterogeneous ensemble every agent's rollout equals its rollout alone."""
+    pb = scenes.tiny(23, n_points=60, n_agents=6, n_steps=40)
+    pb.agents.heuristic = np.array([0, 1, 2, 2, 1, 0], np.int32)
+    pb.agents.k_f = np.where(pb.agents.heuristic == 2, 1e-5, 0.02).astype(np.float32)
+    full = oracle.rollout(pb)
+    for i in range(pb.agents.n):
+        sub = copy.deepcopy(pb)
+        sub.agents = pb.agents.subset([i])
+        one = oracle.rollout(sub)
+        np.testing.assert_array_equal(one.traj[0], full.traj[i])

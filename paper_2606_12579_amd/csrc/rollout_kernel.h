@@ -56,6 +56,7 @@ using namespace dev;
 // Words per (shard, agent) exchange slot: Fx, Fy, Fz, min r2 (the rest pads the slot
 // to its own 128-byte line).
 constexpr int kSlotWords = 4;
+static_assert(kSlotWords == 4, "the one-instruction exchange maps lane l to word l of a slot row");
 
 // Launch-time layout of the shard in LDS.
 struct Lay {
@@ -291,26 +292,45 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
             }
         };
         // device-scope exchange of the group's shard totals, summed in shard order (run by the lead wave)
-        auto exchange = [&](float &Fx_, float &Fy_, float &Fz_, float &m2_) {
-            const unsigned tag = (unsigned)k;
-            if (lane < AW) {
-                unsigned long long *slot = xc.partial + kSlotWords * (((size_t)(par * GW + gw) * S + s) * AW + lane);
+        // Cross-shard exchange of the group's partial sums, in two halves so that work
+        // independent of the total force runs while the words travel.  When the group's
+        // 4 S AW words fit one wave, one store instruction publishes this shard's slot
+        // (lane l holds component l & 3 of agent l >> 2) and one load instruction polls
+        // every slot of the group; otherwise each lane handles whole slots.
+        constexpr bool kVecX = 4 * AW <= 64;
+        const unsigned tag = (unsigned)k;
+        unsigned long long *const garea = xc.partial + kSlotWords * ((size_t)(par * GW + gw) * S * AW);
+        auto publish = [&](float Fx_, float Fy_, float Fz_, float m2_) {
+            if (kVecX && 4 * S * AW <= 64) {
+                const int pa = lane >> 2, pc = lane & 3;
+                float v;
+                if constexpr (AW == 1) {
+                    v = pc == 0 ? Fx_ : pc == 1 ? Fy_ : pc == 2 ? Fz_ : m2_;
+                } else {
+                    const int src = (pa < AW ? pa : 0) << 2;      // byte address of agent pa's lane
+                    const float x = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(Fx_)));
+                    const float y = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(Fy_)));
+                    const float z = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(Fz_)));
+                    const float m = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(m2_)));
+                    v = pc == 0 ? x : pc == 1 ? y : pc == 2 ? z : m;
+                }
+                if (lane < 4 * AW) st64_agent(garea + (size_t)s * AW * kSlotWords + lane, xword(v, tag));
+            } else if (lane < AW) {
+                unsigned long long *slot = garea + kSlotWords * ((size_t)s * AW + lane);
                 st64_agent(slot, xword(Fx_, tag));
                 st64_agent(slot + 1, xword(Fy_, tag));
                 st64_agent(slot + 2, xword(Fz_, tag));
                 st64_agent(slot + 3, xword(m2_, tag));
             }
-            // each lane polls the four words of one (shard, agent) slot until all carry this step's tag
-            for (int l = lane; l < S * AW; l += 64) {
-                const unsigned long long *slot =
-                    xc.partial + kSlotWords * (((size_t)(par * GW + gw) * S + l / AW) * AW + l % AW);
-                unsigned long long q0, q1, q2, q3;
+        };
+        auto collect = [&](float &Fx_, float &Fy_, float &Fz_, float &m2_) {
+            if (kVecX && 4 * S * AW <= 64) {
+                const bool poller = lane < 4 * S * AW;
+                unsigned long long q = 0;
                 unsigned spins = 0;
-                while (true) {                       // the four loads are in flight together
-                    q0 = ld64_agent(slot); q1 = ld64_agent(slot + 1); q2 = ld64_agent(slot + 2);
-                    q3 = ld64_agent(slot + 3);
-                    if (xtag(q0) == tag && xtag(q1) == tag && xtag(q2) == tag && xtag(q3) == tag) break;
-                    __builtin_amdgcn_s_sleep(2);
+                while (true) {
+                    if (poller) q = ld64_agent(garea + lane);
+                    if (__all(!poller || xtag(q) == tag)) break;
                     if ((++spins & 63u) == 0) {
                         if (ld_agent(xc.status) != 0u) break;
                         if (__builtin_amdgcn_s_memrealtime() - t_start > kWatchdogTicks) {
@@ -319,7 +339,28 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
                         }
                     }
                 }
-                xtw[l] = make_float4(xval(q0), xval(q1), xval(q2), xval(q3));
+                if (poller) reinterpret_cast<float *>(xtw)[lane] = xval(q);
+            } else {
+                // each lane polls the four words of one (shard, agent) slot until all carry this step's tag
+                for (int l = lane; l < S * AW; l += 64) {
+                    const unsigned long long *slot = garea + kSlotWords * (size_t)l;
+                    unsigned long long q0, q1, q2, q3;
+                    unsigned spins = 0;
+                    while (true) {                   // the four loads are in flight together
+                        q0 = ld64_agent(slot); q1 = ld64_agent(slot + 1); q2 = ld64_agent(slot + 2);
+                        q3 = ld64_agent(slot + 3);
+                        if (xtag(q0) == tag && xtag(q1) == tag && xtag(q2) == tag && xtag(q3) == tag) break;
+                        __builtin_amdgcn_s_sleep(2);
+                        if ((++spins & 63u) == 0) {
+                            if (ld_agent(xc.status) != 0u) break;
+                            if (__builtin_amdgcn_s_memrealtime() - t_start > kWatchdogTicks) {
+                                st_agent(xc.status, 1u);
+                                break;
+                            }
+                        }
+                    }
+                    xtw[l] = make_float4(xval(q0), xval(q1), xval(q2), xval(q3));
+                }
             }
             __builtin_amdgcn_wave_barrier();
             float4 a4 = xtw[a_w];
@@ -375,8 +416,9 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
                     acc.x += q.x; acc.y += q.y; acc.z += q.z; acc.w = fminf(acc.w, q.w);
                 }
                 Fx = acc.x; Fy = acc.y; Fz = acc.z; m2 = acc.w;
-                if constexpr (!PROBE) costs_early();       // overlaps the other shards' arrival
-                if (S > 1) exchange(Fx, Fy, Fz, m2);
+                if (S > 1) publish(Fx, Fy, Fz, m2);
+                if constexpr (!PROBE) costs_early();       // overlaps the exchange
+                if (S > 1) collect(Fx, Fy, Fz, m2);
                 finish(Fx, Fy, Fz, m2);
                 if (lane < AW) {
                     tot[2 * lane] = make_float4(px, py, pz, vx);
@@ -390,8 +432,9 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
                 px = a.x; py = a.y; pz = a.z; vx = a.w; vy = b.x; vz = b.y;
             }
         } else {
+            if (S > 1) publish(Fx, Fy, Fz, m2);
             if constexpr (!PROBE) costs_early();
-            if (S > 1) exchange(Fx, Fy, Fz, m2);
+            if (S > 1) collect(Fx, Fy, Fz, m2);
             finish(Fx, Fy, Fz, m2);
             if constexpr (PROBE) break;
         }

@@ -150,6 +150,53 @@ gmapp_status gmapp_force_probe(gmapp_ctx *ctx, const gmapp_scene *scene, const g
                                const float *p, const float *v, float t, const gmapp_params *params, float *f_r,
                                float *rho_min, void *stream);
 
+/* Closed planning loop (Sec. V-B, planner architecture; selection rule of Sec. IV-A
+ * across cycles).  The robot is a point mass like the agents.  Cycle c = 0 ..
+ * n_cycles - 1 runs, in stream order and with no host round trip:
+ *  1. the rollout of gmapp_rollout from the robot's state (row c * ctrl_steps of
+ *     out->robot) at t0_c = query->t0 + c * ctrl_steps * ctrl_dt (computed in double,
+ *     rounded to float), its incumbent being i* of cycle c - 1 (query->incumbent for
+ *     c = 0), so that C_best is the incumbent's cost in this cycle;
+ *  2. ctrl_steps control steps of the robot under the selected agent i*_c: at each,
+ *     the repulsive force of i*_c's field at the robot's state and time
+ *     t0_c + j ctrl_dt (the control thread's query), the attractor with i*_c's
+ *     k_a, d_a, and the integration of gmapp_rollout with dt = ctrl_dt.
+ * N_sw counts the cycles whose i* differs from a valid previous i*.  If a cycle's
+ * i* is negative (an error status) the robot keeps its state for that cycle.
+ * Heterogeneous agents are allowed.  All outputs are device memory:
+ *   robot       [n_cycles * ctrl_steps + 1][6]  p, v of the robot; row 0 = query p0, v0
+ *   robot_clear [n_cycles * ctrl_steps] or NULL  rho_min at each control step
+ *   best        [n_cycles]                       i* of each cycle
+ *   cost        [n_cycles][N_a][5]               each cycle's costs (as gmapp_outputs.cost)
+ *   n_switches  [1]                              N_sw
+ * EINVAL for n_cycles < 1, ctrl_steps < 1, ctrl_dt not finite and > 0, N_a = 0 or
+ * a NULL required output. */
+typedef struct {
+    int32_t n_cycles;     /* planning cycles, >= 1 */
+    int32_t ctrl_steps;   /* control steps of the robot per cycle, >= 1 */
+    float ctrl_dt;        /* control period [s] (0.01 = 100 Hz) */
+} gmapp_loop_config;
+
+typedef struct {
+    float *robot;
+    float *robot_clear;
+    int32_t *best;
+    float *cost;
+    int32_t *n_switches;
+} gmapp_loop_outputs;
+
+gmapp_status gmapp_plan_loop(gmapp_ctx *ctx, const gmapp_scene *scene, const gmapp_agents *agents,
+                             const gmapp_query *query, const gmapp_params *params, const gmapp_loop_config *cfg,
+                             const gmapp_loop_outputs *out, void *stream);
+
+/* The control thread's query (Sec. V-B): the repulsive force f_r (Alg. 1, the
+ * agent's own field) of the agent whose index is read from agent (device int32
+ * [1]) at the state (device [6]: p, v) and time t, and rho_min.  f_r: device [3];
+ * rho_min: device [1] or NULL.  An index outside [0, N_a) gives NaN outputs. */
+gmapp_status gmapp_control_force(gmapp_ctx *ctx, const gmapp_scene *scene, const gmapp_agents *agents,
+                                 const int32_t *agent, const float *state, float t, const gmapp_params *params,
+                                 float *f_r, float *rho_min, void *stream);
+
 /* Tiling of the rollout kernel.  An agent group is `agents` agents (power of two)
  * sharing the lanes of one wavefront (group = 1: agents 1..64) or of the whole
  * workgroup (group = 2: agents 1..8, 4/8/16 waves); a workgroup has `waves`

@@ -10,6 +10,7 @@ which holds none of the method's arithmetic.
   rollout_grad(problem)     dC_i/d(k_a, d_a, k_f, omega) by dual numbers (C code)
   costs(...)                Eqs. (16)-(20) on a given trajectory
   select(...)               the selection rule
+  plan_loop(problem, ...)   the closed planning loop: rollouts, selection across cycles, control steps
   perception.*              back-projection and voxel-centre sphere world (numpy)
 """
 from __future__ import annotations
@@ -209,6 +210,74 @@ def pair_force_heuristic(heur, p, w, q, omega, k_f, r_d, R, eps, cutoff=0, band=
     lib.oracle_pair_force_h(int(heur), *[a[1] for a in arrs], float(k_f), float(r_d), float(R), float(eps),
                             int(cutoff), float(band), f.ctypes.data_as(_dp), ctypes.byref(rho))
     return f, rho.value
+
+
+@dataclasses.dataclass
+class LoopResult:
+    robot: np.ndarray        # [n_cycles * ctrl_steps + 1, 6] p, v of the robot
+    robot_clear: np.ndarray  # [n_cycles * ctrl_steps] rho_min at each control step
+    best: np.ndarray         # [n_cycles] i* of each cycle
+    cost: np.ndarray         # [n_cycles, N_a, 5]
+    n_switches: int          # N_sw
+    t0: np.ndarray           # [n_cycles] start time of each cycle (FP32 values)
+
+
+def plan_loop(problem, n_cycles, ctrl_steps, ctrl_dt) -> LoopResult:
+    """The closed planning loop (Sec. V-B) with a point-mass robot, in the order
+    the paper describes it.  Each cycle c:
+      1. takes the robot's current state as the start of every agent and rolls all
+         agents out over N_k steps (rollout above: Eqs. 6-11 and 15-20), selecting
+         i* with the rule of Sec. IV-A against the incumbent, the previous cycle's
+         i* (the query's incumbent at c = 0); the cycle starts at
+         t0_c = t0 + c ctrl_steps ctrl_dt, rounded to FP32 like every time input;
+      2. counts an agent switch when i* differs from a valid previous i*;
+      3. moves the robot ctrl_steps control steps under i*: at step j the repulsive
+         force of i*'s own field at the robot's state and time t0_c + j ctrl_dt
+         (repulsion above, for that agent alone), the attractor of Eq. (7) with
+         i*'s gains, and the explicit integration of Eqs. 9-11 with dt = ctrl_dt.
+    A negative i* (no agents) leaves the robot where it is for that cycle."""
+    import copy
+    pb = copy.deepcopy(problem)
+    ag, q, prm = pb.agents, pb.query, pb.params
+    dt_c = float(np.float32(ctrl_dt))
+    h = 0.5 * dt_c * float(np.float32(prm.inv_mass))
+    goal = np.asarray(q.goal, np.float64)
+    p = np.asarray(q.p0, np.float64).copy()
+    v = np.asarray(q.v0, np.float64).copy()
+    inc = int(q.incumbent)
+    t0 = float(np.float32(q.t0))
+    robot = [np.concatenate([p, v])]
+    clear, best, cost, t0s = [], [], [], []
+    n_sw = 0
+    for c in range(int(n_cycles)):
+        t0c = float(np.float32(t0 + float(c) * float(ctrl_steps) * dt_c))
+        t0s.append(t0c)
+        q.p0, q.v0, q.t0, q.incumbent = p.copy(), v.copy(), t0c, inc
+        r = rollout(pb)
+        i = int(r.best)
+        best.append(i)
+        cost.append(r.cost)
+        if inc >= 0 and i >= 0 and i != inc:
+            n_sw += 1
+        one = copy.deepcopy(pb)
+        if 0 <= i < ag.n:
+            one.agents = ag.subset([i])
+            k_a, d_a = float(np.float32(ag.k_a[i])), float(np.float32(ag.d_a[i]))
+        for j in range(int(ctrl_steps)):
+            if not 0 <= i < ag.n:
+                robot.append(robot[-1].copy())
+                clear.append(np.nan)
+                continue
+            t = t0c + j * dt_c
+            rep = repulsion(one, p[None], v[None], t)
+            F = k_a * (goal - p) - d_a * v + rep.force[0]
+            v = v + h * F
+            p = p + dt_c * v
+            robot.append(np.concatenate([p, v]))
+            clear.append(float(rep.rho_min[0]))
+        inc = i
+    return LoopResult(np.array(robot), np.array(clear), np.array(best, np.int64), np.array(cost), n_sw,
+                      np.array(t0s))
 
 
 def interactions(problem) -> int:

@@ -261,6 +261,43 @@ gmapp_status gmapp_force_probe(gmapp_ctx *ctx, const gmapp_scene *scene, const g
                               static_cast<hipStream_t>(stream));
 }
 
+gmapp_status gmapp_plan_loop(gmapp_ctx *ctx, const gmapp_scene *scene, const gmapp_agents *agents,
+                             const gmapp_query *query, const gmapp_params *params, const gmapp_loop_config *cfg,
+                             const gmapp_loop_outputs *out, void *stream)
+{
+    gmapp_status st = check_ctx(ctx);
+    if (st) return st;
+    if ((st = check_scene(ctx, scene)) || (st = check_agents(ctx, agents)) || (st = check_params(ctx, params, true)))
+        return st;
+    if ((st = check_query(ctx, query))) return st;
+    if (!cfg) return fail(ctx, GMAPP_EINVAL, "loop config is NULL");
+    if (cfg->n_cycles < 1) return fail(ctx, GMAPP_EINVAL, "n_cycles must be >= 1");
+    if (cfg->ctrl_steps < 1) return fail(ctx, GMAPP_EINVAL, "ctrl_steps must be >= 1");
+    if (!finite(cfg->ctrl_dt) || !(cfg->ctrl_dt > 0.0f)) return fail(ctx, GMAPP_EINVAL, "ctrl_dt must be finite and > 0");
+    if (agents->n_agents < 1) return fail(ctx, GMAPP_EINVAL, "the planning loop needs at least one agent");
+    if (!out || !out->robot || !out->best || !out->cost || !out->n_switches)
+        return fail(ctx, GMAPP_EINVAL, "loop outputs robot, best, cost and n_switches must be non-NULL");
+    if ((long long)cfg->n_cycles * cfg->ctrl_steps > (long long)INT32_MAX)
+        return fail(ctx, GMAPP_ECAPACITY, "n_cycles x ctrl_steps exceeds 2^31 - 1");
+    gm::Tiling t = tiling_for(ctx, scene->n_points, agents->n_agents, params->n_steps, scene->n_seg, params->cutoff);
+    return gm::launch_plan_loop(ctx, dev_scene(scene), dev_agents(agents), dev_params(params, query), t, *cfg, *out,
+                                static_cast<hipStream_t>(stream));
+}
+
+gmapp_status gmapp_control_force(gmapp_ctx *ctx, const gmapp_scene *scene, const gmapp_agents *agents,
+                                 const int32_t *agent, const float *state, float t, const gmapp_params *params,
+                                 float *f_r, float *rho_min, void *stream)
+{
+    gmapp_status st = check_ctx(ctx);
+    if (st) return st;
+    if ((st = check_scene(ctx, scene)) || (st = check_agents(ctx, agents)) || (st = check_params(ctx, params, false)))
+        return st;
+    if (!agent || !state || !f_r) return fail(ctx, GMAPP_EINVAL, "agent, state and f_r must be non-NULL");
+    if (!finite(t)) return fail(ctx, GMAPP_EINVAL, "t must be finite");
+    return gm::launch_control_force(ctx, dev_scene(scene), dev_agents(agents), dev_params(params, nullptr), agent,
+                                    state, t, f_r, rho_min, static_cast<hipStream_t>(stream));
+}
+
 gmapp_status gmapp_depth_to_points(gmapp_ctx *ctx, const float *depth, int32_t w, int32_t h, const float K[4],
                                    const float T_wc[12], float *x, float *y, float *z, void *stream)
 {

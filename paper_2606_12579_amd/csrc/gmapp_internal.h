@@ -40,6 +40,8 @@ struct Prm {
     float p0[3], v0[3], goal[3];
     int incumbent;
     float t0;
+    const float *start = nullptr;   // device [6] p0, v0 in place of p0, v0 (closed loop) or nullptr
+    const int *inc_dev = nullptr;   // device incumbent in place of `incumbent` (closed loop) or nullptr
 };
 
 struct Out {
@@ -190,6 +192,12 @@ inline gmapp_status hip_fail(gmapp_ctx *ctx, hipError_t e, const char *what)
 gmapp_status launch_rollout(gmapp_ctx *ctx, const Scn &sc, const Agt &ag, const Prm &pr, const Out &out,
                             const Probe *probe, const Tiling &t, hipStream_t stream);
 Tiling choose_tiling(const gmapp_ctx *ctx, long long n_points, int n_agents, int n_steps, int n_seg, int cutoff);
+
+// closed planning loop and the control query (control.hip)
+gmapp_status launch_plan_loop(gmapp_ctx *ctx, const Scn &sc, const Agt &ag, const Prm &pr0, const Tiling &t,
+                              const gmapp_loop_config &cfg, const gmapp_loop_outputs &o, hipStream_t stream);
+gmapp_status launch_control_force(gmapp_ctx *ctx, const Scn &sc, const Agt &ag, const Prm &pr, const int *agent,
+                                  const float *state, float t, float *f_r, float *rho_min, hipStream_t stream);
 
 // adjoint (adjoint.hip)
 gmapp_status launch_adjoint(gmapp_ctx *ctx, const Scn &sc, const Agt &ag, const Prm &pr, const float *grad_total,

@@ -186,6 +186,9 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
         px = pb.p[3 * ai]; py = pb.p[3 * ai + 1]; pz = pb.p[3 * ai + 2];
         vx = pb.v[3 * ai]; vy = pb.v[3 * ai + 1]; vz = pb.v[3 * ai + 2];
         t_fixed = pb.t;
+    } else if (pr.start) {
+        px = pr.start[0]; py = pr.start[1]; pz = pr.start[2];
+        vx = pr.start[3]; vy = pr.start[4]; vz = pr.start[5];
     } else {
         px = pr.p0[0]; py = pr.p0[1]; pz = pr.p0[2];
         vx = pr.v0[0]; vy = pr.v0[1]; vz = pr.v0[2];
@@ -444,7 +447,8 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
     if (writer) {
         const float N = (float)pr.n_steps;
         const float Cg = sg / N, Co = so / N;
-        const float e1x = gx - pr.p0[0], e1y = gy - pr.p0[1], e1z = gz - pr.p0[2];
+        const float *p0 = pr.start ? pr.start : pr.p0;
+        const float e1x = gx - p0[0], e1y = gy - p0[1], e1z = gz - p0[2];
         const float d1 = sqrtf(fmaf(e1z, e1z, fmaf(e1y, e1y, e1x * e1x)));
         float Cp;
         if (sp >= d1) Cp = (sp > 0.0f) ? 1.0f - d1 / sp : 0.0f;
@@ -468,7 +472,8 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     if constexpr (!PROBE) {
         // argmin over C_i (ties -> lowest index, NaN never wins), incumbent rule
-        const int inc = (pr.incumbent >= 0 && pr.incumbent < ag.n) ? pr.incumbent : -1;
+        const int inc_in = pr.inc_dev ? pr.inc_dev[0] : pr.incumbent;
+        const int inc = (inc_in >= 0 && inc_in < ag.n) ? inc_in : -1;
         const float bound = inc >= 0 ? pr.alpha * out.cost[5 * (size_t)inc + 4] : INFINITY;
         float bv = INFINITY;
         int bi = -1;

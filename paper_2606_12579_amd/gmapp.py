@@ -47,6 +47,15 @@ class Agents(ctypes.Structure):
 H_CF_OMEGA, H_MFI_VEL, H_APF = 0, 1, 2
 
 
+class LoopConfig(ctypes.Structure):
+    _fields_ = [("n_cycles", ctypes.c_int32), ("ctrl_steps", ctypes.c_int32), ("ctrl_dt", ctypes.c_float)]
+
+
+class LoopOutputs(ctypes.Structure):
+    _fields_ = [("robot", ctypes.c_void_p), ("robot_clear", ctypes.c_void_p), ("best", ctypes.c_void_p),
+                ("cost", ctypes.c_void_p), ("n_switches", ctypes.c_void_p)]
+
+
 class Query(ctypes.Structure):
     _fields_ = [("p0", ctypes.c_float * 3), ("v0", ctypes.c_float * 3), ("goal", ctypes.c_float * 3),
                 ("incumbent", ctypes.c_int32), ("t0", ctypes.c_float)]
@@ -142,6 +151,10 @@ def load_library(path: str = LIB_PATH):
         "gmapp_force_probe": (ctypes.c_int32, [vp, P(Scene), P(Agents), vp, vp, ctypes.c_float, P(Params), vp, vp,
                                                vp]),
         "gmapp_set_tiling": (ctypes.c_int32, [vp, P(Tiling)]),
+        "gmapp_plan_loop": (ctypes.c_int32, [vp, P(Scene), P(Agents), P(Query), P(Params), P(LoopConfig),
+                                             P(LoopOutputs), vp]),
+        "gmapp_control_force": (ctypes.c_int32, [vp, P(Scene), P(Agents), vp, vp, ctypes.c_float, P(Params), vp, vp,
+                                                 vp]),
         "gmapp_rollout_backward": (ctypes.c_int32, [vp, P(Scene), P(Agents), P(Query), P(Params), vp, ctypes.c_int32,
                                                     vp, vp, vp, vp, vp]),
         "gmapp_depth_to_points": (ctypes.c_int32, [vp, vp, ctypes.c_int32, ctypes.c_int32, P(ctypes.c_float),
@@ -569,6 +582,44 @@ class Context:
         prm = make_params(params)
         st = self.lib.gmapp_force_probe(self.handle, ctypes.byref(sc), ctypes.byref(ag), _ptr(p), _ptr(v),
                                         float(t), ctypes.byref(prm), _ptr(f), _ptr(r), self._stream(stream))
+        self._raise(st)
+        return f, r
+
+    def plan_loop(self, scene: DeviceScene, agents: DeviceAgents, query, params, n_cycles, ctrl_steps, ctrl_dt,
+                  clear=True, stream=None):
+        """gmapp_plan_loop: the closed planning loop. Returns robot [n_cycles*ctrl_steps + 1, 6] (p, v),
+        robot_clear [n_cycles*ctrl_steps] (or None), best [n_cycles], cost [n_cycles, N_a, 5], n_switches [1]."""
+        import torch
+        na, dev = agents.n, self.device
+        T = int(n_cycles) * int(ctrl_steps)
+        out = {"robot": torch.empty((T + 1, 6), dtype=torch.float32, device=dev),
+               "robot_clear": torch.empty(T, dtype=torch.float32, device=dev) if clear else None,
+               "best": torch.empty(max(int(n_cycles), 0), dtype=torch.int32, device=dev),
+               "cost": torch.empty((max(int(n_cycles), 0), na, 5), dtype=torch.float32, device=dev),
+               "n_switches": torch.empty(1, dtype=torch.int32, device=dev)}
+        sc, ag = _scene_struct(scene, dev), _agents_struct(agents, dev)
+        q, p = make_query(query), make_params(params)
+        cfg = LoopConfig(int(n_cycles), int(ctrl_steps), float(ctrl_dt))
+        lo = LoopOutputs(_ptr(out["robot"]), _ptr(out["robot_clear"]), _ptr(out["best"]), _ptr(out["cost"]),
+                         _ptr(out["n_switches"]))
+        st = self.lib.gmapp_plan_loop(self.handle, ctypes.byref(sc), ctypes.byref(ag), ctypes.byref(q),
+                                      ctypes.byref(p), ctypes.byref(cfg), ctypes.byref(lo), self._stream(stream))
+        self._raise(st)
+        return out
+
+    def control_force(self, scene: DeviceScene, agents: DeviceAgents, agent, state, t, params, stream=None):
+        """gmapp_control_force: f_r [3] and rho_min [1] of the agent whose index is the device int32 `agent` [1]
+        at the device state [6] (p, v) and time t."""
+        import torch
+        dev = self.device
+        _check_tensor(agent, "agent", 1, torch.int32, dev)
+        _check_tensor(state, "state", 6, torch.float32, dev)
+        f = torch.empty(3, dtype=torch.float32, device=dev)
+        r = torch.empty(1, dtype=torch.float32, device=dev)
+        sc, ag = _scene_struct(scene, dev), _agents_struct(agents, dev)
+        prm = make_params(params)
+        st = self.lib.gmapp_control_force(self.handle, ctypes.byref(sc), ctypes.byref(ag), _ptr(agent), _ptr(state),
+                                          float(t), ctypes.byref(prm), _ptr(f), _ptr(r), self._stream(stream))
         self._raise(st)
         return f, r
 

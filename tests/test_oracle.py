@@ -487,3 +487,110 @@ def test_mixed_heuristics_are_independent():
         sub.agents = pb.agents.subset([i])
         one = oracle.rollout(sub)
         np.testing.assert_array_equal(one.traj[0], full.traj[i])
+
+
+# ---------------------------------------------------------------- closed planning loop (Sec. V-B)
+
+def test_loop_control_steps_reproduce_the_selected_rollout():
+    """With the control period equal to dt and N_k control steps per cycle, the
+    robot's control steps integrate exactly the selected agent's rollout, so each
+    cycle ends at that agent's p^(N_k+1), v^(N_k) and records its clearances; the
+    control integration (numpy) and the rollout (C) are separate codes."""
+    pb = scenes.tiny(8, n_points=200, n_agents=5, n_steps=30, moving=True)
+    N, C = pb.params.n_steps, 3
+    res = oracle.plan_loop(pb, C, N, pb.params.dt)
+    inc = pb.query.incumbent
+    for c in range(C):
+        sub = copy.deepcopy(pb)
+        row = res.robot[c * N]
+        sub.query.p0, sub.query.v0, sub.query.t0, sub.query.incumbent = row[:3], row[3:], res.t0[c], inc
+        r = oracle.rollout(sub)
+        i = r.best
+        assert i == res.best[c]
+        np.testing.assert_allclose(res.robot[(c + 1) * N, :3], r.traj[i, N], rtol=0, atol=1e-12)
+        np.testing.assert_allclose(res.robot[(c + 1) * N, 3:], r.vel[i, N], rtol=0, atol=1e-10)
+        np.testing.assert_allclose(res.robot_clear[c * N:(c + 1) * N], r.min_clear[i], rtol=1e-12, atol=0)
+        inc = i
+
+
+def test_loop_grouping_of_control_steps():
+    """While i* stays the same, the robot's path is the same sequence of control
+    steps however they are grouped into cycles (moving spheres, so each step's
+    time matters), and cycle c starts at t0 + c ctrl_steps ctrl_dt."""
+    pb = scenes.tiny(8, n_points=200, n_agents=5, n_steps=30, moving=True)
+    pb.query.t0 = 0.0125
+    a = oracle.plan_loop(pb, 2, 10, 0.005)
+    b = oracle.plan_loop(pb, 4, 5, 0.005)
+    assert len(set(a.best.tolist() + b.best.tolist())) == 1
+    # each cycle's start time is rounded to FP32 (about 1e-9 s here, the spheres move 0.2 m/s)
+    np.testing.assert_allclose(a.robot, b.robot, rtol=0, atol=1e-8)
+    np.testing.assert_allclose(a.robot_clear, b.robot_clear, rtol=0, atol=1e-8)
+    dt = float(np.float32(0.005))
+    assert b.t0.tolist() == [float(np.float32(float(np.float32(0.0125)) + 5 * c * dt)) for c in range(4)]
+
+
+def test_loop_without_obstacles_is_the_damped_oscillator():
+    """No spheres: every agent has the same cost, so i* stays agent 0 and N_sw = 0,
+    and the robot follows x_{n+1} = M x_n + b per axis, whose closed form is
+    x_n = x* + M^n (x_0 - x*) with the fixed point x* = (goal, 0)."""
+    pb = scenes.tiny(3, n_points=0, n_agents=4, n_steps=20)
+    C, J, dtc = 5, 7, 0.004
+    res = oracle.plan_loop(pb, C, J, dtc)
+    assert res.best.tolist() == [0] * C and res.n_switches == 0
+    dt = float(np.float32(dtc))
+    ka, da = float(pb.agents.k_a[0]), float(pb.agents.d_a[0])
+    h = 0.5 * dt * float(np.float32(pb.params.inv_mass))
+    M = np.array([[1.0 - dt * h * ka, dt * (1.0 - h * da)], [-h * ka, 1.0 - h * da]])
+    g = np.asarray(pb.query.goal, np.float64)
+    x0 = np.stack([np.asarray(pb.query.p0, np.float64), np.asarray(pb.query.v0, np.float64)])   # [2, 3]
+    for n in (1, 2, 13, C * J):
+        Mn = np.linalg.matrix_power(M, n)
+        want = np.stack([g, np.zeros(3)]) + Mn @ (x0 - np.stack([g, np.zeros(3)]))
+        np.testing.assert_allclose(res.robot[n, :3], want[0], rtol=0, atol=1e-12)
+        np.testing.assert_allclose(res.robot[n, 3:], want[1], rtol=0, atol=1e-10)
+    assert np.all(np.isinf(res.robot_clear))
+
+
+def brute_select(total, incumbent, alpha):
+    """The selection rule written out: the lowest-cost agent among those below
+    alpha times the incumbent's cost (all agents without an incumbent), lowest
+    index on ties, NaN never chosen; the incumbent when no agent qualifies."""
+    best = -1
+    for i, c in enumerate(total):
+        if c != c or (incumbent >= 0 and not c < alpha * total[incumbent]):
+            continue
+        if best < 0 or c < total[best]:
+            best = i
+    return best if best >= 0 else incumbent
+
+
+def test_loop_selection_and_switch_count():
+    """Every cycle's i* is the selection rule (brute-force pinned) applied to that
+    cycle's costs with the previous i* as incumbent, and N_sw counts the changes;
+    the object scene with a mixed ensemble and alpha = 0.99 switches twice."""
+    pb = scenes.config2(seed=7, n_agents=24, n_steps=100, n_points=5000)
+    pb.agents = scenes.multi_agents(np.random.default_rng(7), 24)
+    pb.params.alpha = 0.99
+    res = oracle.plan_loop(pb, 10, 10, 0.01)
+    inc, sw = pb.query.incumbent, 0
+    for c in range(10):
+        assert res.best[c] == brute_select(res.cost[c][:, 4], inc, pb.params.alpha)
+        sw += int(inc >= 0 and res.best[c] != inc)
+        inc = res.best[c]
+    assert res.n_switches == sw >= 2
+
+
+def test_loop_translation_covariance():
+    """Translating spheres, start and goal together translates the robot's path and
+    leaves every selection unchanged."""
+    pb = scenes.config1()
+    shift = np.array([0.25, -0.5, 1.0])
+    pt = copy.deepcopy(pb)
+    pt.scene = scenes.Scene((pb.scene.x + shift[0]).astype(np.float32), (pb.scene.y + shift[1]).astype(np.float32),
+                            (pb.scene.z + shift[2]).astype(np.float32), pb.scene.r_obs)
+    pt.query.p0 = np.asarray(pb.query.p0, np.float64) + shift
+    pt.query.goal = np.asarray(pb.query.goal, np.float64) + shift
+    a, b = oracle.plan_loop(pb, 4, 8, 0.01), oracle.plan_loop(pt, 4, 8, 0.01)
+    assert a.best.tolist() == b.best.tolist()
+    # the FP32 rounding of the shifted points moves each sphere by up to 6e-8 m
+    np.testing.assert_allclose(b.robot[:, :3] - shift, a.robot[:, :3], rtol=0, atol=1e-6)

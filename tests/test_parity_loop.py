@@ -1,0 +1,170 @@
+"""GPU parity of the closed planning loop (gmapp_plan_loop: rollouts chained on the
+device, selection across cycles, control steps under the selected agent) and of
+the control thread's force query (gmapp_control_force) against the FP64 oracle,
+through the C ABI."""
+import copy
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2606_12579_amd import scenes
+from tests import gpu_util as gu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_2606_12579_amd import gmapp
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = gmapp.Context(0)
+    yield c
+    c.close()
+
+
+def _log(msg):
+    print(msg, flush=True)
+
+
+def _multi(pb, seed=11):
+    pb = copy.deepcopy(pb)
+    pb.agents = scenes.multi_agents(np.random.default_rng(seed), pb.agents.n)
+    return pb
+
+
+def _run(ctx, pb, C, J, dtc, tiling=None):
+    import torch
+    from paper_2606_12579_amd import gmapp
+    if tiling is not None:
+        ctx.set_tiling(*tiling)
+    else:
+        ctx.clear_tiling()
+    sc, ag = gmapp.scene_to_device(pb.scene), gmapp.agents_to_device(pb.agents)
+    out = ctx.plan_loop(sc, ag, pb.query, pb.params, C, J, dtc)
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+def _compare(pb, gpu, ref, pos_tol=gu.POS_TOL):
+    assert gpu["best"].tolist() == ref.best.tolist(), (gpu["best"].tolist(), ref.best.tolist())
+    assert int(gpu["n_switches"][0]) == ref.n_switches
+    pos_err = float(np.abs(gpu["robot"][:, :3].astype(np.float64) - ref.robot[:, :3]).max())
+    vel_err = float(np.abs(gpu["robot"][:, 3:].astype(np.float64) - ref.robot[:, 3:]).max())
+    assert pos_err <= pos_tol, f"robot position error {pos_err:.3e} m"
+    assert vel_err <= 10 * pos_tol, f"robot velocity error {vel_err:.3e} m/s"
+    rc, rr = gpu["robot_clear"].astype(np.float64), ref.robot_clear
+    fin = np.isfinite(rr)
+    assert np.array_equal(np.isfinite(rc), fin)
+    if fin.any():
+        assert np.abs(rc[fin] - rr[fin]).max() <= pos_err + 1e-6 + 1e-5 * rr[fin].max()
+    # each cycle's costs start from the robot's state, known to pos_err
+    tol = gu.cost_tolerances(pb, pos_err)
+    d = np.abs(gpu["cost"].astype(np.float64) - ref.cost)
+    for k in range(3):
+        assert d[..., k].max() <= tol[k], (k, d[..., k].max(), tol[k])
+    assert (d[..., 3] / np.maximum(np.abs(ref.cost[..., 3]), 1e-3)).max() <= tol[3]
+    return pos_err
+
+
+CASES = {
+    "config1": lambda: (scenes.config1(), 10, 10, 0.01),
+    "config1_multi": lambda: (_multi(scenes.config1()), 10, 10, 0.01),
+    "moving_multi": lambda: (_multi(scenes.tiny(8, n_points=200, n_agents=9, n_steps=50, moving=True)), 8, 5, 0.005),
+    "taper": lambda: (scenes.tiny(9, n_points=150, n_agents=6, n_steps=50, cutoff=1), 6, 8, 0.01),
+    "objects_switch": lambda: (_switching(), 10, 10, 0.01),
+}
+
+
+def _switching():
+    """Object scene, mixed ensemble, alpha = 0.99: the loop switches agents twice."""
+    pb = scenes.config2(seed=7, n_agents=24, n_steps=100, n_points=5000)
+    pb.agents = scenes.multi_agents(np.random.default_rng(7), 24)
+    pb.params.alpha = 0.99
+    return pb
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_plan_loop(ctx, case):
+    pb, C, J, dtc = CASES[case]()
+    _log(f"loop {case}: {C} cycles x {J} control steps of {dtc} s, N_a {pb.agents.n}, N_k {pb.params.n_steps}")
+    ref = oracle.plan_loop(pb, C, J, dtc)
+    for tiling in (None, (1, 8, 4, 0, 0, 2), (2, 1, 2, 0, 1, 1)):
+        gpu = _run(ctx, pb, C, J, dtc, tiling)
+        err = _compare(pb, gpu, ref)
+        _log(f"  tiling {tiling}: best {gpu['best'].tolist()} N_sw {int(gpu['n_switches'][0])} pos err {err:.2e}")
+    if case == "objects_switch":
+        assert ref.n_switches >= 2
+
+
+def test_loop_cycles_are_rollouts(ctx):
+    """Each cycle of the loop is gmapp_rollout from the robot's state at that cycle,
+    with the previous i* as incumbent: the same costs bit for bit."""
+    import torch
+    from paper_2606_12579_amd import gmapp
+    pb = _multi(scenes.config2(n_agents=24, n_steps=100, n_points=5000))
+    C, J, dtc = 5, 10, 0.01
+    gpu = _run(ctx, pb, C, J, dtc)
+    sc, ag = gmapp.scene_to_device(pb.scene), gmapp.agents_to_device(pb.agents)
+    inc = pb.query.incumbent
+    for c in range(C):
+        q = copy.deepcopy(pb.query)
+        row = gpu["robot"][c * J]
+        q.p0, q.v0, q.incumbent = row[:3].copy(), row[3:].copy(), inc
+        q.t0 = float(np.float32(float(np.float32(pb.query.t0)) + c * J * float(np.float32(dtc))))
+        out = ctx.rollout(sc, ag, q, pb.params, traj=False, min_clear=False)
+        torch.cuda.synchronize()
+        assert np.array_equal(out["cost"].cpu().numpy(), gpu["cost"][c]), c
+        assert int(out["best"].item()) == gpu["best"][c]
+        inc = int(gpu["best"][c])
+
+
+def test_control_force(ctx):
+    """The control query matches the oracle's response of that agent alone at given
+    states (teacher-forced bound), for every heuristic; an index outside [0, N_a)
+    gives NaN."""
+    import torch
+    from paper_2606_12579_amd import gmapp
+    for pb in (_multi(scenes.config1()), _multi(scenes.tiny(8, n_points=200, n_agents=9, n_steps=50, moving=True))):
+        ref = oracle.rollout(pb)
+        sc, ag = gmapp.scene_to_device(pb.scene), gmapp.agents_to_device(pb.agents)
+        worst = 0.0
+        for i in range(pb.agents.n):
+            one = copy.deepcopy(pb)
+            one.agents = pb.agents.subset([i])
+            for k in (1, pb.params.n_steps // 3, pb.params.n_steps):
+                p32 = ref.traj[i, k - 1].astype(np.float32)
+                v32 = ref.vel[i, k - 1].astype(np.float32)
+                t32 = np.float32(0.5 * k * pb.params.dt)
+                r = oracle.repulsion(one, p32[None].astype(np.float64), v32[None].astype(np.float64), float(t32))
+                state = torch.as_tensor(np.concatenate([p32, v32]), device="cuda")
+                idx = torch.tensor([i], dtype=torch.int32, device="cuda")
+                f, rho = ctx.control_force(sc, ag, idx, state, float(t32), pb.params)
+                torch.cuda.synchronize()
+                d = float(np.linalg.norm(f.cpu().numpy().astype(np.float64) - r.force[0]))
+                bound = float(gu.force_bound(r)[0])
+                assert d <= bound, (pb.name, i, k, d, bound)
+                worst = max(worst, d / max(bound, 1e-300))
+                np.testing.assert_allclose(rho.cpu().numpy(), r.rho_min, rtol=2e-6, atol=1e-9)
+        _log(f"{pb.name} control query: worst |dF|/bound {worst:.3f}")
+        state = torch.zeros(6, dtype=torch.float32, device="cuda")
+        for bad in (-1, pb.agents.n):
+            f, rho = ctx.control_force(sc, ag, torch.tensor([bad], dtype=torch.int32, device="cuda"), state, 0.0,
+                                       pb.params)
+            assert torch.isnan(f).all() and torch.isnan(rho).all()
+
+
+def test_loop_validation(ctx):
+    from paper_2606_12579_amd import gmapp
+    pb = scenes.tiny(5, n_points=37, n_agents=3, n_steps=10)
+    sc, ag = gmapp.scene_to_device(pb.scene), gmapp.agents_to_device(pb.agents)
+    for C, J, dtc in ((0, 5, 0.01), (2, 0, 0.01), (2, 5, 0.0), (2, 5, float("nan"))):
+        with pytest.raises(gmapp.GmappError) as ei:
+            ctx.plan_loop(sc, ag, pb.query, pb.params, C, J, dtc)
+        assert ei.value.status == gmapp.EINVAL
+    empty = gmapp.agents_to_device(pb.agents.subset([]))
+    with pytest.raises(gmapp.GmappError) as ei:
+        ctx.plan_loop(sc, empty, pb.query, pb.params, 2, 5, 0.01)
+    assert ei.value.status == gmapp.EINVAL

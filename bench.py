@@ -199,6 +199,45 @@ def heterogeneous_pass(ctx, dev, base_ms, reps=10):
             "over_homogeneous": ms / base_ms, "best": int(out["best"].item())}
 
 
+def closed_loop(ctx, dev, n_cycles=50, ctrl_steps=10, ctrl_dt=0.01, reps=3):
+    """The planner loop (Sec. V-B) on the config-2 scene: 64 agents, N_k = 100 (one
+    of the paper's horizons), 50 cycles of one rollout plus 10 control steps at
+    100 Hz each, all on the device. HIP events around the whole loop and around a
+    lone rollout of the same shape (its share of a cycle)."""
+    import numpy as np
+    import torch
+    from paper_2606_12579_amd import gmapp, scenes
+    pb = scenes.config2(n_steps=100)
+    sc, ag = gmapp.scene_to_device(pb.scene, dev), gmapp.agents_to_device(pb.agents, dev)
+    stream = torch.cuda.current_stream(dev)
+    out = ctx.plan_loop(sc, ag, pb.query, pb.params, n_cycles, ctrl_steps, ctrl_dt, stream=stream)
+    ro = ctx.rollout(sc, ag, pb.query, pb.params, traj=False, min_clear=False, stream=stream)
+    torch.cuda.synchronize()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    loop_ms, roll_ms = [], []
+    for _ in range(reps):
+        e[0].record(stream)
+        out = ctx.plan_loop(sc, ag, pb.query, pb.params, n_cycles, ctrl_steps, ctrl_dt, stream=stream)
+        e[1].record(stream)
+        e[2].record(stream)
+        ctx.rollout(sc, ag, pb.query, pb.params, traj=False, min_clear=False, out=ro, stream=stream)
+        e[3].record(stream)
+        torch.cuda.synchronize()
+        loop_ms.append(e[0].elapsed_time(e[1]))
+        roll_ms.append(e[2].elapsed_time(e[3]))
+    L, R = float(np.min(loop_ms)), float(np.min(roll_ms))
+    robot = out["robot"].cpu().numpy()
+    clear = out["robot_clear"].cpu().numpy()
+    goal = np.asarray(pb.query.goal, np.float64)
+    return {"workload": f"config-2 scene (N_O=50000 moving points), N_a=64, N_k=100; {n_cycles} cycles x "
+                        f"{ctrl_steps} control steps of {ctrl_dt} s",
+            "loop_ms": L, "cycle_ms": L / n_cycles, "rollout_ms": R,
+            "control_step_ms": max(L / n_cycles - R, 0.0) / ctrl_steps,
+            "n_switches": int(out["n_switches"].item()), "best": out["best"].cpu().numpy().tolist()[-5:],
+            "min_clearance_m": float(np.nanmin(clear)),
+            "final_goal_distance_m": float(np.linalg.norm(robot[-1, :3] - goal))}
+
+
 def batched_vs_per_scene(ctx, dev, reqs, proxy_steps=16):
     """The 512-request mix (N_O in [1k, 200k], N_a in {16, 64, 256}, N_k in [100, 1000]):
     one batched persistent launch (autotuned) against one gmapp_rollout launch per
@@ -283,6 +322,7 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="use the built-in tiling choice")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
     ap.add_argument("--no-heterogeneous", action="store_true", help="skip the mixed-heuristic ensemble timing")
+    ap.add_argument("--no-loop", action="store_true", help="skip the closed planning loop timing")
     ap.add_argument("--quantum", type=int, default=50, help="steps per request per server cycle")
     ap.add_argument("--batch-requests", type=int, default=512, help="requests of the batched / served mix")
     args = ap.parse_args()
@@ -379,6 +419,8 @@ def main():
     }
     if not args.no_heterogeneous:
         res["heterogeneous"] = heterogeneous_pass(ctx, dev, avg_kernel_s * 1e3)
+    if not args.no_loop:
+        res["closed_loop"] = closed_loop(ctx, dev)
     if not args.no_perception:
         res["perception"] = perception_pass(ctx, dev)
     if not args.no_adjoint:

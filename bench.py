@@ -199,6 +199,35 @@ def heterogeneous_pass(ctx, dev, base_ms, reps=10):
             "over_homogeneous": ms / base_ms, "best": int(out["best"].item())}
 
 
+def pose_pass(ctx, dev, base_ms, reps=10):
+    """The headline scene and horizon (N_O=50,000 moving points, N_k=500) with 64
+    6-D pose agents (random start and goal rotors, jittered rotational gains).
+    HIP events around each launch; the library may use fewer shards than for
+    point masses when the pose kernel's registers limit co-residency."""
+    import numpy as np
+    import torch
+    from paper_2606_12579_amd import gmapp, scenes
+    pb = scenes.config2()
+    rng = np.random.default_rng(21)
+    pa, pq = scenes.pose_agents(rng, pb.agents.n), scenes.pose_query(rng)
+    sc, ag = gmapp.scene_to_device(pb.scene, dev), gmapp.agents_to_device(pb.agents, dev)
+    dpa = gmapp.pose_agents_to_device(pa, dev)
+    stream = torch.cuda.current_stream(dev)
+    out = ctx.rollout_pose(sc, ag, dpa, pb.query, pq, pb.params, stream=stream)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for e0, e1 in ev:
+        e0.record(stream)
+        ctx.rollout_pose(sc, ag, dpa, pb.query, pq, pb.params, out=out, stream=stream)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    ms = float(np.mean([e0.elapsed_time(e1) for e0, e1 in ev]))
+    inter = float(pb.agents.n) * pb.params.n_steps * pb.scene.n
+    return {"workload": "config-2 scene, N_a=64 6-D pose agents (Spin(3) x| R^3), N_k=500",
+            "kernel_ms_mean": ms, "interactions_per_s": inter / (ms * 1e-3), "over_point_mass": ms / base_ms,
+            "best": int(out["best"].item())}
+
+
 def closed_loop(ctx, dev, n_cycles=50, ctrl_steps=10, ctrl_dt=0.01, reps=3):
     """The planner loop (Sec. V-B) on the config-2 scene: 64 agents, N_k = 100 (one
     of the paper's horizons), 50 cycles of one rollout plus 10 control steps at
@@ -323,6 +352,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
     ap.add_argument("--no-heterogeneous", action="store_true", help="skip the mixed-heuristic ensemble timing")
     ap.add_argument("--no-loop", action="store_true", help="skip the closed planning loop timing")
+    ap.add_argument("--no-pose", action="store_true", help="skip the 6-D pose-agent timing")
     ap.add_argument("--quantum", type=int, default=50, help="steps per request per server cycle")
     ap.add_argument("--batch-requests", type=int, default=512, help="requests of the batched / served mix")
     args = ap.parse_args()
@@ -419,6 +449,8 @@ def main():
     }
     if not args.no_heterogeneous:
         res["heterogeneous"] = heterogeneous_pass(ctx, dev, avg_kernel_s * 1e3)
+    if not args.no_pose:
+        res["pose"] = pose_pass(ctx, dev, avg_kernel_s * 1e3)
     if not args.no_loop:
         res["closed_loop"] = closed_loop(ctx, dev)
     if not args.no_perception:

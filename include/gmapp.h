@@ -150,6 +150,39 @@ gmapp_status gmapp_force_probe(gmapp_ctx *ctx, const gmapp_scene *scene, const g
                                const float *p, const float *v, float t, const gmapp_params *params, float *f_r,
                                float *rho_min, void *stream);
 
+/* 6-D pose agents (Sec. II, Sec. IV-A Eqs. 6-11 on Spin(3) x| R^3, the planner of
+ * Sec. V-B).  An agent's pose is a unit rotor q (w, x, y, z) and a position p; its
+ * twist (omega, u) is in the body frame.  Per step:
+ *   e = log(M^-1 M_g)  (the Lie-group logarithm of SE(3): rotation vector of
+ *       q^-1 q_g and J(phi)^-1 R^T (p_g - p), J the left Jacobian of SO(3)),
+ *   F = K e - D v + (0, R^T f_r),  K = diag(k_r I, k_a I), D = diag(d_r I, d_a I),
+ *   v += (dt/2) diag(i_r I, m^-1 I) F,   M <- M exp(dt v),
+ * with f_r the agent's field (any heuristic) at p and at the world velocity
+ * R(q) u of the body origin.  Costs (Eqs. 16-20) are taken on the positions, the
+ * jerk literally from the position increments.
+ * k_r, d_r, inv_inertia_r: device [N_a] each.  The query's p0 and goal give the
+ * start and goal positions and v0 the start world linear velocity. */
+typedef struct {
+    const float *k_r;            /* rotational stiffness */
+    const float *d_r;            /* rotational damping */
+    const float *inv_inertia_r;  /* inverse rotational inertia */
+} gmapp_pose_agents;
+
+typedef struct {
+    float q0[4];    /* start rotor (w, x, y, z), normalised on use */
+    float w0[3];    /* start angular velocity, body frame [rad/s] */
+    float qg[4];    /* goal rotor */
+} gmapp_pose_query;
+
+/* Forward rollout of 6-D pose agents: as gmapp_rollout (costs, selection, traj
+ * and min_clear outputs), plus rot: device [N_a][N_k + 1][4] rotors or NULL.
+ * EINVAL for a NULL pose or pose_query, NULL gain arrays with N_a > 0, or rotors
+ * that are not finite with a non-zero norm. */
+gmapp_status gmapp_rollout_pose(gmapp_ctx *ctx, const gmapp_scene *scene, const gmapp_agents *agents,
+                                const gmapp_pose_agents *pose, const gmapp_query *query,
+                                const gmapp_pose_query *pose_query, const gmapp_params *params,
+                                const gmapp_outputs *out, float *rot, void *stream);
+
 /* Closed planning loop (Sec. V-B, planner architecture; selection rule of Sec. IV-A
  * across cycles).  The robot is a point mass like the agents.  Cycle c = 0 ..
  * n_cycles - 1 runs, in stream order and with no host round trip:

@@ -11,6 +11,7 @@ which holds none of the method's arithmetic.
   costs(...)                Eqs. (16)-(20) on a given trajectory
   select(...)               the selection rule
   plan_loop(problem, ...)   the closed planning loop: rollouts, selection across cycles, control steps
+  rollout_pose(...)         6-D pose agents in Spin(3) x| R^3 (C code); se3_exp / se3_log
   perception.*              back-projection and voxel-centre sphere world (numpy)
 """
 from __future__ import annotations
@@ -53,6 +54,14 @@ def _load():
         lib.oracle_pair_force_h.restype = None
         lib.oracle_pair_force_h.argtypes = [ctypes.c_int, _dp, _dp, _dp, _dp, ctypes.c_double, ctypes.c_double,
                                             ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_double, _dp, _dp]
+        lib.oracle_rollout_pose.restype = ctypes.c_int
+        lib.oracle_rollout_pose.argtypes = [ctypes.c_long, _dp, _dp, _dp, ctypes.c_double, ctypes.c_int, _ip, _dp,
+                                            ctypes.c_int, _dp, _dp, _dp, _dp, ctypes.c_int, _dp, ctypes.c_int,
+                                            ctypes.c_int, _dp, _dp, _dp, _dp, _ip]
+        lib.oracle_se3_exp.restype = None
+        lib.oracle_se3_exp.argtypes = [_dp, _dp, _dp, _dp]
+        lib.oracle_se3_log.restype = None
+        lib.oracle_se3_log.argtypes = [_dp, _dp, _dp, _dp]
         _lib = lib
     return _lib
 
@@ -210,6 +219,57 @@ def pair_force_heuristic(heur, p, w, q, omega, k_f, r_d, R, eps, cutoff=0, band=
     lib.oracle_pair_force_h(int(heur), *[a[1] for a in arrs], float(k_f), float(r_d), float(R), float(eps),
                             int(cutoff), float(band), f.ctypes.data_as(_dp), ctypes.byref(rho))
     return f, rho.value
+
+
+@dataclasses.dataclass
+class PoseResult:
+    traj: np.ndarray       # [N_a, N_k + 1, 3]
+    rot: np.ndarray        # [N_a, N_k + 1, 4] unit quaternions (w, x, y, z), w >= 0
+    cost: np.ndarray       # [N_a, 5]
+    min_clear: np.ndarray  # [N_a, N_k]
+    best: int
+
+
+def rollout_pose(problem, pose_agents, pose_query) -> PoseResult:
+    """6-D pose agents (Eqs. 6-11 on Spin(3) x| R^3) for one planning cycle."""
+    lib = _load()
+    sc, ag, q, prm = problem.scene, problem.agents, problem.query, problem.params
+    N, na = int(prm.n_steps), ag.n
+    keep, sargs = _scene_args(sc)
+    A, pA = _d(_agents_rows(ag))
+    G, pG = _d(np.stack([pose_agents.k_r, pose_agents.d_r, pose_agents.inv_inertia_r], 1).reshape(-1, 3)
+               if na else np.zeros((0, 3)))
+    Q, pQ = _d(np.concatenate([q.p0, q.v0, q.goal, [np.float32(q.t0)]]).astype(np.float64))
+    PQ, pPQ = _d(np.concatenate([pose_query.q0, pose_query.w0, pose_query.qg]).astype(np.float32))
+    P, pP = _d(_params_row(prm))
+    traj = np.zeros((na, N + 1, 3)); rot = np.zeros((na, N + 1, 4)); cost = np.zeros((na, 5))
+    mc = np.zeros((na, N))
+    best = ctypes.c_int(-1)
+    rc = lib.oracle_rollout_pose(*sargs, na, pA, pG, pQ, pPQ, int(q.incumbent), pP, N, int(prm.cutoff),
+                                 traj.ctypes.data_as(_dp), rot.ctypes.data_as(_dp), cost.ctypes.data_as(_dp),
+                                 mc.ctypes.data_as(_dp), ctypes.byref(best))
+    if rc != 0:
+        raise RuntimeError(f"oracle_rollout_pose failed ({rc})")
+    del keep
+    return PoseResult(traj, rot, cost, mc, best.value)
+
+
+def se3_exp(phi, rho):
+    """SE(3) exponential: (unit quaternion with w >= 0, translation)."""
+    lib = _load()
+    (a, pa), (b, pb) = _d(phi), _d(rho)
+    q, t = np.zeros(4), np.zeros(3)
+    lib.oracle_se3_exp(pa, pb, q.ctypes.data_as(_dp), t.ctypes.data_as(_dp))
+    return q, t
+
+
+def se3_log(q, t):
+    """SE(3) logarithm: (rotation vector of angle <= pi, J(phi)^-1 t)."""
+    lib = _load()
+    (a, pa), (b, pb) = _d(q), _d(t)
+    phi, rho = np.zeros(3), np.zeros(3)
+    lib.oracle_se3_log(pa, pb, phi.ctypes.data_as(_dp), rho.ctypes.data_as(_dp))
+    return phi, rho
 
 
 @dataclasses.dataclass

@@ -9,7 +9,8 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "libgmapp_oracle.so")
-SOURCES = [os.path.join(HERE, "gmapp_oracle.c"), os.path.join(HERE, "gmapp_oracle_grad.c")]
+SOURCES = [os.path.join(HERE, "gmapp_oracle.c"), os.path.join(HERE, "gmapp_oracle_grad.c"),
+           os.path.join(HERE, "gmapp_oracle_pose.c")]
 
 
 def build(verbose: bool = False) -> str:

@@ -261,6 +261,49 @@ gmapp_status gmapp_force_probe(gmapp_ctx *ctx, const gmapp_scene *scene, const g
                               static_cast<hipStream_t>(stream));
 }
 
+gmapp_status gmapp_rollout_pose(gmapp_ctx *ctx, const gmapp_scene *scene, const gmapp_agents *agents,
+                                const gmapp_pose_agents *pose, const gmapp_query *query,
+                                const gmapp_pose_query *pose_query, const gmapp_params *params,
+                                const gmapp_outputs *out, float *rot, void *stream)
+{
+    gmapp_status st = check_ctx(ctx);
+    if (st) return st;
+    if ((st = check_scene(ctx, scene)) || (st = check_agents(ctx, agents)) || (st = check_params(ctx, params, true)))
+        return st;
+    if ((st = check_query(ctx, query))) return st;
+    if (!pose || !pose_query) return fail(ctx, GMAPP_EINVAL, "pose agents and pose query must be non-NULL");
+    if (agents->n_agents > 0 && (!pose->k_r || !pose->d_r || !pose->inv_inertia_r))
+        return fail(ctx, GMAPP_EINVAL, "pose gains k_r, d_r and inv_inertia_r must be non-NULL");
+    auto rotor_ok = [](const float *q) {
+        const float n = q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
+        return finite(q[0]) && finite(q[1]) && finite(q[2]) && finite(q[3]) && finite(n) && n > 0.0f;
+    };
+    if (!rotor_ok(pose_query->q0) || !rotor_ok(pose_query->qg))
+        return fail(ctx, GMAPP_EINVAL, "q0 and qg must be finite rotors with a non-zero norm");
+    if (!finite(pose_query->w0[0]) || !finite(pose_query->w0[1]) || !finite(pose_query->w0[2]))
+        return fail(ctx, GMAPP_EINVAL, "w0 must be finite");
+    if (!out || !out->best) return fail(ctx, GMAPP_EINVAL, "outputs.best is NULL");
+    if (agents->n_agents > 0 && !out->cost) return fail(ctx, GMAPP_EINVAL, "outputs.cost is NULL");
+    gm::Tiling t = tiling_for(ctx, scene->n_points, agents->n_agents, params->n_steps, scene->n_seg, params->cutoff);
+    gm::Agt ag = dev_agents(agents);
+    if (agents->n_agents > 0) {
+        ag.k_r = pose->k_r;
+        ag.d_r = pose->d_r;
+        ag.i_r = pose->inv_inertia_r;
+    }
+    gm::Prm pr = dev_params(params, query);
+    for (int a = 0; a < 4; ++a) {
+        pr.q0[a] = pose_query->q0[a];
+        pr.qg[a] = pose_query->qg[a];
+    }
+    for (int a = 0; a < 3; ++a) pr.om0[a] = pose_query->w0[a];
+    const gm::Scn sc = dev_scene(scene);
+    // the pose kernels hold more registers: a chosen tiling may need fewer shards to stay co-resident
+    if (!ctx->forced && (st = gm::fit_coresident(ctx, t, sc, ag, pr))) return st;
+    gm::Out o{out->traj, out->cost, out->min_clear, out->best, rot};
+    return gm::launch_rollout(ctx, sc, ag, pr, o, nullptr, t, static_cast<hipStream_t>(stream));
+}
+
 gmapp_status gmapp_plan_loop(gmapp_ctx *ctx, const gmapp_scene *scene, const gmapp_agents *agents,
                              const gmapp_query *query, const gmapp_params *params, const gmapp_loop_config *cfg,
                              const gmapp_loop_outputs *out, void *stream)

@@ -30,6 +30,7 @@ struct Agt {
     const float *k_a, *d_a, *k_f, *r_d, *r_a, *omega;
     int n;
     const int *heur;          // per-agent heuristic or nullptr (all rotation-vector field)
+    const float *k_r = nullptr, *d_r = nullptr, *i_r = nullptr;   // 6-D pose agents: rotational gains
 };
 
 struct Prm {
@@ -40,6 +41,9 @@ struct Prm {
     float p0[3], v0[3], goal[3];
     int incumbent;
     float t0;
+    float q0[4] = {1.f, 0.f, 0.f, 0.f};   // 6-D pose agents: start rotor (w, x, y, z)
+    float om0[3] = {0.f, 0.f, 0.f};       // start angular velocity (body frame)
+    float qg[4] = {1.f, 0.f, 0.f, 0.f};   // goal rotor
     const float *start = nullptr;   // device [6] p0, v0 in place of p0, v0 (closed loop) or nullptr
     const int *inc_dev = nullptr;   // device incumbent in place of `incumbent` (closed loop) or nullptr
 };
@@ -47,6 +51,7 @@ struct Prm {
 struct Out {
     float *traj, *cost, *min_clear;
     int *best;
+    float *rot = nullptr;     // 6-D pose agents: [N_a][N_k + 1][4] rotors, or nullptr
 };
 
 // teacher-forced single-step mode (force probe)
@@ -192,6 +197,7 @@ inline gmapp_status hip_fail(gmapp_ctx *ctx, hipError_t e, const char *what)
 gmapp_status launch_rollout(gmapp_ctx *ctx, const Scn &sc, const Agt &ag, const Prm &pr, const Out &out,
                             const Probe *probe, const Tiling &t, hipStream_t stream);
 Tiling choose_tiling(const gmapp_ctx *ctx, long long n_points, int n_agents, int n_steps, int n_seg, int cutoff);
+gmapp_status fit_coresident(gmapp_ctx *ctx, Tiling &t, const Scn &sc, const Agt &ag, const Prm &pr);
 
 // closed planning loop and the control query (control.hip)
 gmapp_status launch_plan_loop(gmapp_ctx *ctx, const Scn &sc, const Agt &ag, const Prm &pr0, const Tiling &t,

@@ -150,6 +150,7 @@ struct Agent {
     float ka, da, kf, rd, R, wx, wy, wz, tb_a, tb_b;
     int hz = 0;               // heuristic: 0 rotation-vector field, 1 velocity current, 2 APF
     float ird = 0.f;          // 1 / r_d (APF)
+    float kr = 0.f, dr = 0.f, ir = 0.f;   // 6-D pose agents: rotational stiffness, damping, inverse inertia
 };
 
 // One agent-sphere interaction of the artificial potential field (Eq. 1 with the

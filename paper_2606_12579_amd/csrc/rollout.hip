@@ -12,9 +12,10 @@ using namespace dev;
 
 namespace {
 
-KFn pick_kernel(int AW, int W, bool wg, int cut, bool probe, bool het)
+KFn pick_kernel(int AW, int W, bool wg, int cut, bool probe, bool het, bool pose)
 {
-    return het ? pick_kernel_het(AW, W, wg, cut, probe) : pick_kernel_t<false>(AW, W, wg, cut, probe);
+    if (pose) return probe ? nullptr : pick_kernel_pose(AW, W, wg, cut);
+    return het ? pick_kernel_het(AW, W, wg, cut, probe) : pick_kernel_t<false, false>(AW, W, wg, cut, probe);
 }
 
 }  // namespace
@@ -53,7 +54,7 @@ size_t rollout_lds_bytes(const Tiling &t, long long n_points, int n_seg)
 
 gmapp_status check_tiling(gmapp_ctx *ctx, const Tiling &t, long long n_points, int n_seg, int cutoff)
 {
-    if (!pick_kernel(t.A, t.W, t.wg != 0, cutoff, false, false))
+    if (!pick_kernel(t.A, t.W, t.wg != 0, cutoff, false, false, false))
         return fail(ctx, GMAPP_EINVAL, "unsupported tiling: %d agents per %s with %d waves", t.A,
                     t.wg ? "workgroup" : "wave", t.W);
     if (t.S < 1 || t.S > kMaxShards) return fail(ctx, GMAPP_EINVAL, "shards must be in [1, %d]", kMaxShards);
@@ -104,6 +105,29 @@ Tiling choose_tiling(const gmapp_ctx *ctx, long long n_points, int n_agents, int
     return shard(t);
 }
 
+// Halve the shard count of a chosen (not forced) tiling until the kernel that
+// will run, with its own register and LDS needs, fits the cooperative launch.
+gmapp_status fit_coresident(gmapp_ctx *ctx, Tiling &t, const Scn &sc, const Agt &ag, const Prm &pr)
+{
+    if (ag.n == 0) return GMAPP_OK;
+    KFn fn = pick_kernel(t.A, t.W, t.wg != 0, pr.cutoff, false, ag.heur != nullptr, ag.k_r != nullptr);
+    if (!fn) return GMAPP_OK;
+    const int per_wg = t.wg ? t.A : t.A * t.W;
+    const long long G = (ag.n + per_wg - 1) / per_wg;
+    while (t.S > 1) {
+        const Lay lay = make_layout(t, sc.n_cap, sc.n_seg);
+        const size_t shm = lds_plan(lay, t.W, t.wg ? t.W : 1, t.A, t.S).total;
+        int per_cu = 0;
+        GM_HIP(ctx, hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+        GM_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(fn),
+                                                                 64 * t.W, shm));
+        if ((long long)per_cu * ctx->n_cu >= (G * t.S + 7) / 8 * 8) break;
+        t.S /= 2;
+    }
+    return GMAPP_OK;
+}
+
 gmapp_status launch_rollout(gmapp_ctx *ctx, const Scn &sc, const Agt &ag, const Prm &pr, const Out &out,
                             const Probe *probe, const Tiling &t, hipStream_t stream)
 {
@@ -115,7 +139,8 @@ gmapp_status launch_rollout(gmapp_ctx *ctx, const Scn &sc, const Agt &ag, const 
         GM_HIP(ctx, hipGetLastError());
         return GMAPP_OK;
     }
-    KFn fn = pick_kernel(t.A, t.W, t.wg != 0, pr.cutoff, is_probe, ag.heur != nullptr);
+    KFn fn = pick_kernel(t.A, t.W, t.wg != 0, pr.cutoff, is_probe, ag.heur != nullptr, ag.k_r != nullptr);
+    if (!fn) return fail(ctx, GMAPP_EINVAL, "6-D pose agents have no teacher-forced form");
     const int per_wg = t.wg ? t.A : t.A * t.W;
     const int gpw = t.wg ? 1 : t.W;
     const int G = (ag.n + per_wg - 1) / per_wg;

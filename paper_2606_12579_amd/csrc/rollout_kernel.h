@@ -45,6 +45,7 @@
 // exchange area for the next launch.
 #include "gmapp_internal.h"
 #include "pairs.h"
+#include "pose.h"
 
 #include <algorithm>
 #include <cmath>
@@ -92,7 +93,9 @@ __host__ __device__ inline LdsPlan lds_plan(const Lay &l, int W, int WS, int AW,
 // groups.  PROBE: one teacher-forced step at the given states (no integration, no costs).
 // HET: each agent takes its field from ag.heur (rotation-vector circular field,
 // velocity-current field or APF); without it every agent runs the rotation-vector field.
-template <int AW, int W, int WS, int CUT, bool PROBE, bool HET>
+// POSE: 6-D pose agents (rotor and translation, body twist; Eqs. 6-11 on
+// Spin(3) x| R^3); the pairwise pass sees their position and world velocity.
+template <int AW, int W, int WS, int CUT, bool PROBE, bool HET, bool POSE>
 __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out out, Probe pb, Xch xc, Lay lay)
 {
     constexpr int NT = 64 * W;
@@ -150,8 +153,13 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
     P.wz = ag.omega[3 * ai + 2];
     P.tb_a = 1.0f / (pr.band * P.rd);             // taper: s = (r_d - rho) / (band r_d)
     P.tb_b = P.rd * P.tb_a;
+    if constexpr (POSE) {
+        P.kr = ag.k_r[ai];
+        P.dr = ag.d_r[ai];
+        P.ir = ag.i_r[ai];
+    }
     if constexpr (HET) {
-        P.hz = ag.heur[ai];
+        P.hz = ag.heur ? ag.heur[ai] : 0;           // pose kernels run HET with or without codes
         if (P.hz != 1 && P.hz != 2) P.hz = 0;
         P.ird = 1.0f / P.rd;
     }
@@ -195,6 +203,16 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
     }
     float cpx = 0, cpy = 0, cpz = 0, cvx = 0, cvy = 0, cvz = 0;     // Kahan terms
     float F1x = 0, F1y = 0, F1z = 0, F2x = 0, F2y = 0, F2z = 0;     // F^(k-1), F^(k-2)
+    // 6-D pose agents: rotor, body twist (omega, u), and the last three position increments
+    // p^(k) - p^(k-1), ... (the point-mass jerk identity does not hold for them)
+    pose::Q qr{1.f, 0.f, 0.f, 0.f};
+    float ox = 0, oy = 0, oz = 0, ux = 0, uy = 0, uz = 0, cux = 0, cuy = 0, cuz = 0;
+    float D1x = 0, D1y = 0, D1z = 0, D2x = 0, D2y = 0, D2z = 0, D3x = 0, D3y = 0, D3z = 0;
+    if constexpr (POSE && !PROBE) {
+        qr = pose::qnormalize(pose::Q{pr.q0[0], pr.q0[1], pr.q0[2], pr.q0[3]});
+        ox = pr.om0[0]; oy = pr.om0[1]; oz = pr.om0[2];
+        pose::qrot(qr, -1.0f, vx, vy, vz, ux, uy, uz);              // body linear velocity
+    }
     float sg = 0, cg = 0, so = 0, co = 0, sp = 0, cp = 0, sj = 0, cj = 0;  // cost sums
     const float gx = pr.goal[0], gy = pr.goal[1], gz = pr.goal[2];
     const float h = 0.5f * pr.dt * pr.inv_mass;
@@ -206,6 +224,12 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
     if (writer && out.traj) {
         float *tr = out.traj + (size_t)agent * traj_row;
         tr[0] = px; tr[1] = py; tr[2] = pz;
+    }
+    if constexpr (POSE) {
+        if (writer && out.rot) {
+            float *ro = out.rot + (size_t)agent * (pr.n_steps + 1) * 4;
+            ro[0] = qr.w; ro[1] = qr.x; ro[2] = qr.y; ro[3] = qr.z;
+        }
     }
     const unsigned long long t_start = __builtin_amdgcn_s_memrealtime();
 
@@ -288,10 +312,19 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
             const float ex = gx - px, ey = gy - py, ez = gz - pz;
             const float dgoal = __builtin_amdgcn_sqrtf(fmaf(ez, ez, fmaf(ey, ey, ex * ex)));
             kahan_add(sg, cg, fminf(dgoal, pr.r_cost) * inv_rc);
-            if (k >= 2) kahan_add(sp, cp, pr.dt * __builtin_amdgcn_sqrtf(fmaf(vz, vz, fmaf(vy, vy, vx * vx))));
-            if (k >= 4) {
-                const float jx = hj * (F1x - F2x), jy = hj * (F1y - F2y), jz = hj * (F1z - F2z);
-                kahan_add(sj, cj, fmaf(jz, jz, fmaf(jy, jy, jx * jx)));
+            if constexpr (POSE) {
+                if (k >= 2) kahan_add(sp, cp, __builtin_amdgcn_sqrtf(fmaf(D1z, D1z, fmaf(D1y, D1y, D1x * D1x))));
+                if (k >= 4) {       // p^(k) - 3 p^(k-1) + 3 p^(k-2) - p^(k-3) from the increments
+                    const float jx = (D1x - D2x) - (D2x - D3x), jy = (D1y - D2y) - (D2y - D3y);
+                    const float jz = (D1z - D2z) - (D2z - D3z);
+                    kahan_add(sj, cj, fmaf(jz, jz, fmaf(jy, jy, jx * jx)));
+                }
+            } else {
+                if (k >= 2) kahan_add(sp, cp, pr.dt * __builtin_amdgcn_sqrtf(fmaf(vz, vz, fmaf(vy, vy, vx * vx))));
+                if (k >= 4) {
+                    const float jx = hj * (F1x - F2x), jy = hj * (F1y - F2y), jz = hj * (F1z - F2z);
+                    kahan_add(sj, cj, fmaf(jz, jz, fmaf(jy, jy, jx * jx)));
+                }
             }
         };
         // device-scope exchange of the group's shard totals, summed in shard order (run by the lead wave)
@@ -381,6 +414,55 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
                 if (valid && s == 0 && slice == 0) {
                     pb.f_r[3 * agent] = Fx_; pb.f_r[3 * agent + 1] = Fy_; pb.f_r[3 * agent + 2] = Fz_;
                     if (pb.rho_min) pb.rho_min[agent] = rho_min;
+                }
+                return;
+            }
+            if constexpr (POSE) {
+                kahan_add(so, co, 1.0f - fminf(rho_min, pr.r_cost) * inv_rc);
+                // attractor wrench (Eqs. 7, 8): e = log(M^-1 M_g) in the body frame, K = diag(k_r, k_a),
+                // D = diag(d_r, d_a); the repulsive force enters as a pure force, rotated into the body frame
+                float phx, phy, phz;
+                pose::so3_log(pose::qmul(pose::Q{qr.w, -qr.x, -qr.y, -qr.z},
+                                         pose::Q{pr.qg[0], pr.qg[1], pr.qg[2], pr.qg[3]}), phx, phy, phz);
+                float tx, ty, tz, rx, ry, rz, fx, fy, fz;
+                pose::qrot(qr, -1.0f, gx - px, gy - py, gz - pz, tx, ty, tz);
+                pose::jac_apply(phx, phy, phz, -1.0f, tx, ty, tz, rx, ry, rz);
+                pose::qrot(qr, -1.0f, Fx_, Fy_, Fz_, fx, fy, fz);
+                const float Flx = fmaf(P.ka, rx, fmaf(-P.da, ux, fx));
+                const float Fly = fmaf(P.ka, ry, fmaf(-P.da, uy, fy));
+                const float Flz = fmaf(P.ka, rz, fmaf(-P.da, uz, fz));
+                const float Fax = fmaf(P.kr, phx, -P.dr * ox);
+                const float Fay = fmaf(P.kr, phy, -P.dr * oy);
+                const float Faz = fmaf(P.kr, phz, -P.dr * oz);
+                // twist (Eqs. 9, 10), inertia diag(i_r, 1/m)
+                const float hr = 0.5f * pr.dt * P.ir;
+                kahan_add(ux, cux, h * Flx);
+                kahan_add(uy, cuy, h * Fly);
+                kahan_add(uz, cuz, h * Flz);
+                ox = fmaf(hr, Fax, ox); oy = fmaf(hr, Fay, oy); oz = fmaf(hr, Faz, oz);
+                // pose (Eq. 11): M <- M exp(dt v); the translation moves by R J(dt omega) dt u
+                const float ax = pr.dt * ox, ay = pr.dt * oy, az = pr.dt * oz;
+                float jx, jy, jz, dx, dy, dz;
+                pose::jac_apply(ax, ay, az, 1.0f, pr.dt * ux, pr.dt * uy, pr.dt * uz, jx, jy, jz);
+                pose::qrot(qr, 1.0f, jx, jy, jz, dx, dy, dz);
+                kahan_add(px, cpx, dx);
+                kahan_add(py, cpy, dy);
+                kahan_add(pz, cpz, dz);
+                qr = pose::qnormalize(pose::qmul(qr, pose::so3_exp(ax, ay, az)));
+                D3x = D2x; D3y = D2y; D3z = D2z;
+                D2x = D1x; D2y = D1y; D2z = D1z;
+                D1x = dx; D1y = dy; D1z = dz;
+                pose::qrot(qr, 1.0f, ux, uy, uz, vx, vy, vz);        // world velocity of the body origin
+                if (writer) {
+                    if (out.traj) {
+                        float *tr = out.traj + (size_t)agent * traj_row + 3 * (size_t)k;
+                        tr[0] = px; tr[1] = py; tr[2] = pz;
+                    }
+                    if (out.rot) {
+                        float *ro = out.rot + ((size_t)agent * (pr.n_steps + 1) + k) * 4;
+                        ro[0] = qr.w; ro[1] = qr.x; ro[2] = qr.y; ro[3] = qr.z;
+                    }
+                    if (out.min_clear) out.min_clear[(size_t)agent * pr.n_steps + (k - 1)] = rho_min;
                 }
                 return;
             }
@@ -522,50 +604,55 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
 // ---------------------------------------------------------------- kernel tables
 using KFn = void (*)(Scn, Agt, Prm, Out, Probe, Xch, Lay);
 
-template <int AW, int W, int WS, bool HET>
+template <int AW, int W, int WS, bool HET, bool POSE>
 KFn pick_cut(int cut, bool probe)
 {
-    if (probe) return cut ? k_rollout<AW, W, WS, 1, true, HET> : k_rollout<AW, W, WS, 0, true, HET>;
-    return cut ? k_rollout<AW, W, WS, 1, false, HET> : k_rollout<AW, W, WS, 0, false, HET>;
+    if constexpr (POSE) {           // pose agents have no teacher-forced form (the probe takes p, v)
+        if (probe) return nullptr;
+        return cut ? k_rollout<AW, W, WS, 1, false, HET, true> : k_rollout<AW, W, WS, 0, false, HET, true>;
+    } else {
+        if (probe) return cut ? k_rollout<AW, W, WS, 1, true, HET, false> : k_rollout<AW, W, WS, 0, true, HET, false>;
+        return cut ? k_rollout<AW, W, WS, 1, false, HET, false> : k_rollout<AW, W, WS, 0, false, HET, false>;
+    }
 }
 
 // per-wave groups: every (AW, W); workgroup-wide groups: AW <= 8 with 4, 8 or 16 waves
-template <int W, bool HET>
+template <int W, bool HET, bool POSE>
 KFn pick_a(int AW, bool wg, int cut, bool probe)
 {
     if (wg) {
         if constexpr (W >= 4) {
             switch (AW) {
-            case 1: return pick_cut<1, W, W, HET>(cut, probe);
-            case 2: return pick_cut<2, W, W, HET>(cut, probe);
-            case 4: return pick_cut<4, W, W, HET>(cut, probe);
-            case 8: return pick_cut<8, W, W, HET>(cut, probe);
+            case 1: return pick_cut<1, W, W, HET, POSE>(cut, probe);
+            case 2: return pick_cut<2, W, W, HET, POSE>(cut, probe);
+            case 4: return pick_cut<4, W, W, HET, POSE>(cut, probe);
+            case 8: return pick_cut<8, W, W, HET, POSE>(cut, probe);
             default: return nullptr;
             }
         }
         return nullptr;
     }
     switch (AW) {
-    case 1: return pick_cut<1, W, 1, HET>(cut, probe);
-    case 2: return pick_cut<2, W, 1, HET>(cut, probe);
-    case 4: return pick_cut<4, W, 1, HET>(cut, probe);
-    case 8: return pick_cut<8, W, 1, HET>(cut, probe);
-    case 16: return pick_cut<16, W, 1, HET>(cut, probe);
-    case 32: return pick_cut<32, W, 1, HET>(cut, probe);
-    case 64: return pick_cut<64, W, 1, HET>(cut, probe);
+    case 1: return pick_cut<1, W, 1, HET, POSE>(cut, probe);
+    case 2: return pick_cut<2, W, 1, HET, POSE>(cut, probe);
+    case 4: return pick_cut<4, W, 1, HET, POSE>(cut, probe);
+    case 8: return pick_cut<8, W, 1, HET, POSE>(cut, probe);
+    case 16: return pick_cut<16, W, 1, HET, POSE>(cut, probe);
+    case 32: return pick_cut<32, W, 1, HET, POSE>(cut, probe);
+    case 64: return pick_cut<64, W, 1, HET, POSE>(cut, probe);
     default: return nullptr;
     }
 }
 
-template <bool HET>
+template <bool HET, bool POSE>
 KFn pick_kernel_t(int AW, int W, bool wg, int cut, bool probe)
 {
     switch (W) {
-    case 1: return pick_a<1, HET>(AW, wg, cut, probe);
-    case 2: return pick_a<2, HET>(AW, wg, cut, probe);
-    case 4: return pick_a<4, HET>(AW, wg, cut, probe);
-    case 8: return pick_a<8, HET>(AW, wg, cut, probe);
-    case 16: return pick_a<16, HET>(AW, wg, cut, probe);
+    case 1: return pick_a<1, HET, POSE>(AW, wg, cut, probe);
+    case 2: return pick_a<2, HET, POSE>(AW, wg, cut, probe);
+    case 4: return pick_a<4, HET, POSE>(AW, wg, cut, probe);
+    case 8: return pick_a<8, HET, POSE>(AW, wg, cut, probe);
+    case 16: return pick_a<16, HET, POSE>(AW, wg, cut, probe);
     default: return nullptr;
     }
 }
@@ -573,5 +660,7 @@ KFn pick_kernel_t(int AW, int W, bool wg, int cut, bool probe)
 // The kernel for a tiling (nullptr if unsupported); the heterogeneous-field
 // instantiations are compiled in their own unit.
 KFn pick_kernel_het(int AW, int W, bool wg, int cut, bool probe);
+// 6-D pose agents (any heuristic), forward rollouts only; in rollout_pose.hip.
+KFn pick_kernel_pose(int AW, int W, bool wg, int cut);
 
 }  // namespace gm

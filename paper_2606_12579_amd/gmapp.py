@@ -47,6 +47,14 @@ class Agents(ctypes.Structure):
 H_CF_OMEGA, H_MFI_VEL, H_APF = 0, 1, 2
 
 
+class PoseAgents(ctypes.Structure):
+    _fields_ = [("k_r", ctypes.c_void_p), ("d_r", ctypes.c_void_p), ("inv_inertia_r", ctypes.c_void_p)]
+
+
+class PoseQuery(ctypes.Structure):
+    _fields_ = [("q0", ctypes.c_float * 4), ("w0", ctypes.c_float * 3), ("qg", ctypes.c_float * 4)]
+
+
 class LoopConfig(ctypes.Structure):
     _fields_ = [("n_cycles", ctypes.c_int32), ("ctrl_steps", ctypes.c_int32), ("ctrl_dt", ctypes.c_float)]
 
@@ -151,6 +159,8 @@ def load_library(path: str = LIB_PATH):
         "gmapp_force_probe": (ctypes.c_int32, [vp, P(Scene), P(Agents), vp, vp, ctypes.c_float, P(Params), vp, vp,
                                                vp]),
         "gmapp_set_tiling": (ctypes.c_int32, [vp, P(Tiling)]),
+        "gmapp_rollout_pose": (ctypes.c_int32, [vp, P(Scene), P(Agents), P(PoseAgents), P(Query), P(PoseQuery),
+                                                P(Params), P(Outputs), vp, vp]),
         "gmapp_plan_loop": (ctypes.c_int32, [vp, P(Scene), P(Agents), P(Query), P(Params), P(LoopConfig),
                                              P(LoopOutputs), vp]),
         "gmapp_control_force": (ctypes.c_int32, [vp, P(Scene), P(Agents), vp, vp, ctypes.c_float, P(Params), vp, vp,
@@ -241,6 +251,19 @@ class DeviceAgents:
     @property
     def n(self) -> int:
         return int(self.k_a.numel())
+
+
+@dataclasses.dataclass
+class DevicePoseAgents:
+    k_r: object
+    d_r: object
+    inv_inertia_r: object
+
+
+def pose_agents_to_device(pose, device="cuda") -> DevicePoseAgents:
+    import torch
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32), device=device)
+    return DevicePoseAgents(t(pose.k_r), t(pose.d_r), t(pose.inv_inertia_r))
 
 
 def scene_to_device(scene, device="cuda") -> DeviceScene:
@@ -584,6 +607,33 @@ class Context:
                                         float(t), ctypes.byref(prm), _ptr(f), _ptr(r), self._stream(stream))
         self._raise(st)
         return f, r
+
+    def rollout_pose(self, scene: DeviceScene, agents: DeviceAgents, pose_agents, query, pose_query, params,
+                     traj=True, min_clear=True, rot=True, out=None, stream=None):
+        """gmapp_rollout_pose: 6-D pose agents. pose_agents: (k_r, d_r, inv_inertia_r) device float32 [N_a]
+        tensors (DevicePoseAgents); pose_query: q0 [4], w0 [3], qg [4]. Returns the outputs of rollout plus
+        rot [N_a, N_k + 1, 4]."""
+        import torch
+        na, nk, dev = agents.n, int(params.n_steps), self.device
+        if out is None:
+            out = {"traj": torch.empty((na, nk + 1, 3), dtype=torch.float32, device=dev) if traj else None,
+                   "cost": torch.empty((na, 5), dtype=torch.float32, device=dev),
+                   "min_clear": torch.empty((na, nk), dtype=torch.float32, device=dev) if min_clear else None,
+                   "best": torch.empty(1, dtype=torch.int32, device=dev),
+                   "rot": torch.empty((na, nk + 1, 4), dtype=torch.float32, device=dev) if rot else None}
+        for nm in ("k_r", "d_r", "inv_inertia_r"):
+            _check_tensor(getattr(pose_agents, nm), f"pose_agents.{nm}", na, torch.float32, dev)
+        sc, ag = _scene_struct(scene, dev), _agents_struct(agents, dev)
+        pa = PoseAgents(_ptr(pose_agents.k_r), _ptr(pose_agents.d_r), _ptr(pose_agents.inv_inertia_r))
+        f = lambda a, n: (ctypes.c_float * n)(*[float(x) for x in np.asarray(a, np.float32).reshape(-1)])
+        pq = PoseQuery(f(pose_query.q0, 4), f(pose_query.w0, 3), f(pose_query.qg, 4))
+        q, p = make_query(query), make_params(params)
+        o = Outputs(_ptr(out["traj"]), _ptr(out["cost"]), _ptr(out["min_clear"]), _ptr(out["best"]))
+        st = self.lib.gmapp_rollout_pose(self.handle, ctypes.byref(sc), ctypes.byref(ag), ctypes.byref(pa),
+                                         ctypes.byref(q), ctypes.byref(pq), ctypes.byref(p), ctypes.byref(o),
+                                         _ptr(out.get("rot")), self._stream(stream))
+        self._raise(st)
+        return out
 
     def plan_loop(self, scene: DeviceScene, agents: DeviceAgents, query, params, n_cycles, ctrl_steps, ctrl_dt,
                   clear=True, stream=None):

@@ -362,3 +362,48 @@ def tiny(seed: int, n_points: int = 8, n_agents: int = 4, n_steps: int = 10, mov
     agents = default_agents(rng, n_agents)
     q = _query((0.0, 0.0, 0.0), (0.1, 0.0, 0.0), v0=(0.3, 0.0, 0.0))
     return Problem(scene, agents, q, Params(n_steps=n_steps, cutoff=cutoff), f"tiny{seed}")
+
+
+# ---------------------------------------------------------------- 6-D pose agents
+K_R = 10.0           # rotational stiffness [N m / rad]
+I_R = 10.0           # inverse rotational inertia [1 / (kg m^2)]
+
+
+@dataclasses.dataclass
+class PoseAgents:
+    k_r: np.ndarray            # float32 [N_a] rotational stiffness
+    d_r: np.ndarray            # float32 [N_a] rotational damping
+    inv_inertia_r: np.ndarray  # float32 [N_a] inverse rotational inertia
+
+    def subset(self, idx) -> "PoseAgents":
+        idx = np.asarray(idx, dtype=np.int64)
+        return PoseAgents(*(np.ascontiguousarray(getattr(self, f.name)[idx]) for f in dataclasses.fields(self)))
+
+
+@dataclasses.dataclass
+class PoseQuery:
+    q0: np.ndarray   # float32 [4] start rotor (w, x, y, z)
+    w0: np.ndarray   # float32 [3] start angular velocity, body frame
+    qg: np.ndarray   # float32 [4] goal rotor
+
+
+def unit_rotors(rng: np.random.Generator, n: int) -> np.ndarray:
+    """n rotors uniform on S^3 (normalised 4-D Gaussian samples), w >= 0."""
+    q = rng.standard_normal((n, 4))
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    q[q[:, 0] < 0] *= -1
+    return q.astype(F32)
+
+
+def pose_agents(rng: np.random.Generator, n: int, jitter: float = 0.2) -> PoseAgents:
+    """Rotational gains around K_R, I_R (factors U[1 - jitter, 1 + jitter]), each
+    agent critically damped: d_r = 2 sqrt(k_r / i_r)."""
+    k_r = K_R * rng.uniform(1 - jitter, 1 + jitter, n)
+    i_r = I_R * rng.uniform(1 - jitter, 1 + jitter, n)
+    return PoseAgents(k_r.astype(F32), (2.0 * np.sqrt(k_r / i_r)).astype(F32), i_r.astype(F32))
+
+
+def pose_query(rng: np.random.Generator, max_w: float = 1.0) -> PoseQuery:
+    """Random start and goal rotors and a start angular velocity of up to max_w rad/s."""
+    q = unit_rotors(rng, 2)
+    return PoseQuery(q[0], (rng.uniform(-1, 1, 3) * max_w / np.sqrt(3)).astype(F32), q[1])

@@ -594,3 +594,108 @@ def test_loop_translation_covariance():
     assert a.best.tolist() == b.best.tolist()
     # the FP32 rounding of the shifted points moves each sphere by up to 6e-8 m
     np.testing.assert_allclose(b.robot[:, :3] - shift, a.robot[:, :3], rtol=0, atol=1e-6)
+
+
+# ---------------------------------------------------------------- 6-D pose agents (Eqs. 6-11 on Spin(3) x| R^3)
+
+def _identity_pose_query():
+    return scenes.PoseQuery(np.array([1, 0, 0, 0], np.float32), np.zeros(3, np.float32),
+                            np.array([1, 0, 0, 0], np.float32))
+
+
+def test_pose_agents_without_rotation_are_point_masses():
+    """Identity start and goal rotors and no angular velocity: no torque ever acts,
+    the log's translational part is p_g - p, and the pose rollout is the point-mass
+    rollout (moving spheres, mixed heuristics)."""
+    pb = scenes.tiny(8, n_points=200, n_agents=6, n_steps=40, moving=True)
+    pb.agents = scenes.multi_agents(np.random.default_rng(4), 6)
+    pa = scenes.pose_agents(np.random.default_rng(5), 6)
+    a = oracle.rollout(pb)
+    b = oracle.rollout_pose(pb, pa, _identity_pose_query())
+    np.testing.assert_allclose(b.traj, a.traj, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(b.cost, a.cost, rtol=1e-10, atol=1e-12)
+    assert b.best == a.best
+    assert np.abs(b.rot - np.array([1.0, 0, 0, 0])).max() < 1e-15
+
+
+def test_se3_exp_log():
+    """exp against scipy's rotation-vector map and against numerical integration of
+    the constant-twist motion (t(1) = integral of Rot(s phi) rho ds); log inverts exp."""
+    from scipy.integrate import quad_vec
+    from scipy.spatial.transform import Rotation
+    rng = np.random.default_rng(31)
+    for _ in range(25):
+        phi = scenes.unit_vectors(rng, 1)[0].astype(np.float64) * rng.uniform(0.0, 3.0)
+        rho = rng.uniform(-1, 1, 3)
+        q, t = oracle.se3_exp(phi, rho)
+        x, y, z, w = Rotation.from_rotvec(phi).as_quat()
+        want = np.array([w, x, y, z]) * (1 if w >= 0 else -1)
+        np.testing.assert_allclose(q, want, rtol=0, atol=1e-12)
+        ti, _ = quad_vec(lambda s: Rotation.from_rotvec(s * phi).apply(rho), 0.0, 1.0, epsabs=1e-13)
+        np.testing.assert_allclose(t, ti, rtol=0, atol=1e-10)
+        phi2, rho2 = oracle.se3_log(q, t)
+        np.testing.assert_allclose(phi2, phi, rtol=0, atol=1e-10)
+        np.testing.assert_allclose(rho2, rho, rtol=0, atol=1e-10)
+    q, t = oracle.se3_exp(np.zeros(3), np.array([0.1, -0.2, 0.3]))       # pure translation
+    np.testing.assert_allclose(q, [1, 0, 0, 0], atol=0)
+    np.testing.assert_allclose(t, [0.1, -0.2, 0.3], atol=1e-15)
+
+
+def test_pose_rotation_about_a_fixed_axis():
+    """At the goal position with no spheres, a rotor error about a fixed axis n stays
+    about n: theta follows w_k = w_{k-1} + h_r (-k_r theta_k - d_r w_{k-1}),
+    theta_{k+1} = theta_k + dt w_k, whose closed form is a matrix power."""
+    pb = scenes.tiny(3, n_points=0, n_agents=2, n_steps=60)
+    pb.query.p0 = np.asarray(pb.query.goal, np.float32).copy()
+    pb.query.v0 = np.zeros(3, np.float32)
+    n = np.array([2.0, -1.0, 2.0]) / 3.0
+    th0, w0 = 2.0, 1.5
+    pq = scenes.PoseQuery(np.concatenate([[np.cos(th0 / 2)], np.sin(th0 / 2) * n]).astype(np.float32),
+                          (w0 * n).astype(np.float32), np.array([1, 0, 0, 0], np.float32))
+    pa = scenes.pose_agents(np.random.default_rng(6), 2)
+    res = oracle.rollout_pose(pb, pa, pq)
+    q0 = pq.q0.astype(np.float64)
+    th = 2.0 * np.arctan2(np.linalg.norm(q0[1:]), q0[0])
+    axis = q0[1:] / np.linalg.norm(q0[1:])
+    om = float(np.dot(pq.w0.astype(np.float64), axis))
+    dt = float(np.float32(pb.params.dt))
+    for i in range(2):
+        kr, dr, ir = (float(pa.k_r[i]), float(pa.d_r[i]), float(pa.inv_inertia_r[i]))
+        h = 0.5 * dt * ir
+        M = np.array([[1.0 - dt * h * kr, dt * (1.0 - h * dr)], [-h * kr, 1.0 - h * dr]])
+        for k in (1, 7, 60):
+            th_k, _ = np.linalg.matrix_power(M, k) @ np.array([th, om])
+            want = np.concatenate([[np.cos(th_k / 2)], np.sin(th_k / 2) * axis])
+            np.testing.assert_allclose(res.rot[i, k], want * np.sign(want[0]), rtol=0, atol=1e-12)
+        np.testing.assert_allclose(res.traj[i], np.broadcast_to(pb.query.p0, res.traj[i].shape), atol=1e-15)
+
+
+def test_pose_frame_covariance():
+    """Rotating the world (spheres, start, goal, start velocity, field rotation
+    vectors, start and goal rotors) rotates the trajectories and rotors and leaves
+    the costs and the selection unchanged."""
+    from scipy.spatial.transform import Rotation
+    pb = scenes.config1()
+    pa = scenes.pose_agents(np.random.default_rng(7), pb.agents.n)
+    pq = scenes.pose_query(np.random.default_rng(8))
+    Qr = Rotation.from_rotvec([0.3, -1.1, 0.7])
+    Qm = Qr.as_matrix()
+    pt = copy.deepcopy(pb)
+    P = Qm @ np.stack([pb.scene.x, pb.scene.y, pb.scene.z]).astype(np.float64)
+    pt.scene = scenes.Scene(*(P[a].astype(np.float32) for a in range(3)), pb.scene.r_obs)
+    pt.query.p0 = Qm @ np.asarray(pb.query.p0, np.float64)
+    pt.query.goal = Qm @ np.asarray(pb.query.goal, np.float64)
+    pt.query.v0 = Qm @ np.asarray(pb.query.v0, np.float64)
+    pt.agents.omega = (pb.agents.omega.astype(np.float64) @ Qm.T).astype(np.float32)
+    qw = lambda q: np.array([q[3], q[0], q[1], q[2]])
+    rq = lambda q: (Qr * Rotation.from_quat([q[1], q[2], q[3], q[0]])).as_quat()
+    ptq = scenes.PoseQuery(qw(rq(pq.q0.astype(np.float64))), pq.w0, qw(rq(pq.qg.astype(np.float64))))
+    a = oracle.rollout_pose(pb, pa, pq)
+    b = oracle.rollout_pose(pt, pa, ptq)
+    assert a.best == b.best
+    # the FP32 rounding of the rotated spheres, field rotation vectors and rotors moves inputs by ~6e-8
+    np.testing.assert_allclose(b.traj, a.traj @ Qm.T, rtol=0, atol=2e-6)
+    np.testing.assert_allclose(b.cost, a.cost, rtol=0, atol=2e-5)
+    for i in range(pb.agents.n):
+        r = qw(rq(a.rot[i, -1]))
+        assert min(np.abs(b.rot[i, -1] - r).max(), np.abs(b.rot[i, -1] + r).max()) < 2e-6

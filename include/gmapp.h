@@ -457,6 +457,20 @@ gmapp_status gmapp_voxel_downsample(gmapp_ctx *ctx, const float *x, const float 
                                     float *ox, float *oy, float *oz, int64_t capacity, int64_t *n_out_dev,
                                     void *stream);
 
+/* The voxel pass with the robot self-filter of Sec. V-A: before voxelisation,
+ * points within any of the robot's bounding spheres are removed (the caller
+ * places the spheres by forward kinematics).  robot_spheres: device [n_spheres][4]
+ * (centre x, y, z, radius); a point p is removed when |p - c|^2 <= r^2, evaluated
+ * in FP64 as ((dx dx + dy dy) + dz dz) with each operation rounded (no fused
+ * multiply-add).  n_spheres = 0 is gmapp_voxel_downsample.  EINVAL for
+ * n_spheres < 0 or a NULL robot_spheres with n_spheres > 0; otherwise as
+ * gmapp_voxel_downsample. */
+gmapp_status gmapp_voxel_downsample_filtered(gmapp_ctx *ctx, const float *x, const float *y, const float *z,
+                                             int64_t n, float voxel, const float lo[3], const int32_t dims[3],
+                                             int32_t min_count, const float *robot_spheres, int32_t n_spheres,
+                                             float *ox, float *oy, float *oz, int64_t capacity, int64_t *n_out_dev,
+                                             void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -7,6 +7,9 @@
                                  per axis, decided in FP32 as the library does (the
                                  quantisation is an integer decision)
   voxel_centres(cells, ...)      the voxel-centre cloud lo + (k + 1/2) voxel (FP64)
+  on_robot(x, y, z, spheres)     the robot self-filter of Sec. V-A: points within any
+                                 of the robot's bounding spheres (an integer decision,
+                                 taken in FP64 as the library takes it)
 """
 import numpy as np
 
@@ -42,9 +45,27 @@ def voxel_keys(x, y, z, voxel, lo, dims):
     return k, ok
 
 
-def voxel_cells(x, y, z, voxel, lo, dims, min_count=1):
-    """Sorted linear indices (x fastest) of the cells holding >= min_count points."""
+def on_robot(x, y, z, spheres):
+    """Mask of the points p with |p - c|^2 <= r^2 for some sphere (c, r) of spheres
+    [K, 4] (FP32 values), in FP64 as ((dx dx + dy dy) + dz dz) -- each numpy
+    operation rounds once, as each operation of the library does."""
+    P = np.stack([np.asarray(x, np.float32), np.asarray(y, np.float32), np.asarray(z, np.float32)], 1)
+    P = P.astype(np.float64)
+    S = np.asarray(spheres, np.float32).astype(np.float64).reshape(-1, 4)
+    hit = np.zeros(P.shape[0], bool)
+    for c in S:
+        dx, dy, dz = P[:, 0] - c[0], P[:, 1] - c[1], P[:, 2] - c[2]
+        with np.errstate(invalid="ignore"):
+            hit |= ((dx * dx + dy * dy) + dz * dz) <= c[3] * c[3]
+    return hit
+
+
+def voxel_cells(x, y, z, voxel, lo, dims, min_count=1, spheres=None):
+    """Sorted linear indices (x fastest) of the cells holding >= min_count points
+    (points on the robot, within spheres [K, 4], removed first)."""
     k, ok = voxel_keys(x, y, z, voxel, lo, dims)
+    if spheres is not None and len(spheres):
+        ok &= ~on_robot(x, y, z, spheres)
     dims = np.asarray(dims, np.int64)
     lin = (k[ok, 2] * dims[1] + k[ok, 1]) * dims[0] + k[ok, 0]
     cells, counts = np.unique(lin, return_counts=True)

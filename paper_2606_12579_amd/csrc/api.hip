@@ -386,6 +386,16 @@ gmapp_status gmapp_voxel_downsample(gmapp_ctx *ctx, const float *x, const float 
                                     float *ox, float *oy, float *oz, int64_t capacity, int64_t *n_out_dev,
                                     void *stream)
 {
+    return gmapp_voxel_downsample_filtered(ctx, x, y, z, n, voxel, lo, dims, min_count, nullptr, 0, ox, oy, oz,
+                                           capacity, n_out_dev, stream);
+}
+
+gmapp_status gmapp_voxel_downsample_filtered(gmapp_ctx *ctx, const float *x, const float *y, const float *z,
+                                             int64_t n, float voxel, const float lo[3], const int32_t dims[3],
+                                             int32_t min_count, const float *robot_spheres, int32_t n_spheres,
+                                             float *ox, float *oy, float *oz, int64_t capacity, int64_t *n_out_dev,
+                                             void *stream)
+{
     gmapp_status st = check_ctx(ctx);
     if (st) return st;
     if (n < 0 || capacity < 0) return fail(ctx, GMAPP_EINVAL, "n and capacity must be >= 0");
@@ -395,8 +405,12 @@ gmapp_status gmapp_voxel_downsample(gmapp_ctx *ctx, const float *x, const float 
     if (!lo || !dims) return fail(ctx, GMAPP_EINVAL, "lo and dims must be non-NULL");
     if (!finite(voxel) || voxel <= 0.f) return fail(ctx, GMAPP_EINVAL, "voxel must be finite and > 0");
     if (min_count < 1) return fail(ctx, GMAPP_EINVAL, "min_count must be >= 1");
+    if (n_spheres < 0 || (n_spheres > 0 && !robot_spheres))
+        return fail(ctx, GMAPP_EINVAL, "n_spheres must be >= 0, with robot_spheres non-NULL when > 0");
     gm::VoxGrid g;
     g.voxel = voxel;
+    g.excl = n_spheres > 0 ? robot_spheres : nullptr;
+    g.n_excl = n_spheres;
     long long cells = 1;
     for (int a = 0; a < 3; ++a) {
         if (!finite(lo[a])) return fail(ctx, GMAPP_EINVAL, "lo must be finite");

@@ -80,6 +80,8 @@ struct VoxGrid {
     float lo[3];
     float voxel;
     int dims[3];
+    const float *excl = nullptr;  // robot self-filter: [n_excl][4] sphere centres and radii, or nullptr
+    int n_excl = 0;
 };
 
 struct Tiling {

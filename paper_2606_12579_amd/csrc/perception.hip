@@ -124,6 +124,23 @@ __device__ __forceinline__ long long cell_of(float px, float py, float pz, const
     return ((long long)fz * g.dims[1] + (long long)fy) * g.dims[0] + (long long)fx;
 }
 
+// Robot self-filter: a point within any of the robot's bounding spheres (centre c,
+// radius r) is dropped.  The test |p - c|^2 <= r^2 is taken in FP64 with every
+// rounding explicit and in a fixed order, (dx dx + dy dy) + dz dz, so it is
+// reproducible on any IEEE machine.
+__device__ __forceinline__ bool on_robot(float px, float py, float pz, const VoxGrid &g)
+{
+    for (int k = 0; k < g.n_excl; ++k) {
+        const float *s = g.excl + 4 * k;
+        const double dx = __dadd_rn((double)px, -(double)s[0]);
+        const double dy = __dadd_rn((double)py, -(double)s[1]);
+        const double dz = __dadd_rn((double)pz, -(double)s[2]);
+        const double d2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+        if (d2 <= __dmul_rn((double)s[3], (double)s[3])) return true;
+    }
+    return false;
+}
+
 // occupancy (min_count 1: a plain store of 1, racing writers store the same value)
 // or counts (atomic increments)
 template <bool COUNT>
@@ -131,7 +148,8 @@ __global__ void k_count(const float *__restrict__ x, const float *__restrict__ y
                         long long n, VoxGrid g, unsigned *__restrict__ grid)
 {
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
-        const long long c = cell_of(x[i], y[i], z[i], g);
+        long long c = cell_of(x[i], y[i], z[i], g);
+        if (c >= 0 && g.n_excl > 0 && on_robot(x[i], y[i], z[i], g)) c = -1;
         if (c >= 0) {
             if constexpr (COUNT) atomicAdd(&grid[c], 1u);
             else grid[c] = 1u;

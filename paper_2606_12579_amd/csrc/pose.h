@@ -75,13 +75,24 @@ __device__ __forceinline__ void so3_log(Q q, float &px, float &py, float &pz)
     px = f * q.x; py = f * q.y; pz = f * q.z;
 }
 
-// out = J(phi) v   (sgn = +1)   or   J(phi)^-1 v   (sgn = -1)
-__device__ __forceinline__ void jac_apply(float px, float py, float pz, float sgn, float vx, float vy, float vz,
-                                          float &ox, float &oy, float &oz)
+// coefficients (a, b) of J(phi) = I + a [phi] + b [phi]^2 (sgn = +1) or of J(phi)^-1 (sgn = -1)
+__device__ __forceinline__ void jac_coeffs(float px, float py, float pz, float sgn, float &a, float &b);
+
+// out = v + a (phi x v) + b phi x (phi x v)
+__device__ __forceinline__ void jac_mul(float px, float py, float pz, float a, float b, float vx, float vy, float vz,
+                                        float &ox, float &oy, float &oz)
+{
+    const float cx = py * vz - pz * vy, cy = pz * vx - px * vz, cz = px * vy - py * vx;     // phi x v
+    const float dx = py * cz - pz * cy, dy = pz * cx - px * cz, dz = px * cy - py * cx;     // phi x (phi x v)
+    ox = vx + a * cx + b * dx;
+    oy = vy + a * cy + b * dy;
+    oz = vz + a * cz + b * dz;
+}
+
+__device__ __forceinline__ void jac_coeffs(float px, float py, float pz, float sgn, float &a, float &b)
 {
     const float t2 = px * px + py * py + pz * pz;
     const float th = sqrtf(t2);
-    float a, b;
     if (sgn > 0.0f) {
         if (th < 0.25f) {
             a = 0.5f - t2 * (1.0f / 24.0f) + t2 * t2 * (1.0f / 720.0f);
@@ -101,11 +112,15 @@ __device__ __forceinline__ void jac_apply(float px, float py, float pz, float sg
             b = 1.0f / t2 - ch / (2.0f * th * sh);
         }
     }
-    const float cx = py * vz - pz * vy, cy = pz * vx - px * vz, cz = px * vy - py * vx;     // phi x v
-    const float dx = py * cz - pz * cy, dy = pz * cx - px * cz, dz = px * cy - py * cx;     // phi x (phi x v)
-    ox = vx + a * cx + b * dx;
-    oy = vy + a * cy + b * dy;
-    oz = vz + a * cz + b * dz;
+}
+
+// out = J(phi) v   (sgn = +1)   or   J(phi)^-1 v   (sgn = -1)
+__device__ __forceinline__ void jac_apply(float px, float py, float pz, float sgn, float vx, float vy, float vz,
+                                          float &ox, float &oy, float &oz)
+{
+    float a, b;
+    jac_coeffs(px, py, pz, sgn, a, b);
+    jac_mul(px, py, pz, a, b, vx, vy, vz, ox, oy, oz);
 }
 
 }  // namespace pose

@@ -307,8 +307,32 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
         }
         const int par = k & 1;
 
+        // pose agents: the parts of the step that do not depend on f_r, computed while the
+        // exchange is in flight -- the attractor's linear wrench, the new angular velocity
+        // (f_r is a pure force), its exponential and the coefficients of J(dt omega)
+        float aLx = 0, aLy = 0, aLz = 0, jA = 0, jB = 0;
+        pose::Q dq{1.f, 0.f, 0.f, 0.f};
+        auto pose_early = [&]() {
+            float phx, phy, phz, tx, ty, tz, rx, ry, rz;
+            pose::so3_log(pose::qmul(pose::Q{qr.w, -qr.x, -qr.y, -qr.z},
+                                     pose::Q{pr.qg[0], pr.qg[1], pr.qg[2], pr.qg[3]}), phx, phy, phz);
+            pose::qrot(qr, -1.0f, gx - px, gy - py, gz - pz, tx, ty, tz);
+            pose::jac_apply(phx, phy, phz, -1.0f, tx, ty, tz, rx, ry, rz);
+            aLx = fmaf(P.ka, rx, -P.da * ux);
+            aLy = fmaf(P.ka, ry, -P.da * uy);
+            aLz = fmaf(P.ka, rz, -P.da * uz);
+            const float hr = 0.5f * pr.dt * P.ir;
+            ox = fmaf(hr, fmaf(P.kr, phx, -P.dr * ox), ox);
+            oy = fmaf(hr, fmaf(P.kr, phy, -P.dr * oy), oy);
+            oz = fmaf(hr, fmaf(P.kr, phz, -P.dr * oz), oz);
+            const float ax = pr.dt * ox, ay = pr.dt * oy, az = pr.dt * oz;
+            dq = pose::so3_exp(ax, ay, az);
+            pose::jac_coeffs(ax, ay, az, 1.0f, jA, jB);
+        };
+
         // running costs that do not depend on this step's force (Eqs. 17, 19, 20): p^(k), v^(k-1), F^(k-1), F^(k-2)
         auto costs_early = [&]() {
+            if constexpr (POSE) pose_early();
             const float ex = gx - px, ey = gy - py, ez = gz - pz;
             const float dgoal = __builtin_amdgcn_sqrtf(fmaf(ez, ez, fmaf(ey, ey, ex * ex)));
             kahan_add(sg, cg, fminf(dgoal, pr.r_cost) * inv_rc);
@@ -419,36 +443,23 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
             }
             if constexpr (POSE) {
                 kahan_add(so, co, 1.0f - fminf(rho_min, pr.r_cost) * inv_rc);
-                // attractor wrench (Eqs. 7, 8): e = log(M^-1 M_g) in the body frame, K = diag(k_r, k_a),
-                // D = diag(d_r, d_a); the repulsive force enters as a pure force, rotated into the body frame
-                float phx, phy, phz;
-                pose::so3_log(pose::qmul(pose::Q{qr.w, -qr.x, -qr.y, -qr.z},
-                                         pose::Q{pr.qg[0], pr.qg[1], pr.qg[2], pr.qg[3]}), phx, phy, phz);
-                float tx, ty, tz, rx, ry, rz, fx, fy, fz;
-                pose::qrot(qr, -1.0f, gx - px, gy - py, gz - pz, tx, ty, tz);
-                pose::jac_apply(phx, phy, phz, -1.0f, tx, ty, tz, rx, ry, rz);
+                // wrench (Eqs. 6-8): the attractor's part (K e - D v, e = log(M^-1 M_g), K = diag(k_r, k_a),
+                // D = diag(d_r, d_a)) came from pose_early; f_r enters as a pure force in the body frame
+                float fx, fy, fz;
                 pose::qrot(qr, -1.0f, Fx_, Fy_, Fz_, fx, fy, fz);
-                const float Flx = fmaf(P.ka, rx, fmaf(-P.da, ux, fx));
-                const float Fly = fmaf(P.ka, ry, fmaf(-P.da, uy, fy));
-                const float Flz = fmaf(P.ka, rz, fmaf(-P.da, uz, fz));
-                const float Fax = fmaf(P.kr, phx, -P.dr * ox);
-                const float Fay = fmaf(P.kr, phy, -P.dr * oy);
-                const float Faz = fmaf(P.kr, phz, -P.dr * oz);
-                // twist (Eqs. 9, 10), inertia diag(i_r, 1/m)
-                const float hr = 0.5f * pr.dt * P.ir;
-                kahan_add(ux, cux, h * Flx);
-                kahan_add(uy, cuy, h * Fly);
-                kahan_add(uz, cuz, h * Flz);
-                ox = fmaf(hr, Fax, ox); oy = fmaf(hr, Fay, oy); oz = fmaf(hr, Faz, oz);
+                // twist (Eqs. 9, 10), inertia diag(i_r, 1/m): omega was advanced in pose_early
+                kahan_add(ux, cux, h * (aLx + fx));
+                kahan_add(uy, cuy, h * (aLy + fy));
+                kahan_add(uz, cuz, h * (aLz + fz));
                 // pose (Eq. 11): M <- M exp(dt v); the translation moves by R J(dt omega) dt u
                 const float ax = pr.dt * ox, ay = pr.dt * oy, az = pr.dt * oz;
                 float jx, jy, jz, dx, dy, dz;
-                pose::jac_apply(ax, ay, az, 1.0f, pr.dt * ux, pr.dt * uy, pr.dt * uz, jx, jy, jz);
+                pose::jac_mul(ax, ay, az, jA, jB, pr.dt * ux, pr.dt * uy, pr.dt * uz, jx, jy, jz);
                 pose::qrot(qr, 1.0f, jx, jy, jz, dx, dy, dz);
                 kahan_add(px, cpx, dx);
                 kahan_add(py, cpy, dy);
                 kahan_add(pz, cpz, dz);
-                qr = pose::qnormalize(pose::qmul(qr, pose::so3_exp(ax, ay, az)));
+                qr = pose::qnormalize(pose::qmul(qr, dq));
                 D3x = D2x; D3y = D2y; D3z = D2z;
                 D2x = D1x; D2y = D1y; D2z = D1z;
                 D1x = dx; D1y = dy; D1z = dz;

@@ -172,6 +172,10 @@ def load_library(path: str = LIB_PATH):
         "gmapp_voxel_downsample": (ctypes.c_int32, [vp, vp, vp, vp, ctypes.c_int64, ctypes.c_float, P(ctypes.c_float),
                                                     P(ctypes.c_int32), ctypes.c_int32, vp, vp, vp, ctypes.c_int64, vp,
                                                     vp]),
+        "gmapp_voxel_downsample_filtered": (ctypes.c_int32, [vp, vp, vp, vp, ctypes.c_int64, ctypes.c_float,
+                                                             P(ctypes.c_float), P(ctypes.c_int32), ctypes.c_int32,
+                                                             vp, ctypes.c_int32, vp, vp, vp, ctypes.c_int64, vp,
+                                                             vp]),
         "gmapp_depth_to_points_batch": (ctypes.c_int32, [vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                                          P(ctypes.c_float), vp, vp, vp, vp, vp]),
         "gmapp_get_tiling": (ctypes.c_int32, [vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
@@ -728,8 +732,10 @@ class Context:
         self._raise(st)
         return out
 
-    def voxel_downsample(self, x, y, z, voxel, lo, dims, min_count=1, capacity=None, out=None, stream=None):
-        """gmapp_voxel_downsample: occupied voxel centres (sorted by cell) and the device count.
+    def voxel_downsample(self, x, y, z, voxel, lo, dims, min_count=1, capacity=None, out=None, stream=None,
+                         robot_spheres=None):
+        """gmapp_voxel_downsample (gmapp_voxel_downsample_filtered with robot_spheres, a device float32 [K, 4]
+        tensor of the robot's bounding spheres): occupied voxel centres (sorted by cell) and the device count.
 
         Returns (ox, oy, oz, n_out) with n_out an int64 [1] device tensor."""
         import torch
@@ -743,9 +749,17 @@ class Context:
                 (torch.zeros(1, dtype=torch.int64, device=self.device),)
         loc = (ctypes.c_float * 3)(*[float(v) for v in np.asarray(lo, np.float32).reshape(3)])
         dc = (ctypes.c_int32 * 3)(*[int(v) for v in np.asarray(dims).reshape(3)])
-        st = self.lib.gmapp_voxel_downsample(self.handle, _ptr(x), _ptr(y), _ptr(z), n, float(voxel), loc, dc,
-                                             int(min_count), _ptr(out[0]), _ptr(out[1]), _ptr(out[2]),
-                                             int(capacity), _ptr(out[3]), self._stream(stream))
+        if robot_spheres is not None:
+            ns = int(robot_spheres.numel()) // 4
+            _check_tensor(robot_spheres, "robot_spheres", 4 * ns, torch.float32, self.device)
+            st = self.lib.gmapp_voxel_downsample_filtered(self.handle, _ptr(x), _ptr(y), _ptr(z), n, float(voxel),
+                                                          loc, dc, int(min_count), _ptr(robot_spheres), ns,
+                                                          _ptr(out[0]), _ptr(out[1]), _ptr(out[2]), int(capacity),
+                                                          _ptr(out[3]), self._stream(stream))
+        else:
+            st = self.lib.gmapp_voxel_downsample(self.handle, _ptr(x), _ptr(y), _ptr(z), n, float(voxel), loc, dc,
+                                                 int(min_count), _ptr(out[0]), _ptr(out[1]), _ptr(out[2]),
+                                                 int(capacity), _ptr(out[3]), self._stream(stream))
         self._raise(st)
         return out
 

@@ -407,3 +407,17 @@ def pose_query(rng: np.random.Generator, max_w: float = 1.0) -> PoseQuery:
     """Random start and goal rotors and a start angular velocity of up to max_w rad/s."""
     q = unit_rotors(rng, 2)
     return PoseQuery(q[0], (rng.uniform(-1, 1, 3) * max_w / np.sqrt(3)).astype(F32), q[1])
+
+
+def robot_spheres(rng: np.random.Generator, n: int = 8, base=(-0.35, -0.05, 0.0), tip=(0.15, 0.1, 0.35),
+                  r=(0.04, 0.08)) -> np.ndarray:
+    """Bounding spheres of a synthetic arm, float32 [n, 4] (centre, radius): n
+    spheres spaced along a bent polyline from base to tip (a stand-in for the FK
+    of a robot's sphere set), radii U[r0, r1], shrinking towards the tip."""
+    base, tip = np.asarray(base, np.float64), np.asarray(tip, np.float64)
+    elbow = 0.5 * (base + tip) + np.array([0.0, 0.15, 0.1])
+    s = np.linspace(0.0, 1.0, n)
+    pts = np.where(s[:, None] < 0.5, base + (elbow - base) * (2 * s[:, None]),
+                   elbow + (tip - elbow) * (2 * s[:, None] - 1))
+    rad = rng.uniform(r[0], r[1], n) * np.linspace(1.0, 0.6, n)
+    return np.concatenate([pts, rad[:, None]], 1).astype(F32)

@@ -86,3 +86,32 @@ def test_voxel_centre_properties_and_idempotence():
     assert np.array_equal(again, cells)
     # the scene really has boxes above the plane and the plane fills the footprint
     assert len(cells) > 11000 and (C[:, 2] > 0.03).sum() > 500
+
+
+def test_robot_self_filter():
+    """Points within the robot's bounding spheres are removed: exact boundary cases
+    (|p - c| = r is removed, one FP32 step further out is kept) and, away from the
+    boundaries, a k-d tree query of the sphere centres."""
+    from scipy.spatial import cKDTree
+    S = np.array([[0.0, 0.0, 0.0, 0.5], [1.0, 1.0, 1.0, 0.25]], np.float32)
+    x = np.array([0.5, np.nextafter(np.float32(0.5), np.float32(1)), 1.0, 1.25, 0.0, 2.0], np.float32)
+    y = np.array([0.0, 0.0, 1.0, 1.0, -0.5, 2.0], np.float32)
+    z = np.array([0.0, 0.0, 1.25, 1.0, 0.0, 2.0], np.float32)
+    assert op.on_robot(x, y, z, S).tolist() == [True, False, True, True, True, False]
+    rng = np.random.default_rng(5)
+    R = scenes.robot_spheres(rng)
+    P = rng.uniform(-0.5, 0.5, (20000, 3)).astype(np.float32)
+    hit = op.on_robot(P[:, 0], P[:, 1], P[:, 2], R)
+    tree = cKDTree(P.astype(np.float64))
+    want = np.zeros(len(P), bool)
+    far = np.ones(len(P), bool)
+    for c in R.astype(np.float64):
+        want[tree.query_ball_point(c[:3], c[3])] = True
+        d = np.linalg.norm(P.astype(np.float64) - c[:3], axis=1)
+        far &= np.abs(d - c[3]) > 1e-6
+    assert 0 < hit.sum() < len(P)
+    assert np.array_equal(hit[far], want[far])
+    cells = op.voxel_cells(P[:, 0], P[:, 1], P[:, 2], 0.01, np.full(3, -0.5, np.float32), [100, 100, 100], 1, R)
+    keep = ~hit
+    ref = op.voxel_cells(P[keep, 0], P[keep, 1], P[keep, 2], 0.01, np.full(3, -0.5, np.float32), [100, 100, 100])
+    assert np.array_equal(cells, ref)

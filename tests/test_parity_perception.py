@@ -213,3 +213,33 @@ def test_batched_rollout_on_device_sphere_world(ctx):
         ref = oracle.rollout(pb)
         gpu = {k: (v.cpu().numpy()[idx] if k != "best" else None) for k, v in j.out.items()}
         gu.compare_rollout(pb, gpu, ref)
+
+
+def test_voxel_robot_self_filter(ctx):
+    """The self-filtered voxel pass gives exactly the oracle's cells on the config-3
+    frame with a synthetic arm's spheres across the scene, including points placed
+    exactly on the sphere surfaces; no spheres is the plain voxel pass."""
+    import torch
+    fr = scenes.config3_frame()
+    P = op.back_project(fr.depth, fr.K, fr.T_wc).astype(np.float32)
+    R = scenes.robot_spheres(np.random.default_rng(9), base=(-0.3, -0.05, 0.0), tip=(0.2, 0.1, 0.3))
+    surf = np.array([[c[0] + c[3], c[1], c[2]] for c in R], np.float32)      # on each surface (x + r)
+    P = np.concatenate([P, surf, np.nextafter(surf, np.float32(9))], 0)
+    hit = op.on_robot(P[:, 0], P[:, 1], P[:, 2], R)
+    t = [torch.as_tensor(np.ascontiguousarray(P[:, a]), device="cuda") for a in range(3)]
+    Rd = torch.as_tensor(R, device="cuda")
+    for min_count in (1, 2):
+        cells = op.voxel_cells(P[:, 0], P[:, 1], P[:, 2], fr.voxel, fr.box_lo, fr.dims, min_count, R)
+        ox, oy, oz, n = ctx.voxel_downsample(*t, fr.voxel, fr.box_lo, fr.dims, min_count=min_count,
+                                             robot_spheres=Rd)
+        torch.cuda.synchronize()
+        n = int(n.item())
+        assert n == len(cells), (n, len(cells))
+        G = np.stack([ox[:n].cpu().numpy(), oy[:n].cpu().numpy(), oz[:n].cpu().numpy()], 1)
+        assert np.array_equal(G, op.voxel_centres(cells, fr.voxel, fr.box_lo, fr.dims).astype(np.float32))
+    print(f"self-filter: {int(hit.sum())} of {len(P)} points on the robot", flush=True)
+    plain = op.voxel_cells(P[:, 0], P[:, 1], P[:, 2], fr.voxel, fr.box_lo, fr.dims, 1)
+    ox, oy, oz, n = ctx.voxel_downsample(*t, fr.voxel, fr.box_lo, fr.dims,
+                                         robot_spheres=torch.zeros((0, 4), dtype=torch.float32, device="cuda"))
+    torch.cuda.synchronize()
+    assert int(n.item()) == len(plain)

@@ -203,7 +203,7 @@ gmapp_status gmapp_rollout_pose(gmapp_ctx *ctx, const gmapp_scene *scene, const 
  *   cost        [n_cycles][N_a][5]               each cycle's costs (as gmapp_outputs.cost)
  *   n_switches  [1]                              N_sw
  * EINVAL for n_cycles < 1, ctrl_steps < 1, ctrl_dt not finite and > 0, N_a = 0 or
- * a NULL required output. */
+ * a NULL required output; ECAPACITY for a scene of more than 128 segments. */
 typedef struct {
     int32_t n_cycles;     /* planning cycles, >= 1 */
     int32_t ctrl_steps;   /* control steps of the robot per cycle, >= 1 */
@@ -225,7 +225,8 @@ gmapp_status gmapp_plan_loop(gmapp_ctx *ctx, const gmapp_scene *scene, const gma
 /* The control thread's query (Sec. V-B): the repulsive force f_r (Alg. 1, the
  * agent's own field) of the agent whose index is read from agent (device int32
  * [1]) at the state (device [6]: p, v) and time t, and rho_min.  f_r: device [3];
- * rho_min: device [1] or NULL.  An index outside [0, N_a) gives NaN outputs. */
+ * rho_min: device [1] or NULL.  An index outside [0, N_a) gives NaN outputs.
+ * ECAPACITY for a scene of more than 128 segments. */
 gmapp_status gmapp_control_force(gmapp_ctx *ctx, const gmapp_scene *scene, const gmapp_agents *agents,
                                  const int32_t *agent, const float *state, float t, const gmapp_params *params,
                                  float *f_r, float *rho_min, void *stream);

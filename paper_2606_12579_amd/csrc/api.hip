@@ -318,6 +318,8 @@ gmapp_status gmapp_plan_loop(gmapp_ctx *ctx, const gmapp_scene *scene, const gma
     if (cfg->ctrl_steps < 1) return fail(ctx, GMAPP_EINVAL, "ctrl_steps must be >= 1");
     if (!finite(cfg->ctrl_dt) || !(cfg->ctrl_dt > 0.0f)) return fail(ctx, GMAPP_EINVAL, "ctrl_dt must be finite and > 0");
     if (agents->n_agents < 1) return fail(ctx, GMAPP_EINVAL, "the planning loop needs at least one agent");
+    if (scene->n_seg > gm::kMaxControlSegments)
+        return fail(ctx, GMAPP_ECAPACITY, "the control steps take at most %d segments", gm::kMaxControlSegments);
     if (!out || !out->robot || !out->best || !out->cost || !out->n_switches)
         return fail(ctx, GMAPP_EINVAL, "loop outputs robot, best, cost and n_switches must be non-NULL");
     if ((long long)cfg->n_cycles * cfg->ctrl_steps > (long long)INT32_MAX)
@@ -336,6 +338,8 @@ gmapp_status gmapp_control_force(gmapp_ctx *ctx, const gmapp_scene *scene, const
     if ((st = check_scene(ctx, scene)) || (st = check_agents(ctx, agents)) || (st = check_params(ctx, params, false)))
         return st;
     if (!agent || !state || !f_r) return fail(ctx, GMAPP_EINVAL, "agent, state and f_r must be non-NULL");
+    if (scene->n_seg > gm::kMaxControlSegments)
+        return fail(ctx, GMAPP_ECAPACITY, "the control query takes at most %d segments", gm::kMaxControlSegments);
     if (!finite(t)) return fail(ctx, GMAPP_EINVAL, "t must be finite");
     return gm::launch_control_force(ctx, dev_scene(scene), dev_agents(agents), dev_params(params, nullptr), agent,
                                     state, t, f_r, rho_min, static_cast<hipStream_t>(stream));

@@ -5,18 +5,25 @@
 // agent i* (k_control).  Nothing returns to the host between cycles, so a loop
 // of C cycles is 2 C + 1 launches in stream order.
 //
-// k_control is one workgroup of 1024 lanes.  At every control step each lane
-// sums i*'s field (the same pair functions as the rollout: circular field with
-// omega or with the velocity current, or the APF) over a strided share of the
-// spheres, segment by segment; the partials are reduced in a fixed order (wave
-// DPP reduction, then the 16 wave sums in index order), and lane 0 applies the
-// attractor (Eq. 7) and the integration of Eqs. 9-11 with the control period,
-// with Kahan-compensated velocity and position, and hands the new state to all
-// lanes through LDS.  With zero steps the kernel answers the control thread's
-// query: f_r and rho_min at a given state.
+// k_control spreads each control step over NG workgroups of 256 lanes (a
+// cooperative launch; NG = 1 for small clouds).  Workgroup g owns a contiguous
+// chunk of the spheres, which it copies into LDS once (the chunk is the same at
+// every control step; chunks too large for LDS are read from memory instead).
+// Every lane sums i*'s field (the same pair functions as the rollout: circular
+// field with omega or with the velocity current, or the APF) over a strided part
+// of the chunk, segment by segment, and each workgroup reduces its share in a
+// fixed order.  The NG
+// partials meet through the context's exchange area: one 4-lane device-scope
+// store of four tagged words per workgroup, polled by lane g of wave 0 for
+// workgroup g, then a DPP all-reduce across the wave, so every workgroup holds
+// the same total bit for bit and integrates the robot identically (attractor of
+// Eq. 7, Eqs. 9-11 with the control period, Kahan-compensated velocity and
+// position).  Workgroup 0 writes the outputs.  With zero steps the kernel answers
+// the control thread's query: f_r and rho_min at a given state.
 #include "gmapp_internal.h"
 #include "pairs.h"
 
+#include <algorithm>
 #include <cmath>
 
 namespace gm {
@@ -25,8 +32,12 @@ using namespace dev;
 
 namespace {
 
-constexpr int kCtlThreads = 1024;
+constexpr int kCtlThreads = 256;
 constexpr int kCtlWaves = kCtlThreads / 64;
+constexpr int kCtlMaxGroups = 64;                 // one wave polls every workgroup's slot
+constexpr long long kCtlPointsPerGroup = 2048;
+constexpr size_t kCtlLdsBytes = 96 * 1024;        // largest chunk staged in LDS
+constexpr int kCtlMaxRuns = kMaxControlSegments; // segment runs of a chunk held in LDS
 
 struct Ctl {
     float *state;       // [steps + 1][6]: row 0 is read, rows 1..steps are written
@@ -38,58 +49,110 @@ struct Ctl {
     float *f_out;       // query mode: f_r [3]
     float t0, dt;       // time of step 0, control period
     int steps;          // 0 = query mode
+    int staged;         // 1: each workgroup's chunk is held in LDS
 };
 
-// This lane's share of agent P's repulsive force at (p, v) and time t, and of min |d|^2.
+// A run: the part [b, e) of one segment (moving with velocity v) inside a chunk.
+struct Run {
+    long long b, e;
+    float vx, vy, vz;
+};
+
+// This lane's part of agent P's repulsive force at (p, v) and time t, and of min |d|^2,
+// over the runs of its workgroup's chunk [c0, c1) (points in LDS at cl, or in memory
+// when cl is null).
 template <int CUT>
-__device__ __forceinline__ void control_share(const Scn &sc, long long n_pts, const Agent &P, float eps, float px,
-                                              float py, float pz, float vx, float vy, float vz, float t, int tid,
-                                              float &Fx, float &Fy, float &Fz, float &m2)
+__device__ __forceinline__ void control_share(const Scn &sc, const Run *runs, int n_runs, long long c0,
+                                              const float *cl, const Agent &P, float eps, float px, float py,
+                                              float pz, float vx, float vy, float vz, float t, int tid, float &Fx,
+                                              float &Fy, float &Fz, float &m2)
 {
-    const int nseg = sc.n_seg > 0 ? sc.n_seg : 1;
-    for (int g = 0; g < nseg; ++g) {
-        long long b = 0, e = n_pts;
-        float ox = 0.f, oy = 0.f, oz = 0.f;
-        if (sc.n_seg > 0) {
-            b = min(max((long long)sc.seg_begin[g], 0ll), n_pts);
-            e = min(max((long long)sc.seg_begin[g + 1], b), n_pts);
-            ox = sc.seg_vel[3 * g]; oy = sc.seg_vel[3 * g + 1]; oz = sc.seg_vel[3 * g + 2];
+    auto point = [&](long long j, float &qx, float &qy, float &qz) {
+        if (cl) {
+            const float *q = cl + 3 * (j - c0);
+            qx = q[0]; qy = q[1]; qz = q[2];
+        } else {
+            qx = sc.x[j]; qy = sc.y[j]; qz = sc.z[j];
         }
+    };
+    for (int r = 0; r < n_runs; ++r) {
+        const Run rn = runs[r];
         // agent position relative to the moving segment
-        const float psx = fmaf(-t, ox, px), psy = fmaf(-t, oy, py), psz = fmaf(-t, oz, pz);
+        const float psx = fmaf(-t, rn.vx, px), psy = fmaf(-t, rn.vy, py), psz = fmaf(-t, rn.vz, pz);
         if (P.hz == 2) {
             float Ax = 0, Ay = 0, Az = 0;
-            for (long long j = b + tid; j < e; j += kCtlThreads)
-                interact_apf<CUT>(sc.x[j], sc.y[j], sc.z[j], psx, psy, psz, P.R, eps, P.rd, P.ird, P.tb_a, P.tb_b, Ax,
-                                  Ay, Az, m2);
+#pragma unroll 4
+            for (long long j = rn.b + tid; j < rn.e; j += kCtlThreads) {
+                float qx, qy, qz;
+                point(j, qx, qy, qz);
+                interact_apf<CUT>(qx, qy, qz, psx, psy, psz, P.R, eps, P.rd, P.ird, P.tb_a, P.tb_b, Ax, Ay, Az, m2);
+            }
             Fx = fmaf(P.kf, Ax, Fx); Fy = fmaf(P.kf, Ay, Fy); Fz = fmaf(P.kf, Az, Fz);
         } else {
-            const float ux = vx - ox, uy = vy - oy, uz = vz - oz;
+            const float ux = vx - rn.vx, uy = vy - rn.vy, uz = vz - rn.vz;
             const bool cur = P.hz == 1;
             const float cwx = cur ? ux : P.wx, cwy = cur ? uy : P.wy, cwz = cur ? uz : P.wz;
             float G = 0, Sx = 0, Sy = 0, Sz = 0;
-            for (long long j = b + tid; j < e; j += kCtlThreads)
-                interact<CUT>(sc.x[j], sc.y[j], sc.z[j], psx, psy, psz, cwx, cwy, cwz, P.R, eps, P.rd, P.tb_a, P.tb_b,
-                              G, Sx, Sy, Sz, m2);
+#pragma unroll 4
+            for (long long j = rn.b + tid; j < rn.e; j += kCtlThreads) {
+                float qx, qy, qz;
+                point(j, qx, qy, qz);
+                interact<CUT>(qx, qy, qz, psx, psy, psz, cwx, cwy, cwz, P.R, eps, P.rd, P.tb_a, P.tb_b, G, Sx, Sy, Sz,
+                              m2);
+            }
             project_add(ux, uy, uz, P.kf, cwx, cwy, cwz, G, Sx, Sy, Sz, Fx, Fy, Fz);
         }
     }
 }
 
 template <int CUT>
-__global__ __launch_bounds__(kCtlThreads) void k_control(Scn sc, Agt ag, Prm pr, Ctl c)
+__global__ __launch_bounds__(kCtlThreads) void k_control(Scn sc, Agt ag, Prm pr, Ctl c, Xch xc)
 {
     __shared__ float4 red[kCtlWaves];
-    __shared__ float st[6];
+    __shared__ float st[8];
+    __shared__ int s_last, s_nruns;
+    __shared__ Run s_runs[kCtlMaxRuns];
+    extern __shared__ float4 cl4[];           // staged chunk, x y z interleaved
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int NG = gridDim.x, wg = blockIdx.x;
+    const bool out_wg = wg == 0;
     const int a = c.best[0];
     const bool ok = a >= 0 && a < ag.n;
-    if (tid == 0 && c.n_switch) {
+    if (out_wg && tid == 0 && c.n_switch) {
         const int prev = c.prev ? c.prev[0] : c.prev_host;
         if (prev >= 0 && ok && a != prev) c.n_switch[0] += 1;
     }
     long long n_pts = sc.n_cap;
     if (sc.n_dev) n_pts = min(max(*sc.n_dev, 0ll), sc.n_cap);
+    const long long c0 = n_pts * wg / NG, c1 = n_pts * (wg + 1) / NG;
+    // the chunk's runs (segment parts and their velocities), listed once
+    if (tid == 0) {
+        int nr = 0;
+        if (sc.n_seg <= 0) {
+            if (c0 < c1) s_runs[nr++] = Run{c0, c1, 0.f, 0.f, 0.f};
+        } else {
+            for (int g = 0; g < sc.n_seg; ++g) {
+                long long b = min(max((long long)sc.seg_begin[g], 0ll), n_pts);
+                long long e = min(max((long long)sc.seg_begin[g + 1], b), n_pts);
+                b = max(b, c0);
+                e = min(e, c1);
+                if (b >= e) continue;
+                if (nr == kCtlMaxRuns) break;         // the host admits at most kCtlMaxRuns segments
+                s_runs[nr++] = Run{b, e, sc.seg_vel[3 * g], sc.seg_vel[3 * g + 1], sc.seg_vel[3 * g + 2]};
+            }
+        }
+        s_nruns = nr;
+    }
+    __syncthreads();
+    const int n_runs = s_nruns;
+    float *cl = nullptr;
+    if (c.staged) {
+        cl = reinterpret_cast<float *>(cl4);
+        for (long long i = tid; i < c1 - c0; i += kCtlThreads) {
+            cl[3 * i] = sc.x[c0 + i]; cl[3 * i + 1] = sc.y[c0 + i]; cl[3 * i + 2] = sc.z[c0 + i];
+        }
+        __syncthreads();
+    }
     Agent P;
     const int ai = ok ? a : 0;
     P.ka = ok ? ag.k_a[ai] : 0.f;
@@ -112,49 +175,115 @@ __global__ __launch_bounds__(kCtlThreads) void k_control(Scn sc, Agt ag, Prm pr,
     const float gx = pr.goal[0], gy = pr.goal[1], gz = pr.goal[2];
     const float h = 0.5f * c.dt * pr.inv_mass;
     const int iters = c.steps > 0 ? c.steps : 1;
-    for (int j = 0; j < iters; ++j) {
+    const unsigned long long t_start = __builtin_amdgcn_s_memrealtime();
+    bool failed = false;
+    for (int j = 0; j < iters && !failed; ++j) {
         const float t = fmaf((float)j, c.dt, c.t0);
         float Fx = 0, Fy = 0, Fz = 0, m2 = INFINITY;
-        if (ok) control_share<CUT>(sc, n_pts, P, pr.eps, px, py, pz, vx, vy, vz, t, tid, Fx, Fy, Fz, m2);
+        if (ok) control_share<CUT>(sc, s_runs, n_runs, c0, cl, P, pr.eps, px, py, pz, vx, vy, vz, t, tid, Fx, Fy, Fz, m2);
         Fx = agent_allreduce<1, false>(Fx);
         Fy = agent_allreduce<1, false>(Fy);
         Fz = agent_allreduce<1, false>(Fz);
         m2 = agent_allreduce<1, true>(m2);
         if (lane == 0) red[wave] = make_float4(Fx, Fy, Fz, m2);
         __syncthreads();
-        if (tid == 0) {
+        if (wave == 0) {
             float4 acc = red[0];
             for (int w = 1; w < kCtlWaves; ++w) {
                 const float4 q = red[w];
                 acc.x += q.x; acc.y += q.y; acc.z += q.z; acc.w = fminf(acc.w, q.w);
             }
-            float rho = (acc.w < INFINITY) ? fmaxf(sqrtf(acc.w) - P.R, pr.eps) : INFINITY;
-            if (!ok) rho = NAN;
-            if (c.steps == 0) {
-                c.f_out[0] = ok ? acc.x : NAN;
-                c.f_out[1] = ok ? acc.y : NAN;
-                c.f_out[2] = ok ? acc.z : NAN;
-                if (c.clear) c.clear[0] = rho;
-            } else {
-                if (ok) {
-                    const float Ftx = fmaf(P.ka, gx - px, fmaf(-P.da, vx, acc.x));
-                    const float Fty = fmaf(P.ka, gy - py, fmaf(-P.da, vy, acc.y));
-                    const float Ftz = fmaf(P.ka, gz - pz, fmaf(-P.da, vz, acc.z));
-                    kahan_add(vx, cvx, h * Ftx);
-                    kahan_add(vy, cvy, h * Fty);
-                    kahan_add(vz, cvz, h * Ftz);
-                    kahan_add(px, cpx, c.dt * vx);
-                    kahan_add(py, cpy, c.dt * vy);
-                    kahan_add(pz, cpz, c.dt * vz);
+            if (NG > 1) {
+                // publish this workgroup's four words, then gather every workgroup's
+                const unsigned tag = (unsigned)(j + 1);
+                unsigned long long *area = xc.partial + (size_t)(j & 1) * 4 * NG;
+                if (lane < 4) {
+                    const float v = lane == 0 ? acc.x : lane == 1 ? acc.y : lane == 2 ? acc.z : acc.w;
+                    st64_agent(area + 4 * wg + lane, xword(v, tag));
                 }
-                float *row = c.state + 6 * (size_t)(j + 1);
-                row[0] = px; row[1] = py; row[2] = pz; row[3] = vx; row[4] = vy; row[5] = vz;
-                if (c.clear) c.clear[j] = rho;
-                st[0] = px; st[1] = py; st[2] = pz; st[3] = vx; st[4] = vy; st[5] = vz;
+                unsigned long long q0 = 0, q1 = 0, q2 = 0, q3 = 0;
+                const bool poller = lane < NG;
+                unsigned spins = 0;
+                while (true) {
+                    if (poller) {
+                        const unsigned long long *slot = area + 4 * lane;
+                        q0 = ld64_agent(slot); q1 = ld64_agent(slot + 1); q2 = ld64_agent(slot + 2);
+                        q3 = ld64_agent(slot + 3);
+                    }
+                    const bool mine = !poller || (xtag(q0) == tag && xtag(q1) == tag && xtag(q2) == tag &&
+                                                  xtag(q3) == tag);
+                    if (__all(mine)) break;
+                    if ((++spins & 63u) == 0) {
+                        if (ld_agent(xc.status) != 0u ||
+                            __builtin_amdgcn_s_memrealtime() - t_start > kWatchdogTicks) {
+                            if (lane == 0) st_agent(xc.status, 1u);
+                            failed = true;
+                            break;
+                        }
+                    }
+                }
+                float sx = poller ? xval(q0) : 0.f, sy = poller ? xval(q1) : 0.f;
+                float sz = poller ? xval(q2) : 0.f, sm = poller ? xval(q3) : INFINITY;
+                sx = agent_allreduce<1, false>(sx);
+                sy = agent_allreduce<1, false>(sy);
+                sz = agent_allreduce<1, false>(sz);
+                sm = agent_allreduce<1, true>(sm);
+                acc = make_float4(sx, sy, sz, sm);
+            }
+            if (lane == 0) {
+                float rho = (acc.w < INFINITY) ? fmaxf(sqrtf(acc.w) - P.R, pr.eps) : INFINITY;
+                if (!ok || failed) rho = NAN;
+                if (c.steps == 0) {
+                    if (out_wg) {
+                        c.f_out[0] = (ok && !failed) ? acc.x : NAN;
+                        c.f_out[1] = (ok && !failed) ? acc.y : NAN;
+                        c.f_out[2] = (ok && !failed) ? acc.z : NAN;
+                        if (c.clear) c.clear[0] = rho;
+                    }
+                } else {
+                    if (failed) {
+                        px = py = pz = vx = vy = vz = NAN;
+                    } else if (ok) {
+                        const float Ftx = fmaf(P.ka, gx - px, fmaf(-P.da, vx, acc.x));
+                        const float Fty = fmaf(P.ka, gy - py, fmaf(-P.da, vy, acc.y));
+                        const float Ftz = fmaf(P.ka, gz - pz, fmaf(-P.da, vz, acc.z));
+                        kahan_add(vx, cvx, h * Ftx);
+                        kahan_add(vy, cvy, h * Fty);
+                        kahan_add(vz, cvz, h * Ftz);
+                        kahan_add(px, cpx, c.dt * vx);
+                        kahan_add(py, cpy, c.dt * vy);
+                        kahan_add(pz, cpz, c.dt * vz);
+                    }
+                    if (out_wg) {
+                        float *row = c.state + 6 * (size_t)(j + 1);
+                        row[0] = px; row[1] = py; row[2] = pz; row[3] = vx; row[4] = vy; row[5] = vz;
+                        if (c.clear) c.clear[j] = rho;
+                    }
+                    st[0] = px; st[1] = py; st[2] = pz; st[3] = vx; st[4] = vy; st[5] = vz;
+                }
+                st[6] = failed ? 1.f : 0.f;
             }
         }
         __syncthreads();
         px = st[0]; py = st[1]; pz = st[2]; vx = st[3]; vy = st[4]; vz = st[5];
+        failed = st[6] != 0.f;
+    }
+    if (NG > 1) {
+        // the last workgroup out clears the exchange words and the counters for the next launch
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __syncthreads();
+        if (tid == 0) {
+            const unsigned prev = __hip_atomic_fetch_add(xc.done, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            s_last = prev == (unsigned)(NG - 1) ? 1 : 0;
+        }
+        __syncthreads();
+        if (!s_last) return;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        for (int i = tid; i < 8 * NG; i += kCtlThreads) st64_agent(xc.partial + i, 0ull);
+        if (tid == 0) {
+            st_agent(xc.status, 0u);
+            st_agent(xc.done, 0u);
+        }
     }
 }
 
@@ -170,9 +299,31 @@ __global__ void k_loop_init(float *robot, float p0x, float p0y, float p0z, float
 gmapp_status launch_control(gmapp_ctx *ctx, const Scn &sc, const Agt &ag, const Prm &pr, const Ctl &c,
                             hipStream_t stream)
 {
-    if (pr.cutoff) hipLaunchKernelGGL(k_control<1>, dim3(1), dim3(kCtlThreads), 0, stream, sc, ag, pr, c);
-    else hipLaunchKernelGGL(k_control<0>, dim3(1), dim3(kCtlThreads), 0, stream, sc, ag, pr, c);
-    GM_HIP(ctx, hipGetLastError());
+    const long long ng = (sc.n_cap + kCtlPointsPerGroup - 1) / kCtlPointsPerGroup;
+    const int cap = std::max(1, std::min(kCtlMaxGroups, ctx->n_cu));
+    const int NG = (int)std::min<long long>(std::max<long long>(ng, 1), cap);
+    // largest chunk: n * (g + 1) / NG - n * g / NG <= ceil(n / NG) for the capacity n >= N_O
+    const size_t chunk = (size_t)((sc.n_cap + NG - 1) / NG);
+    const size_t shm = chunk * 3 * sizeof(float);
+    Ctl c_ = c;
+    c_.staged = (shm > 0 && shm <= kCtlLdsBytes) ? 1 : 0;
+    const unsigned dyn = c_.staged ? (unsigned)shm : 0u;
+    Xch xc;
+    xc.partial = ctx->xchg;
+    xc.flags = ctx->sync;
+    xc.done = ctx->sync + kCounterWords;
+    xc.status = ctx->sync + kCounterWords + 16;
+    xc.S = NG;
+    xc.G = 1;
+    const void *fn = pr.cutoff ? reinterpret_cast<const void *>(k_control<1>)
+                               : reinterpret_cast<const void *>(k_control<0>);
+    Scn s_ = sc;
+    Agt a_ = ag;
+    Prm p_ = pr;
+    void *args[] = {(void *)&s_, (void *)&a_, (void *)&p_, (void *)&c_, (void *)&xc};
+    GM_HIP(ctx, hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kCtlLdsBytes));
+    if (NG > 1) GM_HIP(ctx, hipLaunchCooperativeKernel(fn, dim3(NG), dim3(kCtlThreads), args, dyn, stream));
+    else GM_HIP(ctx, hipLaunchKernel(fn, dim3(1), dim3(kCtlThreads), args, dyn, stream));
     return GMAPP_OK;
 }
 

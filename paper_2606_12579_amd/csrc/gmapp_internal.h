@@ -202,6 +202,7 @@ Tiling choose_tiling(const gmapp_ctx *ctx, long long n_points, int n_agents, int
 gmapp_status fit_coresident(gmapp_ctx *ctx, Tiling &t, const Scn &sc, const Agt &ag, const Prm &pr);
 
 // closed planning loop and the control query (control.hip)
+constexpr int kMaxControlSegments = 128;
 gmapp_status launch_plan_loop(gmapp_ctx *ctx, const Scn &sc, const Agt &ag, const Prm &pr0, const Tiling &t,
                               const gmapp_loop_config &cfg, const gmapp_loop_outputs &o, hipStream_t stream);
 gmapp_status launch_control_force(gmapp_ctx *ctx, const Scn &sc, const Agt &ag, const Prm &pr, const int *agent,

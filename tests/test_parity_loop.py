@@ -75,6 +75,8 @@ CASES = {
     "moving_multi": lambda: (_multi(scenes.tiny(8, n_points=200, n_agents=9, n_steps=50, moving=True)), 8, 5, 0.005),
     "taper": lambda: (scenes.tiny(9, n_points=150, n_agents=6, n_steps=50, cutoff=1), 6, 8, 0.01),
     "objects_switch": lambda: (_switching(), 10, 10, 0.01),
+    # 50,000 moving points: each control step spans 25 workgroups meeting through the exchange
+    "objects_large": lambda: (scenes.config2(n_agents=16, n_steps=60), 4, 10, 0.01),
 }
 
 
@@ -91,7 +93,9 @@ def test_plan_loop(ctx, case):
     pb, C, J, dtc = CASES[case]()
     _log(f"loop {case}: {C} cycles x {J} control steps of {dtc} s, N_a {pb.agents.n}, N_k {pb.params.n_steps}")
     ref = oracle.plan_loop(pb, C, J, dtc)
-    for tiling in (None, (1, 8, 4, 0, 0, 2), (2, 1, 2, 0, 1, 1)):
+    # a forced LDS-resident layout cannot hold the large scene's 25,000-point shards: stream it instead
+    last = (8, 4, 1, 256, 2, 1) if case == "objects_large" else (2, 1, 2, 0, 1, 1)
+    for tiling in (None, (1, 8, 4, 0, 0, 2), last):
         gpu = _run(ctx, pb, C, J, dtc, tiling)
         err = _compare(pb, gpu, ref)
         _log(f"  tiling {tiling}: best {gpu['best'].tolist()} N_sw {int(gpu['n_switches'][0])} pos err {err:.2e}")
@@ -127,7 +131,8 @@ def test_control_force(ctx):
     gives NaN."""
     import torch
     from paper_2606_12579_amd import gmapp
-    for pb in (_multi(scenes.config1()), _multi(scenes.tiny(8, n_points=200, n_agents=9, n_steps=50, moving=True))):
+    for pb in (_multi(scenes.config1()), _multi(scenes.tiny(8, n_points=200, n_agents=9, n_steps=50, moving=True)),
+               _multi(scenes.config2(n_agents=6, n_steps=30))):
         ref = oracle.rollout(pb)
         sc, ag = gmapp.scene_to_device(pb.scene), gmapp.agents_to_device(pb.agents)
         worst = 0.0

@@ -183,6 +183,29 @@ gmapp_status gmapp_rollout_pose(gmapp_ctx *ctx, const gmapp_scene *scene, const 
                                 const gmapp_pose_query *pose_query, const gmapp_params *params,
                                 const gmapp_outputs *out, float *rot, void *stream);
 
+/* Arm agents (Sec. IV-A Eqs. 12-14): each agent drives a serial chain of n revolute
+ * joints about their local z axes, M(q) = L_0 Rz(q_1) L_1 ... Rz(q_n) L_n.  Per
+ * step the wrench and twist are those of gmapp_rollout_pose (Eqs. 6-10) at the
+ * end-effector pose M(q); then qdot = J_b^T (J_b J_b^T + damping^2 I)^-1 v with
+ * J_b the body Jacobian of M, q += dt qdot, and M = M(q).  Costs are taken on the
+ * end-effector positions.  The start pose is M(q0): the query's p0 and the pose
+ * query's q0 are not used; v0 (world, linear) and w0 (body, angular) give the
+ * start twist, goal and qg the goal pose. */
+typedef struct {
+    int32_t n_joints;      /* 1..7 */
+    const float *links;    /* device [n_joints + 1][7]: L_i as rotor (w, x, y, z) and offset (x, y, z) */
+    const float *q0;       /* device [n_joints]: start joint angles [rad] */
+    float damping;         /* lambda >= 0 of the damped pseudo-inverse (0: J_b^T (J_b J_b^T)^-1) */
+} gmapp_arm;
+
+/* Forward rollout of arm agents: outputs as gmapp_rollout_pose, plus joints:
+ * device [N_a][N_k + 1][n_joints] joint angles or NULL.  EINVAL for a NULL arm,
+ * n_joints outside 1..7, NULL links or q0, or a damping that is not finite and >= 0. */
+gmapp_status gmapp_rollout_arm(gmapp_ctx *ctx, const gmapp_scene *scene, const gmapp_agents *agents,
+                               const gmapp_pose_agents *pose, const gmapp_arm *arm, const gmapp_query *query,
+                               const gmapp_pose_query *pose_query, const gmapp_params *params,
+                               const gmapp_outputs *out, float *rot, float *joints, void *stream);
+
 /* Closed planning loop (Sec. V-B, planner architecture; selection rule of Sec. IV-A
  * across cycles).  The robot is a point mass like the agents.  Cycle c = 0 ..
  * n_cycles - 1 runs, in stream order and with no host round trip:

@@ -261,10 +261,39 @@ gmapp_status gmapp_force_probe(gmapp_ctx *ctx, const gmapp_scene *scene, const g
                               static_cast<hipStream_t>(stream));
 }
 
+namespace {
+
+// shared by the pose and arm entry points: validation and launch of the 6-D rollout
+gmapp_status rollout_6d(gmapp_ctx *ctx, const gmapp_scene *scene, const gmapp_agents *agents,
+                        const gmapp_pose_agents *pose, const gmapp_arm *arm, const gmapp_query *query,
+                        const gmapp_pose_query *pose_query, const gmapp_params *params, const gmapp_outputs *out,
+                        float *rot, float *joints, void *stream);
+
+}  // namespace
+
 gmapp_status gmapp_rollout_pose(gmapp_ctx *ctx, const gmapp_scene *scene, const gmapp_agents *agents,
                                 const gmapp_pose_agents *pose, const gmapp_query *query,
                                 const gmapp_pose_query *pose_query, const gmapp_params *params,
                                 const gmapp_outputs *out, float *rot, void *stream)
+{
+    return rollout_6d(ctx, scene, agents, pose, nullptr, query, pose_query, params, out, rot, nullptr, stream);
+}
+
+gmapp_status gmapp_rollout_arm(gmapp_ctx *ctx, const gmapp_scene *scene, const gmapp_agents *agents,
+                               const gmapp_pose_agents *pose, const gmapp_arm *arm, const gmapp_query *query,
+                               const gmapp_pose_query *pose_query, const gmapp_params *params,
+                               const gmapp_outputs *out, float *rot, float *joints, void *stream)
+{
+    if (ctx && !arm) return fail(ctx, GMAPP_EINVAL, "arm is NULL");
+    return rollout_6d(ctx, scene, agents, pose, arm, query, pose_query, params, out, rot, joints, stream);
+}
+
+namespace {
+
+gmapp_status rollout_6d(gmapp_ctx *ctx, const gmapp_scene *scene, const gmapp_agents *agents,
+                        const gmapp_pose_agents *pose, const gmapp_arm *arm, const gmapp_query *query,
+                        const gmapp_pose_query *pose_query, const gmapp_params *params, const gmapp_outputs *out,
+                        float *rot, float *joints, void *stream)
 {
     gmapp_status st = check_ctx(ctx);
     if (st) return st;
@@ -278,8 +307,15 @@ gmapp_status gmapp_rollout_pose(gmapp_ctx *ctx, const gmapp_scene *scene, const 
         const float n = q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
         return finite(q[0]) && finite(q[1]) && finite(q[2]) && finite(q[3]) && finite(n) && n > 0.0f;
     };
-    if (!rotor_ok(pose_query->q0) || !rotor_ok(pose_query->qg))
+    if ((!arm && !rotor_ok(pose_query->q0)) || !rotor_ok(pose_query->qg))
         return fail(ctx, GMAPP_EINVAL, "q0 and qg must be finite rotors with a non-zero norm");
+    if (arm) {
+        if (arm->n_joints < 1 || arm->n_joints > gm::kMaxArmJoints)
+            return fail(ctx, GMAPP_EINVAL, "n_joints must be in [1, %d]", gm::kMaxArmJoints);
+        if (!arm->links || !arm->q0) return fail(ctx, GMAPP_EINVAL, "arm links and q0 must be non-NULL");
+        if (!finite(arm->damping) || arm->damping < 0.0f)
+            return fail(ctx, GMAPP_EINVAL, "damping must be finite and >= 0");
+    }
     if (!finite(pose_query->w0[0]) || !finite(pose_query->w0[1]) || !finite(pose_query->w0[2]))
         return fail(ctx, GMAPP_EINVAL, "w0 must be finite");
     if (!out || !out->best) return fail(ctx, GMAPP_EINVAL, "outputs.best is NULL");
@@ -297,12 +333,20 @@ gmapp_status gmapp_rollout_pose(gmapp_ctx *ctx, const gmapp_scene *scene, const 
         pr.qg[a] = pose_query->qg[a];
     }
     for (int a = 0; a < 3; ++a) pr.om0[a] = pose_query->w0[a];
+    if (arm) {
+        pr.arm_links = arm->links;
+        pr.arm_q0 = arm->q0;
+        pr.arm_n = arm->n_joints;
+        pr.arm_lam2 = arm->damping * arm->damping;
+    }
     const gm::Scn sc = dev_scene(scene);
     // the pose kernels hold more registers: a chosen tiling may need fewer shards to stay co-resident
     if (!ctx->forced && (st = gm::fit_coresident(ctx, t, sc, ag, pr))) return st;
-    gm::Out o{out->traj, out->cost, out->min_clear, out->best, rot};
+    gm::Out o{out->traj, out->cost, out->min_clear, out->best, rot, arm ? joints : nullptr};
     return gm::launch_rollout(ctx, sc, ag, pr, o, nullptr, t, static_cast<hipStream_t>(stream));
 }
+
+}  // namespace
 
 gmapp_status gmapp_plan_loop(gmapp_ctx *ctx, const gmapp_scene *scene, const gmapp_agents *agents,
                              const gmapp_query *query, const gmapp_params *params, const gmapp_loop_config *cfg,

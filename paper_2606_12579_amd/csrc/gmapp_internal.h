@@ -44,6 +44,10 @@ struct Prm {
     float q0[4] = {1.f, 0.f, 0.f, 0.f};   // 6-D pose agents: start rotor (w, x, y, z)
     float om0[3] = {0.f, 0.f, 0.f};       // start angular velocity (body frame)
     float qg[4] = {1.f, 0.f, 0.f, 0.f};   // goal rotor
+    const float *arm_links = nullptr;   // arm agents: device [arm_n + 1][7] link transforms
+    const float *arm_q0 = nullptr;      // device [arm_n] start joint angles
+    int arm_n = 0;
+    float arm_lam2 = 0.f;               // damping lambda^2 of the pseudo-inverse
     const float *start = nullptr;   // device [6] p0, v0 in place of p0, v0 (closed loop) or nullptr
     const int *inc_dev = nullptr;   // device incumbent in place of `incumbent` (closed loop) or nullptr
 };
@@ -52,6 +56,7 @@ struct Out {
     float *traj, *cost, *min_clear;
     int *best;
     float *rot = nullptr;     // 6-D pose agents: [N_a][N_k + 1][4] rotors, or nullptr
+    float *joints = nullptr;  // arm agents: [N_a][N_k + 1][n_joints] joint angles, or nullptr
 };
 
 // teacher-forced single-step mode (force probe)
@@ -200,6 +205,8 @@ gmapp_status launch_rollout(gmapp_ctx *ctx, const Scn &sc, const Agt &ag, const 
                             const Probe *probe, const Tiling &t, hipStream_t stream);
 Tiling choose_tiling(const gmapp_ctx *ctx, long long n_points, int n_agents, int n_steps, int n_seg, int cutoff);
 gmapp_status fit_coresident(gmapp_ctx *ctx, Tiling &t, const Scn &sc, const Agt &ag, const Prm &pr);
+
+constexpr int kMaxArmJoints = 7;                      // serial chains of arm agents
 
 // closed planning loop and the control query (control.hip)
 constexpr int kMaxControlSegments = 128;

@@ -12,10 +12,17 @@ using namespace dev;
 
 namespace {
 
-KFn pick_kernel(int AW, int W, bool wg, int cut, bool probe, bool het, bool pose)
+// agent kind of a launch: 0 point masses, 1 pose agents, 2 arm agents
+int kind_of(const Agt &ag, const Prm &pr)
 {
-    if (pose) return probe ? nullptr : pick_kernel_pose(AW, W, wg, cut);
-    return het ? pick_kernel_het(AW, W, wg, cut, probe) : pick_kernel_t<false, false>(AW, W, wg, cut, probe);
+    return ag.k_r == nullptr ? 0 : (pr.arm_links != nullptr ? 2 : 1);
+}
+
+KFn pick_kernel(int AW, int W, bool wg, int cut, bool probe, bool het, int kind)
+{
+    if (kind == 2) return probe ? nullptr : pick_kernel_arm(AW, W, wg, cut);
+    if (kind == 1) return probe ? nullptr : pick_kernel_pose(AW, W, wg, cut);
+    return het ? pick_kernel_het(AW, W, wg, cut, probe) : pick_kernel_t<false, 0>(AW, W, wg, cut, probe);
 }
 
 }  // namespace
@@ -54,7 +61,7 @@ size_t rollout_lds_bytes(const Tiling &t, long long n_points, int n_seg)
 
 gmapp_status check_tiling(gmapp_ctx *ctx, const Tiling &t, long long n_points, int n_seg, int cutoff)
 {
-    if (!pick_kernel(t.A, t.W, t.wg != 0, cutoff, false, false, false))
+    if (!pick_kernel(t.A, t.W, t.wg != 0, cutoff, false, false, 0))
         return fail(ctx, GMAPP_EINVAL, "unsupported tiling: %d agents per %s with %d waves", t.A,
                     t.wg ? "workgroup" : "wave", t.W);
     if (t.S < 1 || t.S > kMaxShards) return fail(ctx, GMAPP_EINVAL, "shards must be in [1, %d]", kMaxShards);
@@ -110,7 +117,7 @@ Tiling choose_tiling(const gmapp_ctx *ctx, long long n_points, int n_agents, int
 gmapp_status fit_coresident(gmapp_ctx *ctx, Tiling &t, const Scn &sc, const Agt &ag, const Prm &pr)
 {
     if (ag.n == 0) return GMAPP_OK;
-    KFn fn = pick_kernel(t.A, t.W, t.wg != 0, pr.cutoff, false, ag.heur != nullptr, ag.k_r != nullptr);
+    KFn fn = pick_kernel(t.A, t.W, t.wg != 0, pr.cutoff, false, ag.heur != nullptr, kind_of(ag, pr));
     if (!fn) return GMAPP_OK;
     const int per_wg = t.wg ? t.A : t.A * t.W;
     const long long G = (ag.n + per_wg - 1) / per_wg;
@@ -139,7 +146,7 @@ gmapp_status launch_rollout(gmapp_ctx *ctx, const Scn &sc, const Agt &ag, const 
         GM_HIP(ctx, hipGetLastError());
         return GMAPP_OK;
     }
-    KFn fn = pick_kernel(t.A, t.W, t.wg != 0, pr.cutoff, is_probe, ag.heur != nullptr, ag.k_r != nullptr);
+    KFn fn = pick_kernel(t.A, t.W, t.wg != 0, pr.cutoff, is_probe, ag.heur != nullptr, kind_of(ag, pr));
     if (!fn) return fail(ctx, GMAPP_EINVAL, "6-D pose agents have no teacher-forced form");
     const int per_wg = t.wg ? t.A : t.A * t.W;
     const int gpw = t.wg ? 1 : t.W;

@@ -7,7 +7,7 @@ namespace gm {
 
 KFn pick_kernel_het(int AW, int W, bool wg, int cut, bool probe)
 {
-    return pick_kernel_t<true, false>(AW, W, wg, cut, probe);
+    return pick_kernel_t<true, 0>(AW, W, wg, cut, probe);
 }
 
 }  // namespace gm

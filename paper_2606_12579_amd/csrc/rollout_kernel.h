@@ -46,6 +46,7 @@
 #include "gmapp_internal.h"
 #include "pairs.h"
 #include "pose.h"
+#include "arm.h"
 
 #include <algorithm>
 #include <cmath>
@@ -93,9 +94,11 @@ __host__ __device__ inline LdsPlan lds_plan(const Lay &l, int W, int WS, int AW,
 // groups.  PROBE: one teacher-forced step at the given states (no integration, no costs).
 // HET: each agent takes its field from ag.heur (rotation-vector circular field,
 // velocity-current field or APF); without it every agent runs the rotation-vector field.
-// POSE: 6-D pose agents (rotor and translation, body twist; Eqs. 6-11 on
-// Spin(3) x| R^3); the pairwise pass sees their position and world velocity.
-template <int AW, int W, int WS, int CUT, bool PROBE, bool HET, bool POSE>
+// KIND 1: 6-D pose agents (rotor and translation, body twist; Eqs. 6-11 on
+// Spin(3) x| R^3); KIND 2: arm agents (the same wrench and twist, the pose moved
+// through the joints, Eqs. 12-14).  The pairwise pass sees their end-effector
+// position and world velocity.
+template <int AW, int W, int WS, int CUT, bool PROBE, bool HET, int KIND>
 __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out out, Probe pb, Xch xc, Lay lay)
 {
     constexpr int NT = 64 * W;
@@ -112,6 +115,8 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
     float4 *rvel = reinterpret_cast<float4 *>(lds + lp.rvel);  // [runs_cap]
     __shared__ int s_last, s_nruns, s_split;
 
+    constexpr bool POSE = KIND >= 1;
+    constexpr bool ARM = KIND == 2;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
@@ -208,8 +213,27 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
     pose::Q qr{1.f, 0.f, 0.f, 0.f};
     float ox = 0, oy = 0, oz = 0, ux = 0, uy = 0, uz = 0, cux = 0, cuy = 0, cuz = 0;
     float D1x = 0, D1y = 0, D1z = 0, D2x = 0, D2y = 0, D2z = 0, D3x = 0, D3y = 0, D3z = 0;
+    // arm agents: joint half-angle rotors, the FP64 end-effector position and the start position
+    double jc[arm::kMaxJoints], js[arm::kMaxJoints];
+    double pdx = 0, pdy = 0, pdz = 0;
+    float a0x = 0, a0y = 0, a0z = 0;
+    if constexpr (ARM && !PROBE) {
+#pragma unroll
+        for (int i = 0; i < arm::kMaxJoints; ++i) {
+            jc[i] = 1.0; js[i] = 0.0;
+            if (i < pr.arm_n) sincos(0.5 * (double)pr.arm_q0[i], &js[i], &jc[i]);
+        }
+        arm::QD r;
+        arm::fk_d(pr.arm_links, pr.arm_n, jc, js, r, pdx, pdy, pdz);
+        qr = pose::Q{(float)r.w, (float)r.x, (float)r.y, (float)r.z};
+        px = (float)pdx; py = (float)pdy; pz = (float)pdz;
+        a0x = px; a0y = py; a0z = pz;
+    } else {
+#pragma unroll
+        for (int i = 0; i < arm::kMaxJoints; ++i) { jc[i] = 1.0; js[i] = 0.0; }
+    }
     if constexpr (POSE && !PROBE) {
-        qr = pose::qnormalize(pose::Q{pr.q0[0], pr.q0[1], pr.q0[2], pr.q0[3]});
+        if constexpr (!ARM) qr = pose::qnormalize(pose::Q{pr.q0[0], pr.q0[1], pr.q0[2], pr.q0[3]});
         ox = pr.om0[0]; oy = pr.om0[1]; oz = pr.om0[2];
         pose::qrot(qr, -1.0f, vx, vy, vz, ux, uy, uz);              // body linear velocity
     }
@@ -229,6 +253,12 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
         if (writer && out.rot) {
             float *ro = out.rot + (size_t)agent * (pr.n_steps + 1) * 4;
             ro[0] = qr.w; ro[1] = qr.x; ro[2] = qr.y; ro[3] = qr.z;
+        }
+    }
+    if constexpr (ARM) {
+        if (writer && out.joints) {
+            float *jo = out.joints + (size_t)agent * (pr.n_steps + 1) * pr.arm_n;
+            for (int i = 0; i < pr.arm_n && i < arm::kMaxJoints; ++i) jo[i] = pr.arm_q0[i];
         }
     }
     const unsigned long long t_start = __builtin_amdgcn_s_memrealtime();
@@ -325,9 +355,11 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
             ox = fmaf(hr, fmaf(P.kr, phx, -P.dr * ox), ox);
             oy = fmaf(hr, fmaf(P.kr, phy, -P.dr * oy), oy);
             oz = fmaf(hr, fmaf(P.kr, phz, -P.dr * oz), oz);
-            const float ax = pr.dt * ox, ay = pr.dt * oy, az = pr.dt * oz;
-            dq = pose::so3_exp(ax, ay, az);
-            pose::jac_coeffs(ax, ay, az, 1.0f, jA, jB);
+            if constexpr (!ARM) {
+                const float ax = pr.dt * ox, ay = pr.dt * oy, az = pr.dt * oz;
+                dq = pose::so3_exp(ax, ay, az);
+                pose::jac_coeffs(ax, ay, az, 1.0f, jA, jB);
+            }
         };
 
         // running costs that do not depend on this step's force (Eqs. 17, 19, 20): p^(k), v^(k-1), F^(k-1), F^(k-2)
@@ -451,15 +483,34 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
                 kahan_add(ux, cux, h * (aLx + fx));
                 kahan_add(uy, cuy, h * (aLy + fy));
                 kahan_add(uz, cuz, h * (aLz + fz));
-                // pose (Eq. 11): M <- M exp(dt v); the translation moves by R J(dt omega) dt u
-                const float ax = pr.dt * ox, ay = pr.dt * oy, az = pr.dt * oz;
-                float jx, jy, jz, dx, dy, dz;
-                pose::jac_mul(ax, ay, az, jA, jB, pr.dt * ux, pr.dt * uy, pr.dt * uz, jx, jy, jz);
-                pose::qrot(qr, 1.0f, jx, jy, jz, dx, dy, dz);
-                kahan_add(px, cpx, dx);
-                kahan_add(py, cpy, dy);
-                kahan_add(pz, cpz, dz);
-                qr = pose::qnormalize(pose::qmul(qr, dq));
+                float dx, dy, dz;
+                if constexpr (ARM) {
+                    // joints (Eqs. 12, 13): qdot = J^+ v, q += dt qdot; pose (Eq. 14): M = FK(q)
+                    float wa[3], wl[3], qd[arm::kMaxJoints];
+                    pose::qrot(qr, 1.0f, ox, oy, oz, wa[0], wa[1], wa[2]);
+                    pose::qrot(qr, 1.0f, ux, uy, uz, wl[0], wl[1], wl[2]);
+                    arm::joint_rates(pr.arm_links, pr.arm_n, jc, js, px, py, pz, wa, wl, pr.arm_lam2, qd);
+#pragma unroll
+                    for (int i = 0; i < arm::kMaxJoints; ++i)
+                        if (i < pr.arm_n) arm::advance(jc[i], js[i], 0.5 * (double)pr.dt * (double)qd[i]);
+                    arm::QD r;
+                    double tx, ty, tz;
+                    arm::fk_d(pr.arm_links, pr.arm_n, jc, js, r, tx, ty, tz);
+                    dx = (float)(tx - pdx); dy = (float)(ty - pdy); dz = (float)(tz - pdz);
+                    pdx = tx; pdy = ty; pdz = tz;
+                    px = (float)tx; py = (float)ty; pz = (float)tz;
+                    qr = pose::Q{(float)r.w, (float)r.x, (float)r.y, (float)r.z};
+                } else {
+                    // pose (Eq. 11): M <- M exp(dt v); the translation moves by R J(dt omega) dt u
+                    const float ax = pr.dt * ox, ay = pr.dt * oy, az = pr.dt * oz;
+                    float jx, jy, jz;
+                    pose::jac_mul(ax, ay, az, jA, jB, pr.dt * ux, pr.dt * uy, pr.dt * uz, jx, jy, jz);
+                    pose::qrot(qr, 1.0f, jx, jy, jz, dx, dy, dz);
+                    kahan_add(px, cpx, dx);
+                    kahan_add(py, cpy, dy);
+                    kahan_add(pz, cpz, dz);
+                    qr = pose::qnormalize(pose::qmul(qr, dq));
+                }
                 D3x = D2x; D3y = D2y; D3z = D2z;
                 D2x = D1x; D2y = D1y; D2z = D1z;
                 D1x = dx; D1y = dy; D1z = dz;
@@ -472,6 +523,13 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
                     if (out.rot) {
                         float *ro = out.rot + ((size_t)agent * (pr.n_steps + 1) + k) * 4;
                         ro[0] = qr.w; ro[1] = qr.x; ro[2] = qr.y; ro[3] = qr.z;
+                    }
+                    if constexpr (ARM) {
+                        if (out.joints) {
+                            float *jo = out.joints + ((size_t)agent * (pr.n_steps + 1) + k) * pr.arm_n;
+                            for (int i = 0; i < pr.arm_n && i < arm::kMaxJoints; ++i)
+                                jo[i] = (float)(2.0 * atan2(js[i], jc[i]));
+                        }
                     }
                     if (out.min_clear) out.min_clear[(size_t)agent * pr.n_steps + (k - 1)] = rho_min;
                 }
@@ -541,7 +599,8 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
         const float N = (float)pr.n_steps;
         const float Cg = sg / N, Co = so / N;
         const float *p0 = pr.start ? pr.start : pr.p0;
-        const float e1x = gx - p0[0], e1y = gy - p0[1], e1z = gz - p0[2];
+        const float s0x = ARM ? a0x : p0[0], s0y = ARM ? a0y : p0[1], s0z = ARM ? a0z : p0[2];
+        const float e1x = gx - s0x, e1y = gy - s0y, e1z = gz - s0z;
         const float d1 = sqrtf(fmaf(e1z, e1z, fmaf(e1y, e1y, e1x * e1x)));
         float Cp;
         if (sp >= d1) Cp = (sp > 0.0f) ? 1.0f - d1 / sp : 0.0f;
@@ -615,55 +674,55 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
 // ---------------------------------------------------------------- kernel tables
 using KFn = void (*)(Scn, Agt, Prm, Out, Probe, Xch, Lay);
 
-template <int AW, int W, int WS, bool HET, bool POSE>
+template <int AW, int W, int WS, bool HET, int KIND>
 KFn pick_cut(int cut, bool probe)
 {
-    if constexpr (POSE) {           // pose agents have no teacher-forced form (the probe takes p, v)
+    if constexpr (KIND != 0) {      // pose and arm agents have no teacher-forced form (the probe takes p, v)
         if (probe) return nullptr;
-        return cut ? k_rollout<AW, W, WS, 1, false, HET, true> : k_rollout<AW, W, WS, 0, false, HET, true>;
+        return cut ? k_rollout<AW, W, WS, 1, false, HET, KIND> : k_rollout<AW, W, WS, 0, false, HET, KIND>;
     } else {
-        if (probe) return cut ? k_rollout<AW, W, WS, 1, true, HET, false> : k_rollout<AW, W, WS, 0, true, HET, false>;
-        return cut ? k_rollout<AW, W, WS, 1, false, HET, false> : k_rollout<AW, W, WS, 0, false, HET, false>;
+        if (probe) return cut ? k_rollout<AW, W, WS, 1, true, HET, 0> : k_rollout<AW, W, WS, 0, true, HET, 0>;
+        return cut ? k_rollout<AW, W, WS, 1, false, HET, 0> : k_rollout<AW, W, WS, 0, false, HET, 0>;
     }
 }
 
 // per-wave groups: every (AW, W); workgroup-wide groups: AW <= 8 with 4, 8 or 16 waves
-template <int W, bool HET, bool POSE>
+template <int W, bool HET, int KIND>
 KFn pick_a(int AW, bool wg, int cut, bool probe)
 {
     if (wg) {
         if constexpr (W >= 4) {
             switch (AW) {
-            case 1: return pick_cut<1, W, W, HET, POSE>(cut, probe);
-            case 2: return pick_cut<2, W, W, HET, POSE>(cut, probe);
-            case 4: return pick_cut<4, W, W, HET, POSE>(cut, probe);
-            case 8: return pick_cut<8, W, W, HET, POSE>(cut, probe);
+            case 1: return pick_cut<1, W, W, HET, KIND>(cut, probe);
+            case 2: return pick_cut<2, W, W, HET, KIND>(cut, probe);
+            case 4: return pick_cut<4, W, W, HET, KIND>(cut, probe);
+            case 8: return pick_cut<8, W, W, HET, KIND>(cut, probe);
             default: return nullptr;
             }
         }
         return nullptr;
     }
     switch (AW) {
-    case 1: return pick_cut<1, W, 1, HET, POSE>(cut, probe);
-    case 2: return pick_cut<2, W, 1, HET, POSE>(cut, probe);
-    case 4: return pick_cut<4, W, 1, HET, POSE>(cut, probe);
-    case 8: return pick_cut<8, W, 1, HET, POSE>(cut, probe);
-    case 16: return pick_cut<16, W, 1, HET, POSE>(cut, probe);
-    case 32: return pick_cut<32, W, 1, HET, POSE>(cut, probe);
-    case 64: return pick_cut<64, W, 1, HET, POSE>(cut, probe);
+    case 1: return pick_cut<1, W, 1, HET, KIND>(cut, probe);
+    case 2: return pick_cut<2, W, 1, HET, KIND>(cut, probe);
+    case 4: return pick_cut<4, W, 1, HET, KIND>(cut, probe);
+    case 8: return pick_cut<8, W, 1, HET, KIND>(cut, probe);
+    case 16: return pick_cut<16, W, 1, HET, KIND>(cut, probe);
+    case 32: return pick_cut<32, W, 1, HET, KIND>(cut, probe);
+    case 64: return pick_cut<64, W, 1, HET, KIND>(cut, probe);
     default: return nullptr;
     }
 }
 
-template <bool HET, bool POSE>
+template <bool HET, int KIND>
 KFn pick_kernel_t(int AW, int W, bool wg, int cut, bool probe)
 {
     switch (W) {
-    case 1: return pick_a<1, HET, POSE>(AW, wg, cut, probe);
-    case 2: return pick_a<2, HET, POSE>(AW, wg, cut, probe);
-    case 4: return pick_a<4, HET, POSE>(AW, wg, cut, probe);
-    case 8: return pick_a<8, HET, POSE>(AW, wg, cut, probe);
-    case 16: return pick_a<16, HET, POSE>(AW, wg, cut, probe);
+    case 1: return pick_a<1, HET, KIND>(AW, wg, cut, probe);
+    case 2: return pick_a<2, HET, KIND>(AW, wg, cut, probe);
+    case 4: return pick_a<4, HET, KIND>(AW, wg, cut, probe);
+    case 8: return pick_a<8, HET, KIND>(AW, wg, cut, probe);
+    case 16: return pick_a<16, HET, KIND>(AW, wg, cut, probe);
     default: return nullptr;
     }
 }
@@ -673,5 +732,7 @@ KFn pick_kernel_t(int AW, int W, bool wg, int cut, bool probe)
 KFn pick_kernel_het(int AW, int W, bool wg, int cut, bool probe);
 // 6-D pose agents (any heuristic), forward rollouts only; in rollout_pose.hip.
 KFn pick_kernel_pose(int AW, int W, bool wg, int cut);
+// arm agents (any heuristic), forward rollouts only; in rollout_arm.hip.
+KFn pick_kernel_arm(int AW, int W, bool wg, int cut);
 
 }  // namespace gm

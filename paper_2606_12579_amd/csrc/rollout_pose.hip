@@ -6,7 +6,7 @@ namespace gm {
 
 KFn pick_kernel_pose(int AW, int W, bool wg, int cut)
 {
-    return pick_kernel_t<true, true>(AW, W, wg, cut, false);
+    return pick_kernel_t<true, 1>(AW, W, wg, cut, false);
 }
 
 }  // namespace gm

@@ -55,6 +55,11 @@ class PoseQuery(ctypes.Structure):
     _fields_ = [("q0", ctypes.c_float * 4), ("w0", ctypes.c_float * 3), ("qg", ctypes.c_float * 4)]
 
 
+class Arm(ctypes.Structure):
+    _fields_ = [("n_joints", ctypes.c_int32), ("links", ctypes.c_void_p), ("q0", ctypes.c_void_p),
+                ("damping", ctypes.c_float)]
+
+
 class LoopConfig(ctypes.Structure):
     _fields_ = [("n_cycles", ctypes.c_int32), ("ctrl_steps", ctypes.c_int32), ("ctrl_dt", ctypes.c_float)]
 
@@ -161,6 +166,8 @@ def load_library(path: str = LIB_PATH):
         "gmapp_set_tiling": (ctypes.c_int32, [vp, P(Tiling)]),
         "gmapp_rollout_pose": (ctypes.c_int32, [vp, P(Scene), P(Agents), P(PoseAgents), P(Query), P(PoseQuery),
                                                 P(Params), P(Outputs), vp, vp]),
+        "gmapp_rollout_arm": (ctypes.c_int32, [vp, P(Scene), P(Agents), P(PoseAgents), P(Arm), P(Query),
+                                               P(PoseQuery), P(Params), P(Outputs), vp, vp, vp]),
         "gmapp_plan_loop": (ctypes.c_int32, [vp, P(Scene), P(Agents), P(Query), P(Params), P(LoopConfig),
                                              P(LoopOutputs), vp]),
         "gmapp_control_force": (ctypes.c_int32, [vp, P(Scene), P(Agents), vp, vp, ctypes.c_float, P(Params), vp, vp,
@@ -636,6 +643,36 @@ class Context:
         st = self.lib.gmapp_rollout_pose(self.handle, ctypes.byref(sc), ctypes.byref(ag), ctypes.byref(pa),
                                          ctypes.byref(q), ctypes.byref(pq), ctypes.byref(p), ctypes.byref(o),
                                          _ptr(out.get("rot")), self._stream(stream))
+        self._raise(st)
+        return out
+
+    def rollout_arm(self, scene: DeviceScene, agents: DeviceAgents, pose_agents, links, q0, damping, query,
+                    pose_query, params, stream=None):
+        """gmapp_rollout_arm: arm agents driving the serial chain `links` (device float32 [n + 1, 7]) from the
+        joint angles q0 (device float32 [n]). Returns the outputs of rollout_pose plus joints [N_a, N_k + 1, n]."""
+        import torch
+        na, nk, dev = agents.n, int(params.n_steps), self.device
+        nj = int(q0.numel())
+        _check_tensor(links, "links", 7 * (nj + 1), torch.float32, dev)
+        _check_tensor(q0, "q0", nj, torch.float32, dev)
+        for nm in ("k_r", "d_r", "inv_inertia_r"):
+            _check_tensor(getattr(pose_agents, nm), f"pose_agents.{nm}", na, torch.float32, dev)
+        out = {"traj": torch.empty((na, nk + 1, 3), dtype=torch.float32, device=dev),
+               "cost": torch.empty((na, 5), dtype=torch.float32, device=dev),
+               "min_clear": torch.empty((na, nk), dtype=torch.float32, device=dev),
+               "best": torch.empty(1, dtype=torch.int32, device=dev),
+               "rot": torch.empty((na, nk + 1, 4), dtype=torch.float32, device=dev),
+               "joints": torch.empty((na, nk + 1, max(nj, 1)), dtype=torch.float32, device=dev)}
+        sc, ag = _scene_struct(scene, dev), _agents_struct(agents, dev)
+        pa = PoseAgents(_ptr(pose_agents.k_r), _ptr(pose_agents.d_r), _ptr(pose_agents.inv_inertia_r))
+        arm = Arm(nj, _ptr(links), _ptr(q0), float(damping))
+        f = lambda a, n: (ctypes.c_float * n)(*[float(x) for x in np.asarray(a, np.float32).reshape(-1)])
+        pq = PoseQuery(f(pose_query.q0, 4), f(pose_query.w0, 3), f(pose_query.qg, 4))
+        q, p = make_query(query), make_params(params)
+        o = Outputs(_ptr(out["traj"]), _ptr(out["cost"]), _ptr(out["min_clear"]), _ptr(out["best"]))
+        st = self.lib.gmapp_rollout_arm(self.handle, ctypes.byref(sc), ctypes.byref(ag), ctypes.byref(pa),
+                                        ctypes.byref(arm), ctypes.byref(q), ctypes.byref(pq), ctypes.byref(p),
+                                        ctypes.byref(o), _ptr(out["rot"]), _ptr(out["joints"]), self._stream(stream))
         self._raise(st)
         return out
 

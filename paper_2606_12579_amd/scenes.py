@@ -421,3 +421,45 @@ def robot_spheres(rng: np.random.Generator, n: int = 8, base=(-0.35, -0.05, 0.0)
                    elbow + (tip - elbow) * (2 * s[:, None] - 1))
     rad = rng.uniform(r[0], r[1], n) * np.linspace(1.0, 0.6, n)
     return np.concatenate([pts, rad[:, None]], 1).astype(F32)
+
+
+# ---------------------------------------------------------------- arm agents
+def arm_links(base=(0.0, 0.0, 0.0)) -> np.ndarray:
+    """Link transforms [8, 7] (rotor w, x, y, z; offset) of a synthetic 7-joint arm:
+    joint axes alternate by +-90 degree turns about x, with 0.33 / 0.316 / 0.384 /
+    0.107 m offsets (proportions of a common 7-DoF arm).  Row 0 places the base."""
+    h = np.sqrt(0.5)
+    rx_m = (h, -h, 0.0, 0.0)          # rotation by -90 degrees about x
+    rx_p = (h, h, 0.0, 0.0)           # rotation by +90 degrees about x
+    rows = [(1.0, 0.0, 0.0, 0.0, base[0], base[1], base[2] + 0.333),
+            (*rx_m, 0.0, 0.0, 0.0),
+            (*rx_p, 0.0, -0.316, 0.0),
+            (*rx_p, 0.0825, 0.0, 0.0),
+            (*rx_m, -0.0825, 0.384, 0.0),
+            (*rx_p, 0.0, 0.0, 0.0),
+            (*rx_p, 0.088, 0.0, 0.0),
+            (1.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.107)]
+    return np.array(rows, F32)
+
+
+ARM_Q0 = np.array([0.0, -0.3, 0.0, -2.2, 0.0, 2.0, 0.8], F32)
+
+
+def arm_problem(seed: int = 13, n_agents: int = 8, n_points: int = 600, n_steps: int = 80, moving: bool = False):
+    """Arm agents on a small scene: the synthetic arm at ARM_Q0 (its hand starts near
+    (0.47, 0, 0.52)), a goal 0.3 m away, and spheres in an 8 cm box beside the way.
+    Returns (Problem, PoseAgents, PoseQuery, links [8, 7], q0 [7])."""
+    rng = np.random.default_rng(seed)
+    goal = np.array([0.55, 0.25, 0.35], F32)
+    P = rng.uniform([0.47, 0.08, 0.42], [0.55, 0.16, 0.50], (n_points, 3)).astype(F32)
+    seg_begin = seg_vel = None
+    if moving and n_points > 0:
+        cut = np.sort(rng.integers(0, n_points + 1, 2))
+        seg_begin = np.array([0, cut[0], cut[1], n_points], np.int32)
+        seg_vel = (0.2 * unit_vectors(rng, 3)).astype(F32)
+    scene = Scene(P[:, 0].copy(), P[:, 1].copy(), P[:, 2].copy(), R_OBS, seg_begin, seg_vel)
+    agents = default_agents(rng, n_agents)
+    pb = Problem(scene, agents, _query((0.0, 0.0, 0.0), tuple(goal)), Params(n_steps=n_steps), name=f"arm{seed}")
+    pa = pose_agents(rng, n_agents)
+    pq = PoseQuery(np.array([1, 0, 0, 0], F32), np.zeros(3, F32), unit_rotors(rng, 1)[0])
+    return pb, pa, pq, arm_links(), ARM_Q0.copy()

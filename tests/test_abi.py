@@ -55,11 +55,11 @@ def test_struct_layouts_match_header():
 #include <stdio.h>
 #include "gmapp.h"
 #include <stddef.h>
-int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %d\n", sizeof(gmapp_scene),
+int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %d\n", sizeof(gmapp_scene),
  sizeof(gmapp_agents), sizeof(gmapp_query), sizeof(gmapp_params), sizeof(gmapp_outputs), sizeof(gmapp_tiling),
  sizeof(gmapp_job), sizeof(gmapp_batch_tuning), sizeof(gmapp_server_config), sizeof(gmapp_request),
  sizeof(gmapp_completion), sizeof(gmapp_server_stats), sizeof(gmapp_loop_config), sizeof(gmapp_loop_outputs),
- sizeof(gmapp_pose_agents), sizeof(gmapp_pose_query),
+ sizeof(gmapp_pose_agents), sizeof(gmapp_pose_query), sizeof(gmapp_arm),
  offsetof(gmapp_job, state), offsetof(gmapp_job, k_end),
  offsetof(gmapp_request, deadline_s), offsetof(gmapp_agents, heuristic), GMAPP_STATE_FLOATS);
  return 0;}
@@ -74,7 +74,7 @@ int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %
     mine = [ctypes.sizeof(s) for s in (gmapp.Scene, gmapp.Agents, gmapp.Query, gmapp.Params, gmapp.Outputs,
                                        gmapp.Tiling, gmapp.Job, gmapp.BatchTuning, gmapp.ServerConfig,
                                        gmapp.Request, gmapp.Completion, gmapp.ServerStats, gmapp.LoopConfig,
-                                       gmapp.LoopOutputs, gmapp.PoseAgents, gmapp.PoseQuery)]
+                                       gmapp.LoopOutputs, gmapp.PoseAgents, gmapp.PoseQuery, gmapp.Arm)]
     mine += [gmapp.Job.state.offset, gmapp.Job.k_end.offset, gmapp.Request.deadline_s.offset,
              gmapp.Agents.heuristic.offset, gmapp.STATE_FLOATS]
     assert sizes == mine

@@ -699,3 +699,75 @@ def test_pose_frame_covariance():
     for i in range(pb.agents.n):
         r = qw(rq(a.rot[i, -1]))
         assert min(np.abs(b.rot[i, -1] - r).max(), np.abs(b.rot[i, -1] + r).max()) < 2e-6
+
+
+# ---------------------------------------------------------------- arm agents (Eqs. 12-14)
+
+def test_arm_forward_kinematics_composition():
+    """M(q) against the chain composed with scipy rotations: R = R_0 Rz(q_1) R_1 ...,
+    p = sum of each link offset rotated by the rotation accumulated before it."""
+    from scipy.spatial.transform import Rotation
+    from oracle import arm as oa
+    L = scenes.arm_links(base=(0.1, -0.2, 0.05)).astype(np.float64)
+    rng = np.random.default_rng(41)
+    rq = lambda r: Rotation.from_quat([r[1], r[2], r[3], r[0]])
+    for _ in range(10):
+        q = rng.uniform(-2.5, 2.5, 7)
+        R = rq(L[0])
+        p = L[0, 4:7].copy()
+        for i in range(7):
+            R = R * Rotation.from_rotvec([0.0, 0.0, q[i]])
+            p = p + R.apply(L[i + 1, 4:7])
+            R = R * rq(L[i + 1])
+        T = oa.fk(L.astype(np.float32), q)
+        np.testing.assert_allclose(T[:3, 3], p, rtol=0, atol=1e-12)
+        np.testing.assert_allclose(T[:3, :3], R.as_matrix(), rtol=0, atol=1e-12)
+
+
+def test_arm_jacobian_and_pseudo_inverse():
+    """The world Jacobian against central differences of M(q) (position, and the
+    rotation vector of R(q + h e_i) R(q)^T), and J J^+ = I for the undamped
+    pseudo-inverse J^T (J J^T)^-1."""
+    from scipy.spatial.transform import Rotation
+    from oracle import arm as oa
+    L = scenes.arm_links()
+    rng = np.random.default_rng(42)
+    for _ in range(5):
+        q = scenes.ARM_Q0.astype(np.float64) + rng.uniform(-0.5, 0.5, 7)
+        J = oa.jacobian(L, q)
+        T = oa.fk(L, q)
+        h = 1e-6
+        for i in range(7):
+            e = np.zeros(7); e[i] = h
+            Tp, Tm = oa.fk(L, q + e), oa.fk(L, q - e)
+            np.testing.assert_allclose((Tp[:3, 3] - Tm[:3, 3]) / (2 * h), J[3:, i], rtol=0, atol=1e-7)
+            w = Rotation.from_matrix(Tp[:3, :3] @ Tm[:3, :3].T).as_rotvec() / (2 * h)
+            np.testing.assert_allclose(w, J[:3, i], rtol=0, atol=1e-7)
+        Jp = J.T @ np.linalg.inv(J @ J.T)
+        np.testing.assert_allclose(J @ Jp, np.eye(6), rtol=0, atol=1e-10)
+        assert T.shape == (4, 4)
+
+
+def test_arm_follows_the_pose_agent():
+    """Undamped, the joint step realises the commanded twist to first order in dt:
+    one step of the arm's hand matches the 6-D pose agent started at the same pose
+    to second order, and over a fixed horizon the gap is first order in dt (halving
+    dt halves it), i.e. both integrate the same motion."""
+    from oracle import arm as oa
+
+    def gap(n_steps, dt):
+        pb, pa, pq, L, q0 = scenes.arm_problem(n_steps=n_steps)
+        pb.params.dt = dt
+        ra = oa.rollout_arm(pb, pa, pq, L, q0, 0.0)
+        T = oa.fk(L, q0)
+        pp = copy.deepcopy(pb)
+        pp.query.p0 = T[:3, 3]
+        rp = oracle.rollout_pose(pp, pa, scenes.PoseQuery(oa._mat_quat(T[:3, :3]), pq.w0, pq.qg))
+        assert np.abs(ra["traj"][:, 1:] - ra["traj"][:, :1]).max() > 1e-3      # the hands do move
+        return np.abs(ra["traj"] - rp.traj).max(axis=(0, 2))
+
+    g1 = gap(40, 1e-3)
+    assert g1[1] < 1e-7
+    g2 = gap(80, 5e-4)
+    ratio = g1[-1] / g2[-1]
+    assert 1.6 < ratio < 2.5, ratio

@@ -228,6 +228,37 @@ def pose_pass(ctx, dev, base_ms, reps=10):
             "best": int(out["best"].item())}
 
 
+def arm_pass(ctx, dev, base_ms, reps=5):
+    """The headline scene and horizon (N_O=50,000 moving points, N_k=500) with 64 arm
+    agents on the synthetic 7-joint chain (damped pseudo-inverse, lambda = 0.01).
+    HIP events around each launch."""
+    import numpy as np
+    import torch
+    from paper_2606_12579_amd import gmapp, scenes
+    pb = scenes.config2()
+    _, pa, pq, L, q0 = scenes.arm_problem(n_agents=pb.agents.n)
+    pb.query.goal = np.array([0.55, 0.25, 0.35], np.float32)
+    sc, ag = gmapp.scene_to_device(pb.scene, dev), gmapp.agents_to_device(pb.agents, dev)
+    dpa = gmapp.pose_agents_to_device(pa, dev)
+    Ld, qd = torch.as_tensor(L, device=dev), torch.as_tensor(q0, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    out = ctx.rollout_arm(sc, ag, dpa, Ld, qd, 0.01, pb.query, pq, pb.params, stream=stream)
+    torch.cuda.synchronize()
+    ms = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        ctx.rollout_arm(sc, ag, dpa, Ld, qd, 0.01, pb.query, pq, pb.params, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    m = float(np.mean(ms))
+    inter = float(pb.agents.n) * pb.params.n_steps * pb.scene.n
+    return {"workload": "config-2 scene, N_a=64 arm agents (7 joints, damped pseudo-inverse), N_k=500",
+            "kernel_ms_mean": m, "interactions_per_s": inter / (m * 1e-3), "over_point_mass": m / base_ms,
+            "best": int(out["best"].item())}
+
+
 def closed_loop(ctx, dev, n_cycles=50, ctrl_steps=10, ctrl_dt=0.01, reps=3):
     """The planner loop (Sec. V-B) on the config-2 scene: 64 agents, N_k = 100 (one
     of the paper's horizons), 50 cycles of one rollout plus 10 control steps at
@@ -353,6 +384,7 @@ def main():
     ap.add_argument("--no-heterogeneous", action="store_true", help="skip the mixed-heuristic ensemble timing")
     ap.add_argument("--no-loop", action="store_true", help="skip the closed planning loop timing")
     ap.add_argument("--no-pose", action="store_true", help="skip the 6-D pose-agent timing")
+    ap.add_argument("--no-arm", action="store_true", help="skip the arm-agent timing")
     ap.add_argument("--quantum", type=int, default=50, help="steps per request per server cycle")
     ap.add_argument("--batch-requests", type=int, default=512, help="requests of the batched / served mix")
     args = ap.parse_args()
@@ -451,6 +483,8 @@ def main():
         res["heterogeneous"] = heterogeneous_pass(ctx, dev, avg_kernel_s * 1e3)
     if not args.no_pose:
         res["pose"] = pose_pass(ctx, dev, avg_kernel_s * 1e3)
+    if not args.no_arm:
+        res["arm"] = arm_pass(ctx, dev, avg_kernel_s * 1e3)
     if not args.no_loop:
         res["closed_loop"] = closed_loop(ctx, dev)
     if not args.no_perception:

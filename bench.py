@@ -66,9 +66,16 @@ def cpu_baseline(pb):
     oracle.rollout(pb)
     dt = time.perf_counter() - t0
     n = oracle.interactions(pb)
+    cpu = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu = next(l.split(":", 1)[1].strip() for l in f if l.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
     return {"value": n / dt, "unit": "interactions/s", "cores": oracle.n_threads(), "kind": "oracle",
             "sample": f"FP64 oracle, the full workload: {pb.agents.n} agents x {pb.params.n_steps} steps x "
-                      f"{pb.scene.n} points ({n:.3g} interactions) in {dt:.2f} s"}
+                      f"{pb.scene.n} points ({n:.3g} interactions) in {dt:.2f} s on {oracle.n_threads()} "
+                      f"threads of {os.cpu_count()} logical CPUs ({cpu})"}
 
 
 def perception_pass(ctx, dev, reps=20):
@@ -106,37 +113,42 @@ def perception_pass(ctx, dev, reps=20):
            "depth_to_points_GBps": bp_bytes / (t_bp / reps * 1e-3) / 1e9,
            "voxel_downsample_GBps": vx_bytes / (t_vx / reps * 1e-3) / 1e9,
            "bytes_note": "algorithmic: depth 4 B + points 12 B per pixel; points 12 B per point + centres 12 B"}
-    # multi-view: B frames from B poses in one launch, then one fused voxel pass (the HBM-bound regime)
-    B = 64
-    T = torch.as_tensor(scenes.config3_poses(B), device=dev)
-    db = d.unsqueeze(0).repeat(B, 1, 1).contiguous()
-    nb = db.numel()
-    ptsb = tuple(torch.empty(nb, dtype=torch.float32, device=dev) for _ in range(3))
-    capb = 1 << 18
-    voxb = tuple(torch.empty(capb, dtype=torch.float32, device=dev) for _ in range(3)) + \
-        (torch.zeros(1, dtype=torch.int64, device=dev),)
-    for _ in range(2):
-        ctx.depth_to_points_batch(db, fr.K, T, out=ptsb)
-        ctx.voxel_downsample(*ptsb, fr.voxel, fr.box_lo, fr.dims, capacity=capb, out=voxb)
-    torch.cuda.synchronize()
-    t_bp, t_vx = [], []
-    for _ in range(5):
-        e[0].record()
-        ctx.depth_to_points_batch(db, fr.K, T, out=ptsb)
-        e[1].record()
-        ctx.voxel_downsample(*ptsb, fr.voxel, fr.box_lo, fr.dims, capacity=capb, out=voxb)
-        e[2].record()
+    # multi-view: B frames from B poses in one launch, then one fused voxel pass; the sweep
+    # over B shows the launch-bound regime give way to the HBM-bound one
+    def multiview(B):
+        T = torch.as_tensor(scenes.config3_poses(B), device=dev)
+        db = d.unsqueeze(0).repeat(B, 1, 1).contiguous()
+        nb = db.numel()
+        ptsb = tuple(torch.empty(nb, dtype=torch.float32, device=dev) for _ in range(3))
+        capb = 1 << 18
+        voxb = tuple(torch.empty(capb, dtype=torch.float32, device=dev) for _ in range(3)) + \
+            (torch.zeros(1, dtype=torch.int64, device=dev),)
+        for _ in range(2):
+            ctx.depth_to_points_batch(db, fr.K, T, out=ptsb)
+            ctx.voxel_downsample(*ptsb, fr.voxel, fr.box_lo, fr.dims, capacity=capb, out=voxb)
         torch.cuda.synchronize()
-        t_bp.append(e[0].elapsed_time(e[1]))
-        t_vx.append(e[1].elapsed_time(e[2]))
-    nvb = int(voxb[3].item())
-    assert nvb <= capb
-    tb, tv = min(t_bp), min(t_vx)
-    res["multiview"] = {"frames": B, "points": nb, "fused_voxels": nvb, "depth_to_points_ms": tb,
-                        "voxel_downsample_ms": tv,
-                        "depth_to_points_GBps": 16 * nb / (tb * 1e-3) / 1e9,
-                        "voxel_downsample_GBps": (12 * nb + 12 * nvb) / (tv * 1e-3) / 1e9,
-                        "hbm_peak_GBps": 8000.0}
+        t_bp, t_vx = [], []
+        for _ in range(5):
+            e[0].record()
+            ctx.depth_to_points_batch(db, fr.K, T, out=ptsb)
+            e[1].record()
+            ctx.voxel_downsample(*ptsb, fr.voxel, fr.box_lo, fr.dims, capacity=capb, out=voxb)
+            e[2].record()
+            torch.cuda.synchronize()
+            t_bp.append(e[0].elapsed_time(e[1]))
+            t_vx.append(e[1].elapsed_time(e[2]))
+        nvb = int(voxb[3].item())
+        assert nvb <= capb
+        tb, tv = min(t_bp), min(t_vx)
+        del db, ptsb, voxb
+        return {"frames": B, "points": nb, "fused_voxels": nvb, "depth_to_points_ms": tb,
+                "voxel_downsample_ms": tv,
+                "depth_to_points_GBps": 16 * nb / (tb * 1e-3) / 1e9,
+                "voxel_downsample_GBps": (12 * nb + 12 * nvb) / (tv * 1e-3) / 1e9}
+    sweep = [multiview(B) for B in (1, 4, 16, 64, 256)]
+    res["multiview"] = dict(sweep[3], hbm_peak_GBps=8000.0)
+    res["multiview_sweep"] = [{k: m[k] for k in ("frames", "depth_to_points_GBps", "voxel_downsample_GBps")}
+                              for m in sweep]
     return res
 
 
@@ -375,7 +387,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--replans", type=int, default=2000, help="back-to-back replans for the latency percentiles")
+    ap.add_argument("--replans", type=int, default=10000, help="back-to-back replans for the latency percentiles")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU (oracle) baseline")
     ap.add_argument("--no-perception", action="store_true", help="skip the perception-pass timing")
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-request batched / served mix")

@@ -51,6 +51,28 @@ def _smooth_bound(pb, ref):
     return err / (N * dt ** 4 * float(np.float32(pb.params.a_max)) ** 2)
 
 
+def _check(pb, gpu, ref, sampled=False):
+    pos_err = float(np.abs(gpu["traj"].astype(np.float64) - ref["traj"]).max())
+    assert pos_err <= gu.POS_TOL, pos_err
+    r = gpu["rot"].astype(np.float64)
+    r = r * np.where(r[..., :1] < 0, -1.0, 1.0)
+    rot_err = float(np.abs(r - ref["rot"]).max())
+    assert rot_err <= ROT_TOL, rot_err
+    j_err = float(np.abs(gpu["joints"].astype(np.float64) - ref["joints"]).max())
+    assert j_err <= JOINT_TOL, j_err
+    fin = np.isfinite(ref["min_clear"])
+    assert np.abs(gpu["min_clear"][fin] - ref["min_clear"][fin]).max() <= pos_err + 1e-6
+    tol = gu.cost_tolerances(pb, pos_err)
+    d = np.abs(gpu["cost"].astype(np.float64) - ref["cost"])
+    for k in range(3):
+        assert (d[:, k] <= tol[k]).all(), (k, d[:, k].max(), tol[k])
+    sm = tol[3] * np.maximum(np.abs(ref["cost"][:, 3]), 1e-3) + _smooth_bound(pb, ref)
+    assert (d[:, 3] <= sm).all(), ("C_smooth", d[:, 3].max())
+    if not sampled:
+        gu.check_selection(gpu["best"], ref["cost"], gpu["cost"])
+    return pos_err, rot_err, j_err
+
+
 @pytest.mark.parametrize("case", ["static", "moving", "undamped"])
 def test_arm_rollout(ctx, case):
     pb, pa, pq, L, q0 = scenes.arm_problem(moving=case == "moving")
@@ -58,23 +80,7 @@ def test_arm_rollout(ctx, case):
     ref = oa.rollout_arm(pb, pa, pq, L, q0, damping)
     for tiling in (None, (1, 8, 4, 0, 0, 2), (2, 1, 2, 0, 1, 1), (8, 4, 1, 64, 2, 1)):
         gpu = _gpu(ctx, pb, pa, pq, L, q0, damping, tiling)
-        pos_err = float(np.abs(gpu["traj"].astype(np.float64) - ref["traj"]).max())
-        assert pos_err <= gu.POS_TOL, pos_err
-        r = gpu["rot"].astype(np.float64)
-        r = r * np.where(r[..., :1] < 0, -1.0, 1.0)
-        rot_err = float(np.abs(r - ref["rot"]).max())
-        assert rot_err <= ROT_TOL, rot_err
-        j_err = float(np.abs(gpu["joints"].astype(np.float64) - ref["joints"]).max())
-        assert j_err <= JOINT_TOL, j_err
-        fin = np.isfinite(ref["min_clear"])
-        assert np.abs(gpu["min_clear"][fin] - ref["min_clear"][fin]).max() <= pos_err + 1e-6
-        tol = gu.cost_tolerances(pb, pos_err)
-        d = np.abs(gpu["cost"].astype(np.float64) - ref["cost"])
-        for k in range(3):
-            assert (d[:, k] <= tol[k]).all(), (k, d[:, k].max(), tol[k])
-        sm = tol[3] * np.maximum(np.abs(ref["cost"][:, 3]), 1e-3) + _smooth_bound(pb, ref)
-        assert (d[:, 3] <= sm).all(), ("C_smooth", d[:, 3].max())
-        gu.check_selection(gpu["best"], ref["cost"], gpu["cost"])
+        pos_err, rot_err, j_err = _check(pb, gpu, ref)
         print(f"arm {case} tiling {tiling}: pos {pos_err:.2e} rotor {rot_err:.2e} joints {j_err:.2e} "
               f"best {gpu['best']}/{ref['best']}", flush=True)
 
@@ -94,3 +100,22 @@ def test_arm_validation(ctx):
     with pytest.raises(gmapp.GmappError) as ei:
         ctx.rollout_arm(sc, ag, dpa, L9, q8, 0.01, pb.query, pq, pb.params)
     assert ei.value.status == gmapp.EINVAL
+
+
+def test_arm_full_size_sampled(ctx):
+    """The benchmark's arm workload at full size (config-2 scene, 50,000 moving
+    points, 64 arm agents, 500 steps, the built-in tiling): four sampled agents
+    against the oracle run on those agents alone."""
+    import copy
+    pb = scenes.config2()
+    pb.query.goal = np.array([0.55, 0.25, 0.35], np.float32)
+    _, pa, pq, L, q0 = scenes.arm_problem(n_agents=pb.agents.n)
+    idx = [0, 21, 42, 63]
+    gpu = _gpu(ctx, pb, pa, pq, L, q0, 0.01)
+    sub = copy.deepcopy(pb)
+    sub.agents = pb.agents.subset(idx)
+    ref = oa.rollout_arm(sub, pa.subset(idx), pq, L, q0, 0.01)
+    g = {k: (v[idx] if isinstance(v, np.ndarray) and v.ndim and v.shape[0] == pb.agents.n else v)
+         for k, v in gpu.items()}
+    pos_err, rot_err, j_err = _check(sub, g, ref, sampled=True)
+    print(f"arm full size: sampled pos {pos_err:.2e} rotor {rot_err:.2e} joints {j_err:.2e}", flush=True)

@@ -157,3 +157,17 @@ def test_heuristics_rejected_outside_rollout(ctx):
     with pytest.raises(gmapp.GmappError) as ei:
         gmapp.rollout_cost(ctx, sc, ag, pb.query, pb.params)
     assert ei.value.status == gmapp.EINVAL
+
+
+def test_multi_full_size_sampled(ctx):
+    """The benchmark's mixed-ensemble workload at full size (config-2 scene, 50,000
+    moving points, 64 agents, 500 steps, the built-in tiling): eight sampled agents
+    against the oracle run on those agents alone (agents are independent)."""
+    pb = _multi(scenes.config2())
+    idx = [0, 9, 18, 27, 36, 45, 54, 63]
+    gpu = gu.gpu_rollout(ctx, pb)
+    sub = copy.deepcopy(pb)
+    sub.agents = pb.agents.subset(idx)
+    ref = oracle.rollout(sub)
+    err = gu.compare_rollout(pb, gpu, ref, agents=idx)
+    _log(f"mixed full size: sampled pos err {err:.2e}")

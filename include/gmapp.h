@@ -199,8 +199,10 @@ typedef struct {
 } gmapp_arm;
 
 /* Forward rollout of arm agents: outputs as gmapp_rollout_pose, plus joints:
- * device [N_a][N_k + 1][n_joints] joint angles or NULL.  EINVAL for a NULL arm,
- * n_joints outside 1..7, NULL links or q0, or a damping that is not finite and >= 0. */
+ * device [N_a][N_k + 1][n_joints] joint angles (q0 + the sum of dt qdot, not wrapped)
+ * or NULL.  EINVAL for a NULL arm, n_joints outside 1..7, NULL links or q0, a damping
+ * that is not finite and >= 0, or a forced tiling (gmapp_set_tiling) with more than
+ * 8 agents per group (each agent holds one lane per joint in a wave). */
 gmapp_status gmapp_rollout_arm(gmapp_ctx *ctx, const gmapp_scene *scene, const gmapp_agents *agents,
                                const gmapp_pose_agents *pose, const gmapp_arm *arm, const gmapp_query *query,
                                const gmapp_pose_query *pose_query, const gmapp_params *params,

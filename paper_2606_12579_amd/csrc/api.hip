@@ -321,6 +321,8 @@ gmapp_status rollout_6d(gmapp_ctx *ctx, const gmapp_scene *scene, const gmapp_ag
     if (!out || !out->best) return fail(ctx, GMAPP_EINVAL, "outputs.best is NULL");
     if (agents->n_agents > 0 && !out->cost) return fail(ctx, GMAPP_EINVAL, "outputs.cost is NULL");
     gm::Tiling t = tiling_for(ctx, scene->n_points, agents->n_agents, params->n_steps, scene->n_seg, params->cutoff);
+    // arm agents hold a lane per joint in a wave: a chosen or tuned tiling is capped
+    if (arm && !ctx->forced && t.A > gm::kMaxArmAgentsPerGroup) t.A = gm::kMaxArmAgentsPerGroup;
     gm::Agt ag = dev_agents(agents);
     if (agents->n_agents > 0) {
         ag.k_r = pose->k_r;

@@ -10,11 +10,22 @@
 // v_b = (omega_b, u_b) the damped least-squares joint rates are
 //   qdot = J^T (J J^T + lambda^2 I)^-1 (R omega_b, R u_b),
 // the body-frame form J_b^T (J_b J_b^T + lambda^2 I)^-1 v_b written in the world
-// frame (J_b = diag(R^T, R^T) J).  Joint angles are held as half-angle rotors
-// (cos(q/2), sin(q/2)) in FP64 and advanced by a rotation through dt qdot / 2
-// (see advance), so that the
-// forward kinematics of consecutive steps differ by their true increment: the
-// jerk cost of Eq. (20) takes third differences of these positions.
+// frame (J_b = diag(R^T, R^T) J).
+//
+// Work is spread over the lanes of an agent.  In a wave, agent a's lanes are
+// a + AW j (j = 0 .. 64 / AW - 1), and lane j owns joint j: its half-angle rotor
+// (cos(q_j / 2), sin(q_j / 2)) in FP64 and its angle q_j, summed as q_j += dt qdot_j.
+// Per step:
+//   factor -- every lane walks the joint frames at the current angles (FP32),
+//     accumulates A = J J^T + lambda^2 I (FP64; J J^T squares J's condition
+//     number) and keeps its own column of J; A is factored as G G^T.  None of this
+//     depends on the repulsive force, so it runs while the force is exchanged;
+//   solve -- y = A^-1 (R omega_b, R u_b); the owner lane forms qdot_j = col_j . y
+//     and advances its rotor through dt qdot_j / 2 (see advance), so the forward
+//     kinematics of consecutive steps differ by their true increment (the jerk cost
+//     of Eq. (20) takes third differences of these positions);
+//   gather + fk_d -- the rotors are gathered from their owners and every lane
+//     evaluates the FP64 forward kinematics.
 #pragma once
 
 #include "gmapp_internal.h"
@@ -25,6 +36,7 @@ namespace arm {
 
 constexpr int kMaxJoints = 7;
 static_assert(kMaxJoints == kMaxArmJoints, "the chain length the host admits");
+static_assert(kMaxArmAgentsPerGroup * kMaxJoints <= 64, "each agent holds one lane per joint in a wave");
 
 struct QD {
     double w, x, y, z;
@@ -34,6 +46,17 @@ __device__ __forceinline__ QD qmul_d(const QD &a, const QD &b)
 {
     return QD{a.w * b.w - a.x * b.x - a.y * b.y - a.z * b.z, a.w * b.x + a.x * b.w + a.y * b.z - a.z * b.y,
               a.w * b.y - a.x * b.z + a.y * b.w + a.z * b.x, a.w * b.z + a.x * b.y - a.y * b.x + a.z * b.w};
+}
+
+// r (x) (c, 0, 0, s): a rotation about r's local z axis
+__device__ __forceinline__ QD qmul_z(const QD &r, double c, double s)
+{
+    return QD{r.w * c - r.z * s, r.x * c + r.y * s, r.y * c - r.x * s, r.z * c + r.w * s};
+}
+
+__device__ __forceinline__ pose::Q qmul_z(const pose::Q &r, float c, float s)
+{
+    return pose::Q{r.w * c - r.z * s, r.x * c + r.y * s, r.y * c - r.x * s, r.z * c + r.w * s};
 }
 
 __device__ __forceinline__ void qrot_d(const QD &q, double vx, double vy, double vz, double &ox, double &oy,
@@ -46,65 +69,93 @@ __device__ __forceinline__ void qrot_d(const QD &q, double vx, double vy, double
     oz = vz + 2.0 * (q.w * cz + dz);
 }
 
+// 1 / sqrt(x) for x in the FP32 normal range: the FP32 hardware estimate refined by
+// two Newton steps y <- y (1 + (1 - x y^2) / 2), each of which squares the relative error
+__device__ __forceinline__ double rsqrt_d(double x)
+{
+    double y = (double)__builtin_amdgcn_rsqf((float)x);
+    double e = fma(-x * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+    e = fma(-x * y, y, 1.0);
+    return fma(0.5 * y, e, y);
+}
+
+// a double from lane src (every lane of the wave must be active)
+__device__ __forceinline__ double lane_d(double v, int src)
+{
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const int lo = __builtin_amdgcn_ds_bpermute(src << 2, (int)(unsigned)b);
+    const int hi = __builtin_amdgcn_ds_bpermute(src << 2, (int)(unsigned)(b >> 32));
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+// every lane of agent a_w receives the rotors (c[i], s[i]) held by the joints' owner lanes a_w + AW i
+template <int AW>
+__device__ __forceinline__ void gather(double c_own, double s_own, int a_w, double *c, double *s)
+{
+    static_assert(AW * kMaxJoints <= 64, "joint owners within the wave");
+#pragma unroll
+    for (int i = 0; i < kMaxJoints; ++i) {
+        c[i] = lane_d(c_own, a_w + AW * i);
+        s[i] = lane_d(s_own, a_w + AW * i);
+    }
+}
+
 // end-effector pose (rotor, position) in FP64 for joint half-angle rotors (c[i], s[i])
 __device__ __forceinline__ void fk_d(const float *L, int n, const double *c, const double *s, QD &r, double &tx,
                                      double &ty, double &tz)
 {
     r = QD{L[0], L[1], L[2], L[3]};
     tx = L[4]; ty = L[5]; tz = L[6];
+#pragma unroll
     for (int i = 0; i < kMaxJoints; ++i) {
         if (i >= n) break;
-        r = qmul_d(r, QD{c[i], 0.0, 0.0, s[i]});
+        r = qmul_z(r, c[i], s[i]);
         const float *l = L + 7 * (i + 1);
         double ox, oy, oz;
         qrot_d(r, l[4], l[5], l[6], ox, oy, oz);
         tx += ox; ty += oy; tz += oz;
         r = qmul_d(r, QD{l[0], l[1], l[2], l[3]});
     }
-    const double nr = 1.0 / sqrt(r.w * r.w + r.x * r.x + r.y * r.y + r.z * r.z);
+    const double nr = rsqrt_d(r.w * r.w + r.x * r.x + r.y * r.y + r.z * r.z);
     r = QD{r.w * nr, r.x * nr, r.y * nr, r.z * nr};
 }
 
-// visit every joint's axis z_i and origin o_i (FP32) at the half-angle rotors (c, s)
-template <class F>
-__device__ __forceinline__ void joints_f(const float *L, int n, const double *c, const double *s, F &&visit)
+// The joint frames at the rotors (c, s) (FP32) give J; A = J J^T + lam2 I (FP64, lower
+// triangle row-major, 21 entries) is factored in place as G G^T, G lower triangular,
+// with G's diagonal stored as its reciprocals.  col receives column `mine` of J (zeros
+// when mine >= n).  p: end-effector position.
+__device__ __forceinline__ void factor(const float *L, int n, const double *c, const double *s, float px, float py,
+                                       float pz, float lam2, int mine, double *A, float *col)
 {
+#pragma unroll
+    for (int k = 0; k < 21; ++k) A[k] = 0.0;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) col[k] = 0.0f;
     pose::Q r{L[0], L[1], L[2], L[3]};
     float tx = L[4], ty = L[5], tz = L[6];
+#pragma unroll
     for (int i = 0; i < kMaxJoints; ++i) {
         if (i >= n) break;
-        float zx, zy, zz;
-        pose::qrot(r, 1.0f, 0.0f, 0.0f, 1.0f, zx, zy, zz);
-        visit(i, zx, zy, zz, tx, ty, tz);
-        r = pose::qmul(r, pose::Q{(float)c[i], 0.0f, 0.0f, (float)s[i]});
+        // z axis of the frame r: the third column of its rotation matrix
+        const float zx = 2.0f * (r.x * r.z + r.w * r.y), zy = 2.0f * (r.y * r.z - r.w * r.x);
+        const float zz = 1.0f - 2.0f * (r.x * r.x + r.y * r.y);
+        const float rx = px - tx, ry = py - ty, rz = pz - tz;
+        const float cl[6] = {zx, zy, zz, zy * rz - zz * ry, zz * rx - zx * rz, zx * ry - zy * rx};
+#pragma unroll
+        for (int a = 0; a < 6; ++a) {
+            col[a] = (i == mine) ? cl[a] : col[a];
+#pragma unroll
+            for (int b = 0; b <= a; ++b) A[a * (a + 1) / 2 + b] = fma((double)cl[a], (double)cl[b], A[a * (a + 1) / 2 + b]);
+        }
+        r = qmul_z(r, (float)c[i], (float)s[i]);
         const float *l = L + 7 * (i + 1);
         float ox, oy, oz;
         pose::qrot(r, 1.0f, l[4], l[5], l[6], ox, oy, oz);
         tx += ox; ty += oy; tz += oz;
         r = pose::qmul(r, pose::Q{l[0], l[1], l[2], l[3]});
     }
-}
-
-// joint rates for the world twist (wa, wl) at end-effector position p:
-// qdot = J^T y, (J J^T + lambda^2 I) y = (wa, wl): the FP32 columns are accumulated
-// and the system is solved by Cholesky in FP64 (J J^T squares J's condition number)
-__device__ __forceinline__ void joint_rates(const float *L, int n, const double *c, const double *s, float px,
-                                            float py, float pz, const float wa[3], const float wl[3], float lam2,
-                                            float *qd)
-{
-    double A[21];                                  // lower triangle of the 6x6 matrix, row-major
-#pragma unroll
-    for (int k = 0; k < 21; ++k) A[k] = 0.0;
-    joints_f(L, n, c, s, [&](int, float zx, float zy, float zz, float ox, float oy, float oz) {
-        const float rx = px - ox, ry = py - oy, rz = pz - oz;
-        const double col[6] = {zx, zy, zz, zy * rz - zz * ry, zz * rx - zx * rz, zx * ry - zy * rx};
-#pragma unroll
-        for (int a = 0; a < 6; ++a)
-#pragma unroll
-            for (int b = 0; b <= a; ++b) A[a * (a + 1) / 2 + b] += col[a] * col[b];
-    });
     A[0] += lam2; A[2] += lam2; A[5] += lam2; A[9] += lam2; A[14] += lam2; A[20] += lam2;
-    // Cholesky in place: A = G G^T, G lower
 #pragma unroll
     for (int a = 0; a < 6; ++a) {
         const int ra = a * (a + 1) / 2;
@@ -113,33 +164,34 @@ __device__ __forceinline__ void joint_rates(const float *L, int n, const double 
             const int rb = b * (b + 1) / 2;
             double sum = A[ra + b];
 #pragma unroll
-            for (int k = 0; k < b; ++k) sum -= A[ra + k] * A[rb + k];
-            A[ra + b] = (a == b) ? sqrt(fmax(sum, 1e-300)) : sum / A[rb + b];
+            for (int k = 0; k < b; ++k) sum = fma(-A[ra + k], A[rb + k], sum);
+            // the clamp keeps a singular undamped system finite (its rates are then huge)
+            A[ra + b] = (a == b) ? rsqrt_d(fmax(sum, 1e-30)) : sum * A[rb + b];
         }
     }
-    double y[6] = {wa[0], wa[1], wa[2], wl[0], wl[1], wl[2]};
+}
+
+// y <- (G G^T)^-1 y for the factor of factor()
+__device__ __forceinline__ void solve(const double *A, double *y)
+{
 #pragma unroll
-    for (int a = 0; a < 6; ++a) {                  // G z = b
+    for (int a = 0; a < 6; ++a) {                  // G z = y
         const int ra = a * (a + 1) / 2;
 #pragma unroll
-        for (int k = 0; k < a; ++k) y[a] -= A[ra + k] * y[k];
-        y[a] /= A[ra + a];
+        for (int k = 0; k < a; ++k) y[a] = fma(-A[ra + k], y[k], y[a]);
+        y[a] *= A[ra + a];
     }
 #pragma unroll
     for (int a = 5; a >= 0; --a) {                 // G^T y = z
 #pragma unroll
-        for (int k = a + 1; k < 6; ++k) y[a] -= A[k * (k + 1) / 2 + a] * y[k];
-        y[a] /= A[a * (a + 1) / 2 + a];
+        for (int k = a + 1; k < 6; ++k) y[a] = fma(-A[k * (k + 1) / 2 + a], y[k], y[a]);
+        y[a] *= A[a * (a + 1) / 2 + a];
     }
-    joints_f(L, n, c, s, [&](int i, float zx, float zy, float zz, float ox, float oy, float oz) {
-        const float rx = px - ox, ry = py - oy, rz = pz - oz;
-        qd[i] = (float)(zx * y[0] + zy * y[1] + zz * y[2] + (zy * rz - zz * ry) * y[3] + (zz * rx - zx * rz) * y[4] +
-                        (zx * ry - zy * rx) * y[5]);
-    });
 }
 
 // advance a half-angle rotor (c, s) by the half angle h: rotation by (cos h, sin h), by
-// series for |h| <= 0.05 (truncation under 1e-17), else by sincos
+// series for |h| <= 0.05 (truncation under 1e-17), else by sincos.  Both factors are
+// unit to rounding, so one Newton step from 1 renormalises the product.
 __device__ __forceinline__ void advance(double &c, double &s, double h)
 {
     const double h2 = h * h;
@@ -151,7 +203,7 @@ __device__ __forceinline__ void advance(double &c, double &s, double h)
         sincos(h, &sh, &ch);
     }
     const double c1 = c * ch - s * sh, s1 = s * ch + c * sh;
-    const double nr = 1.0 / sqrt(c1 * c1 + s1 * s1);
+    const double nr = fma(-0.5, fma(c1, c1, s1 * s1), 1.5);
     c = c1 * nr;
     s = s1 * nr;
 }

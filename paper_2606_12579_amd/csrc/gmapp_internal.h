@@ -207,6 +207,7 @@ Tiling choose_tiling(const gmapp_ctx *ctx, long long n_points, int n_agents, int
 gmapp_status fit_coresident(gmapp_ctx *ctx, Tiling &t, const Scn &sc, const Agt &ag, const Prm &pr);
 
 constexpr int kMaxArmJoints = 7;                      // serial chains of arm agents
+constexpr int kMaxArmAgentsPerGroup = 8;              // arm agents hold a lane per joint in a wave
 
 // closed planning loop and the control query (control.hip)
 constexpr int kMaxControlSegments = 128;

@@ -147,7 +147,11 @@ gmapp_status launch_rollout(gmapp_ctx *ctx, const Scn &sc, const Agt &ag, const 
         return GMAPP_OK;
     }
     KFn fn = pick_kernel(t.A, t.W, t.wg != 0, pr.cutoff, is_probe, ag.heur != nullptr, kind_of(ag, pr));
-    if (!fn) return fail(ctx, GMAPP_EINVAL, "6-D pose agents have no teacher-forced form");
+    if (!fn) {
+        if (is_probe) return fail(ctx, GMAPP_EINVAL, "6-D pose agents have no teacher-forced form");
+        return fail(ctx, GMAPP_EINVAL, "arm agents take at most %d agents per group (tiling has %d)",
+                    kMaxArmAgentsPerGroup, t.A);
+    }
     const int per_wg = t.wg ? t.A : t.A * t.W;
     const int gpw = t.wg ? 1 : t.W;
     const int G = (ag.n + per_wg - 1) / per_wg;

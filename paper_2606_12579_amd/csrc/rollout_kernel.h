@@ -117,6 +117,7 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
 
     constexpr bool POSE = KIND >= 1;
     constexpr bool ARM = KIND == 2;
+    static_assert(!ARM || AW <= kMaxArmAgentsPerGroup, "arm agents hold a lane per joint in a wave");
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
@@ -213,24 +214,24 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
     pose::Q qr{1.f, 0.f, 0.f, 0.f};
     float ox = 0, oy = 0, oz = 0, ux = 0, uy = 0, uz = 0, cux = 0, cuy = 0, cuz = 0;
     float D1x = 0, D1y = 0, D1z = 0, D2x = 0, D2y = 0, D2z = 0, D3x = 0, D3y = 0, D3z = 0;
-    // arm agents: joint half-angle rotors, the FP64 end-effector position and the start position
-    double jc[arm::kMaxJoints], js[arm::kMaxJoints];
+    // arm agents: lane a_w + AW j of each wave owns joint j (j = lane / AW): its half-angle
+    // rotor and its angle; every lane holds the FP64 end-effector position and the start position
+    const int my_j = lane / AW;
+    double jc_own = 1.0, js_own = 0.0, q_own = 0.0;
     double pdx = 0, pdy = 0, pdz = 0;
     float a0x = 0, a0y = 0, a0z = 0;
     if constexpr (ARM && !PROBE) {
-#pragma unroll
-        for (int i = 0; i < arm::kMaxJoints; ++i) {
-            jc[i] = 1.0; js[i] = 0.0;
-            if (i < pr.arm_n) sincos(0.5 * (double)pr.arm_q0[i], &js[i], &jc[i]);
+        if (my_j < pr.arm_n) {
+            q_own = (double)pr.arm_q0[my_j];
+            sincos(0.5 * q_own, &js_own, &jc_own);
         }
+        double jc[arm::kMaxJoints], js[arm::kMaxJoints];
+        arm::gather<AW>(jc_own, js_own, a_w, jc, js);
         arm::QD r;
         arm::fk_d(pr.arm_links, pr.arm_n, jc, js, r, pdx, pdy, pdz);
         qr = pose::Q{(float)r.w, (float)r.x, (float)r.y, (float)r.z};
         px = (float)pdx; py = (float)pdy; pz = (float)pdz;
         a0x = px; a0y = py; a0z = pz;
-    } else {
-#pragma unroll
-        for (int i = 0; i < arm::kMaxJoints; ++i) { jc[i] = 1.0; js[i] = 0.0; }
     }
     if constexpr (POSE && !PROBE) {
         if constexpr (!ARM) qr = pose::qnormalize(pose::Q{pr.q0[0], pr.q0[1], pr.q0[2], pr.q0[3]});
@@ -255,11 +256,10 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
             ro[0] = qr.w; ro[1] = qr.x; ro[2] = qr.y; ro[3] = qr.z;
         }
     }
+    // joint angles are written by their owner lanes of the lead wave of shard 0
+    const bool jwriter = ARM && valid && s == 0 && lead && !PROBE && my_j < pr.arm_n;
     if constexpr (ARM) {
-        if (writer && out.joints) {
-            float *jo = out.joints + (size_t)agent * (pr.n_steps + 1) * pr.arm_n;
-            for (int i = 0; i < pr.arm_n && i < arm::kMaxJoints; ++i) jo[i] = pr.arm_q0[i];
-        }
+        if (jwriter && out.joints) out.joints[(size_t)agent * (pr.n_steps + 1) * pr.arm_n + my_j] = pr.arm_q0[my_j];
     }
     const unsigned long long t_start = __builtin_amdgcn_s_memrealtime();
 
@@ -342,6 +342,8 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
         // (f_r is a pure force), its exponential and the coefficients of J(dt omega)
         float aLx = 0, aLy = 0, aLz = 0, jA = 0, jB = 0;
         pose::Q dq{1.f, 0.f, 0.f, 0.f};
+        double Af[21];                      // arm agents: factor of J J^T + lambda^2 I
+        float colj[6];                      // arm agents: this lane's column of J
         auto pose_early = [&]() {
             float phx, phy, phz, tx, ty, tz, rx, ry, rz;
             pose::so3_log(pose::qmul(pose::Q{qr.w, -qr.x, -qr.y, -qr.z},
@@ -355,7 +357,12 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
             ox = fmaf(hr, fmaf(P.kr, phx, -P.dr * ox), ox);
             oy = fmaf(hr, fmaf(P.kr, phy, -P.dr * oy), oy);
             oz = fmaf(hr, fmaf(P.kr, phz, -P.dr * oz), oz);
-            if constexpr (!ARM) {
+            if constexpr (ARM) {
+                // J at the current joints and the factor of J J^T + lambda^2 I (Eq. 12)
+                double jc[arm::kMaxJoints], js[arm::kMaxJoints];
+                arm::gather<AW>(jc_own, js_own, a_w, jc, js);
+                arm::factor(pr.arm_links, pr.arm_n, jc, js, px, py, pz, pr.arm_lam2, my_j, Af, colj);
+            } else {
                 const float ax = pr.dt * ox, ay = pr.dt * oy, az = pr.dt * oz;
                 dq = pose::so3_exp(ax, ay, az);
                 pose::jac_coeffs(ax, ay, az, 1.0f, jA, jB);
@@ -485,14 +492,21 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
                 kahan_add(uz, cuz, h * (aLz + fz));
                 float dx, dy, dz;
                 if constexpr (ARM) {
-                    // joints (Eqs. 12, 13): qdot = J^+ v, q += dt qdot; pose (Eq. 14): M = FK(q)
-                    float wa[3], wl[3], qd[arm::kMaxJoints];
+                    // joints (Eqs. 12, 13): qdot = J^+ v, q += dt qdot (each on its owner lane);
+                    // pose (Eq. 14): M = FK(q)
+                    float wa[3], wl[3];
                     pose::qrot(qr, 1.0f, ox, oy, oz, wa[0], wa[1], wa[2]);
                     pose::qrot(qr, 1.0f, ux, uy, uz, wl[0], wl[1], wl[2]);
-                    arm::joint_rates(pr.arm_links, pr.arm_n, jc, js, px, py, pz, wa, wl, pr.arm_lam2, qd);
-#pragma unroll
-                    for (int i = 0; i < arm::kMaxJoints; ++i)
-                        if (i < pr.arm_n) arm::advance(jc[i], js[i], 0.5 * (double)pr.dt * (double)qd[i]);
+                    double y[6] = {wa[0], wa[1], wa[2], wl[0], wl[1], wl[2]};
+                    arm::solve(Af, y);
+                    const float qd = (float)(colj[0] * y[0] + colj[1] * y[1] + colj[2] * y[2] + colj[3] * y[3] +
+                                             colj[4] * y[4] + colj[5] * y[5]);
+                    if (my_j < pr.arm_n) {
+                        arm::advance(jc_own, js_own, 0.5 * (double)pr.dt * (double)qd);
+                        q_own += (double)pr.dt * (double)qd;
+                    }
+                    double jc[arm::kMaxJoints], js[arm::kMaxJoints];
+                    arm::gather<AW>(jc_own, js_own, a_w, jc, js);
                     arm::QD r;
                     double tx, ty, tz;
                     arm::fk_d(pr.arm_links, pr.arm_n, jc, js, r, tx, ty, tz);
@@ -524,14 +538,11 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
                         float *ro = out.rot + ((size_t)agent * (pr.n_steps + 1) + k) * 4;
                         ro[0] = qr.w; ro[1] = qr.x; ro[2] = qr.y; ro[3] = qr.z;
                     }
-                    if constexpr (ARM) {
-                        if (out.joints) {
-                            float *jo = out.joints + ((size_t)agent * (pr.n_steps + 1) + k) * pr.arm_n;
-                            for (int i = 0; i < pr.arm_n && i < arm::kMaxJoints; ++i)
-                                jo[i] = (float)(2.0 * atan2(js[i], jc[i]));
-                        }
-                    }
                     if (out.min_clear) out.min_clear[(size_t)agent * pr.n_steps + (k - 1)] = rho_min;
+                }
+                if constexpr (ARM) {
+                    if (jwriter && out.joints)
+                        out.joints[((size_t)agent * (pr.n_steps + 1) + k) * pr.arm_n + my_j] = (float)q_own;
                 }
                 return;
             }
@@ -677,7 +688,10 @@ using KFn = void (*)(Scn, Agt, Prm, Out, Probe, Xch, Lay);
 template <int AW, int W, int WS, bool HET, int KIND>
 KFn pick_cut(int cut, bool probe)
 {
-    if constexpr (KIND != 0) {      // pose and arm agents have no teacher-forced form (the probe takes p, v)
+    if constexpr (KIND == 2 && AW > kMaxArmAgentsPerGroup) {   // arm agents need a lane per joint in a wave
+        (void)cut; (void)probe;
+        return nullptr;
+    } else if constexpr (KIND != 0) {   // pose and arm agents have no teacher-forced form (the probe takes p, v)
         if (probe) return nullptr;
         return cut ? k_rollout<AW, W, WS, 1, false, HET, KIND> : k_rollout<AW, W, WS, 0, false, HET, KIND>;
     } else {

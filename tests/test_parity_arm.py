@@ -100,6 +100,15 @@ def test_arm_validation(ctx):
     with pytest.raises(gmapp.GmappError) as ei:
         ctx.rollout_arm(sc, ag, dpa, L9, q8, 0.01, pb.query, pq, pb.params)
     assert ei.value.status == gmapp.EINVAL
+    # each agent holds one lane per joint in a wave: at most 8 agents per group
+    ctx.set_tiling(16, 1, 1, 0, 0, 1)
+    try:
+        with pytest.raises(gmapp.GmappError) as ei:
+            ctx.rollout_arm(sc, ag, dpa, Ld, qd, 0.01, pb.query, pq, pb.params)
+        assert ei.value.status == gmapp.EINVAL and "agents per group" in str(ei.value)
+    finally:
+        ctx.clear_tiling()
+    torch.cuda.synchronize()
 
 
 def test_arm_full_size_sampled(ctx):

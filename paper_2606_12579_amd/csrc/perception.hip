@@ -141,20 +141,46 @@ __device__ __forceinline__ bool on_robot(float px, float py, float pz, const Vox
     return false;
 }
 
-// occupancy (min_count 1: a plain store of 1, racing writers store the same value)
-// or counts (atomic increments)
+// mark a point's cell: occupancy (min_count 1: a plain store of 1, racing writers
+// store the same value) or counts (atomic increments)
+template <bool COUNT>
+__device__ __forceinline__ void mark(float px, float py, float pz, const VoxGrid &g, unsigned *__restrict__ grid)
+{
+    long long c = cell_of(px, py, pz, g);
+    if (c >= 0 && g.n_excl > 0 && on_robot(px, py, pz, g)) c = -1;
+    if (c >= 0) {
+        if constexpr (COUNT) atomicAdd(&grid[c], 1u);
+        else grid[c] = 1u;
+    }
+}
+
 template <bool COUNT>
 __global__ void k_count(const float *__restrict__ x, const float *__restrict__ y, const float *__restrict__ z,
                         long long n, VoxGrid g, unsigned *__restrict__ grid)
 {
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
-        long long c = cell_of(x[i], y[i], z[i], g);
-        if (c >= 0 && g.n_excl > 0 && on_robot(x[i], y[i], z[i], g)) c = -1;
-        if (c >= 0) {
-            if constexpr (COUNT) atomicAdd(&grid[c], 1u);
-            else grid[c] = 1u;
-        }
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        mark<COUNT>(x[i], y[i], z[i], g, grid);
+}
+
+// The same with four points per thread from 16-byte loads of each coordinate stream
+// (x, y, z 16-byte aligned); the last n - 4 n4 (< 4) points go to the first threads.
+template <bool COUNT>
+__global__ __launch_bounds__(256) void k_count_v4(const float4 *__restrict__ x4, const float4 *__restrict__ y4,
+                                                  const float4 *__restrict__ z4, long long n4,
+                                                  const float *__restrict__ x, const float *__restrict__ y,
+                                                  const float *__restrict__ z, long long n, VoxGrid g,
+                                                  unsigned *__restrict__ grid)
+{
+    const long long tid = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    for (long long i = tid; i < n4; i += (long long)gridDim.x * blockDim.x) {
+        const float4 a = x4[i], b = y4[i], c = z4[i];
+        mark<COUNT>(a.x, b.x, c.x, g, grid);
+        mark<COUNT>(a.y, b.y, c.y, g, grid);
+        mark<COUNT>(a.z, b.z, c.z, g, grid);
+        mark<COUNT>(a.w, b.w, c.w, g, grid);
     }
+    const long long t = 4 * n4 + tid;
+    if (t < n) mark<COUNT>(x[t], y[t], z[t], g, grid);
 }
 
 __device__ __forceinline__ unsigned block_sum(unsigned v, unsigned *sh)
@@ -312,7 +338,20 @@ gmapp_status launch_voxel_downsample(gmapp_ctx *ctx, const float *x, const float
     unsigned *bsum = reinterpret_cast<unsigned *>(ctx->scratch + ((size_t)cells * 4 + 255) / 256 * 256);
     const int zb = (int)std::min<long long>((cells + 255) / 256, 8192);
     hipLaunchKernelGGL(k_zero_u32, dim3(zb), dim3(256), 0, stream, grid, cells);
-    if (n > 0) {
+    // four points per thread only when the quads still give every SIMD two waves; below that
+    // one point per thread hides more latency
+    auto aligned = [](const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; };
+    const long long fill = 2ll * 64 * 4 * std::max(ctx->n_cu, 1);
+    if (n / 4 >= fill && aligned(x) && aligned(y) && aligned(z)) {
+        const long long n4 = n / 4;
+        const int pb = (int)std::min<long long>((n4 + 255) / 256, 16384);
+        const float4 *x4 = reinterpret_cast<const float4 *>(x), *y4 = reinterpret_cast<const float4 *>(y);
+        const float4 *z4 = reinterpret_cast<const float4 *>(z);
+        if (min_count > 1)
+            hipLaunchKernelGGL(k_count_v4<true>, dim3(pb), dim3(256), 0, stream, x4, y4, z4, n4, x, y, z, n, g, grid);
+        else
+            hipLaunchKernelGGL(k_count_v4<false>, dim3(pb), dim3(256), 0, stream, x4, y4, z4, n4, x, y, z, n, g, grid);
+    } else if (n > 0) {
         const int pb = (int)std::min<long long>((n + 255) / 256, 8192);
         if (min_count > 1) hipLaunchKernelGGL(k_count<true>, dim3(pb), dim3(256), 0, stream, x, y, z, n, g, grid);
         else hipLaunchKernelGGL(k_count<false>, dim3(pb), dim3(256), 0, stream, x, y, z, n, g, grid);

@@ -121,6 +121,31 @@ def test_voxel_edges(ctx):
     assert int(n.item()) == 0
 
 
+def test_voxel_ragged_and_unaligned(ctx):
+    """Above about 2^19 points (two waves per SIMD of four-point threads) the marking pass
+    takes four points per thread from 16-byte loads when x, y, z are 16-byte aligned and
+    hands the last n mod 4 points to single threads; shorter or unaligned inputs take the
+    one-point path.  Every length and alignment gives the oracle's cells."""
+    import torch
+    rng = np.random.default_rng(17)
+    lo, dims, s = np.array([0.0, 0.0, 0.0], np.float32), np.array([4, 3, 2], np.int32), 0.01
+    P = rng.uniform(-0.005, 0.045, ((1 << 21) + 8, 3)).astype(np.float32)   # 24 cells, many points each
+    for n in (1, 2, 3, 4, 5, 7, 8, 9, 4097, (1 << 21) + 1, (1 << 21) + 3, 1 << 21):
+        for off in (0, 1):                                           # off 1: a view 4 bytes into the buffer
+            Q = P[off:off + n]
+            full = [torch.as_tensor(np.ascontiguousarray(P[:off + n, a]), device="cuda") for a in range(3)]
+            t = [f[off:] for f in full]
+            for min_count in (1, 2):
+                cells = op.voxel_cells(Q[:, 0], Q[:, 1], Q[:, 2], s, lo, dims, min_count)
+                ox, oy, oz, m = ctx.voxel_downsample(*t, s, lo, dims, min_count=min_count, capacity=64)
+                torch.cuda.synchronize()
+                m = int(m.item())
+                assert m == len(cells), (n, off, min_count, m, len(cells))
+                C = op.voxel_centres(cells, s, lo, dims).astype(np.float32)
+                G = np.stack([ox[:m].cpu().numpy(), oy[:m].cpu().numpy(), oz[:m].cpu().numpy()], 1)
+                assert np.array_equal(G, C), (n, off, min_count)
+
+
 def test_pipeline_config3(ctx):
     """Depth image -> points -> voxel centres on the GPU against the oracle's
     pipeline; cells may differ only where an input point lies within 1e-5 of a

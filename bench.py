@@ -78,6 +78,77 @@ def cpu_baseline(pb):
                       f"threads of {os.cpu_count()} logical CPUs ({cpu})"}
 
 
+def cpu_baseline_rows(legs):
+    """The oracle timed beside the other legs, each on a bounded sample of that leg's
+    workload (agents are independent, so a subset of agents over the full scene and
+    horizon is the same per-interaction work).  Part of the cpu_baseline leg."""
+    import copy
+    import numpy as np
+    import oracle
+    from oracle import arm as oarm, perception as operc
+    from paper_2606_12579_amd import scenes
+
+    def timed(fn):
+        t0 = time.perf_counter()
+        fn()
+        return time.perf_counter() - t0
+
+    rows = {}
+    idx = [0, 9, 18, 27, 36, 45, 54, 63]
+    threads = min(len(idx), oracle.n_threads())
+    if "heterogeneous" in legs:
+        pb = scenes.config2()
+        pb.agents = scenes.multi_agents(np.random.default_rng(11), pb.agents.n).subset(idx)
+        n = oracle.interactions(pb)
+        dt = timed(lambda: oracle.rollout(pb))
+        rows["heterogeneous"] = {"value": n / dt, "unit": "interactions/s", "cores": threads,
+                                 "sample": f"agents {idx} of the mixed ensemble, full scene and horizon, {dt:.2f} s"}
+    if "pose" in legs:
+        pb = scenes.config2()
+        rng = np.random.default_rng(21)
+        pa, pq = scenes.pose_agents(rng, pb.agents.n), scenes.pose_query(rng)
+        pb.agents = pb.agents.subset(idx)
+        n = oracle.interactions(pb)
+        dt = timed(lambda: oracle.rollout_pose(pb, pa.subset(idx), pq))
+        rows["pose"] = {"value": n / dt, "unit": "interactions/s", "cores": threads,
+                        "sample": f"pose agents {idx}, full scene and horizon, {dt:.2f} s"}
+    if "arm" in legs:
+        pb = scenes.config2()
+        pb.query.goal = np.array([0.55, 0.25, 0.35], np.float32)
+        _, pa, pq, L, q0 = scenes.arm_problem(n_agents=pb.agents.n)
+        pb.agents = pb.agents.subset([0])
+        n = oracle.interactions(pb)
+        dt = timed(lambda: oarm.rollout_arm(pb, pa.subset([0]), pq, L, q0, 0.01))
+        rows["arm"] = {"value": n / dt, "unit": "interactions/s", "cores": 1,
+                       "sample": f"arm agent 0, full scene and horizon (NumPy chain, C repulsion), {dt:.2f} s"}
+    if "closed_loop" in legs:
+        pb = scenes.config2(n_steps=100)
+        dt = timed(lambda: oracle.plan_loop(copy.deepcopy(pb), 1, 10, 0.01))
+        rows["closed_loop"] = {"value": 1.0 / dt, "unit": "cycles/s", "cores": oracle.n_threads(),
+                               "sample": f"1 cycle (64-agent rollout of 100 steps and 10 control steps), {dt:.2f} s"}
+    if "perception" in legs:
+        fr = scenes.config3_frame()
+
+        def frame():
+            P = operc.back_project(fr.depth, fr.K, fr.T_wc).astype(np.float32)
+            cells = operc.voxel_cells(P[:, 0], P[:, 1], P[:, 2], fr.voxel, fr.box_lo, fr.dims)
+            operc.voxel_centres(cells, fr.voxel, fr.box_lo, fr.dims)
+            return len(cells)
+        nv = frame()
+        dt = timed(frame)
+        nbytes = 16 * fr.depth.size + 12 * fr.depth.size + 12 * nv
+        rows["perception"] = {"value": nbytes / dt / 1e9, "unit": "GB/s", "cores": 1,
+                              "sample": f"one 640x480 frame: back-projection and voxel pass (NumPy), {dt:.3f} s"}
+    if "adjoint" in legs:
+        pb = scenes.config4()
+        pb.agents = pb.agents.subset([0, 64])
+        n = oracle.interactions(pb)
+        dt = timed(lambda: oracle.rollout_grad(pb))
+        rows["adjoint"] = {"value": n / dt, "unit": "interactions/s", "cores": min(2, oracle.n_threads()),
+                           "sample": f"agents [0, 64] of config 4, forward and dual-number gradient, {dt:.2f} s"}
+    return rows
+
+
 def perception_pass(ctx, dev, reps=20):
     """Depth image (640x480) -> points -> 1 cm voxel centres, timed with HIP events.
     Algorithmic bytes: depth read + points written, points read + centres written."""
@@ -521,6 +592,8 @@ def main():
     del ref, ref2
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(pb)
+        res["cpu_baseline"]["per_row"] = cpu_baseline_rows(
+            [k for k in ("heterogeneous", "pose", "arm", "closed_loop", "perception", "adjoint") if k in res])
     ctx.close()
     print(json.dumps(res), flush=True)
 

@@ -85,6 +85,22 @@ def test_arm_rollout(ctx, case):
               f"best {gpu['best']}/{ref['best']}", flush=True)
 
 
+@pytest.mark.parametrize("n", [1, 3])
+def test_arm_short_chains(ctx, n):
+    """Chains of fewer joints than lanes per agent (the first n joints of the synthetic
+    arm): lanes past the last joint hold identity rotors and write no joint angles.  With
+    one joint the hand sits on the joint's axis, so J has no linear part and the hand
+    cannot move; with three it moves about 0.1 m."""
+    pb, pa, pq, L, q0 = scenes.arm_problem()
+    Ln, qn = np.ascontiguousarray(L[:n + 1]), np.ascontiguousarray(q0[:n])
+    ref = oa.rollout_arm(pb, pa, pq, Ln, qn, 0.01)
+    for tiling in (None, (2, 1, 2, 0, 1, 1), (8, 4, 1, 64, 2, 1)):
+        gpu = _gpu(ctx, pb, pa, pq, Ln, qn, 0.01, tiling)
+        assert gpu["joints"].shape == ref["joints"].shape
+        pos_err, rot_err, j_err = _check(pb, gpu, ref)
+        print(f"arm {n} joints tiling {tiling}: pos {pos_err:.2e} rotor {rot_err:.2e} joints {j_err:.2e}", flush=True)
+
+
 def test_arm_validation(ctx):
     import torch
     from paper_2606_12579_amd import gmapp

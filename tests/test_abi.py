@@ -78,3 +78,14 @@ int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %
     mine += [gmapp.Job.state.offset, gmapp.Job.k_end.offset, gmapp.Request.deadline_s.offset,
              gmapp.Agents.heuristic.offset, gmapp.STATE_FLOATS]
     assert sizes == mine
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: --gpus 2 exits with status 2 and a message, before any
+    device is touched."""
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120, cwd=root)
+    assert r.returncode == 2
+    assert "one GPU" in (r.stdout + r.stderr)

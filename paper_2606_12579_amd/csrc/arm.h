@@ -24,8 +24,8 @@
 //     and advances its rotor through dt qdot_j / 2 (see advance), so the forward
 //     kinematics of consecutive steps differ by their true increment (the jerk cost
 //     of Eq. (20) takes third differences of these positions);
-//   gather + fk_d -- the rotors are gathered from their owners and every lane
-//     evaluates the FP64 forward kinematics.
+//   fk_tree -- each owner lane forms its joint's transform Rz(q_j) L_{j+1}, and the
+//     FP64 forward kinematics is their product, taken as a tree over the lanes.
 #pragma once
 
 #include "gmapp_internal.h"
@@ -49,11 +49,6 @@ __device__ __forceinline__ QD qmul_d(const QD &a, const QD &b)
 }
 
 // r (x) (c, 0, 0, s): a rotation about r's local z axis
-__device__ __forceinline__ QD qmul_z(const QD &r, double c, double s)
-{
-    return QD{r.w * c - r.z * s, r.x * c + r.y * s, r.y * c - r.x * s, r.z * c + r.w * s};
-}
-
 __device__ __forceinline__ pose::Q qmul_z(const pose::Q &r, float c, float s)
 {
     return pose::Q{r.w * c - r.z * s, r.x * c + r.y * s, r.y * c - r.x * s, r.z * c + r.w * s};
@@ -101,24 +96,56 @@ __device__ __forceinline__ void gather(double c_own, double s_own, int a_w, doub
     }
 }
 
-// end-effector pose (rotor, position) in FP64 for joint half-angle rotors (c[i], s[i])
-__device__ __forceinline__ void fk_d(const float *L, int n, const double *c, const double *s, QD &r, double &tx,
-                                     double &ty, double &tz)
+// A rigid transform (rotor r, translation t) in FP64: x -> R(r) x + t
+struct TD {
+    QD r;
+    double x, y, z;
+};
+
+// a o b: first b, then a
+__device__ __forceinline__ TD compose(const TD &a, const TD &b)
 {
-    r = QD{L[0], L[1], L[2], L[3]};
-    tx = L[4]; ty = L[5]; tz = L[6];
-#pragma unroll
-    for (int i = 0; i < kMaxJoints; ++i) {
-        if (i >= n) break;
-        r = qmul_z(r, c[i], s[i]);
-        const float *l = L + 7 * (i + 1);
-        double ox, oy, oz;
-        qrot_d(r, l[4], l[5], l[6], ox, oy, oz);
-        tx += ox; ty += oy; tz += oz;
-        r = qmul_d(r, QD{l[0], l[1], l[2], l[3]});
+    double ox, oy, oz;
+    qrot_d(a.r, b.x, b.y, b.z, ox, oy, oz);
+    return TD{qmul_d(a.r, b.r), a.x + ox, a.y + oy, a.z + oz};
+}
+
+__device__ __forceinline__ TD lane_td(const TD &v, int src)
+{
+    return TD{QD{lane_d(v.r.w, src), lane_d(v.r.x, src), lane_d(v.r.y, src), lane_d(v.r.z, src)}, lane_d(v.x, src),
+              lane_d(v.y, src), lane_d(v.z, src)};
+}
+
+// End-effector pose M(q) = L_0 T_0 T_1 ... T_7 with T_j = Rz(q_j) L_{j+1} for the joints
+// j < n (identity beyond): each owner lane a_w + AW j forms its T_j from its half-angle
+// rotor (c, s) -- Rz(q) turns offsets by (cos q, sin q) = (c^2 - s^2, 2 c s) -- and
+// three rounds of pairwise products over the agent's first 8 lanes leave the product on
+// lane a_w, which every lane of the agent then reads.  Every lane of the wave must be
+// active.
+template <int AW>
+__device__ __forceinline__ void fk_tree(const float *L, int n, int a_w, int j, double c, double s, QD &r, double &tx,
+                                        double &ty, double &tz)
+{
+    static_assert(AW * 8 <= 64, "8 lanes per agent in the wave");
+    TD T{QD{1.0, 0.0, 0.0, 0.0}, 0.0, 0.0, 0.0};
+    if (j < n && j < kMaxJoints) {
+        const float *l = L + 7 * (j + 1);
+        const double lw = l[0], lx = l[1], ly = l[2], lz = l[3];
+        const double cq = c * c - s * s, sq = 2.0 * c * s;
+        T = TD{QD{c * lw - s * lz, c * lx - s * ly, c * ly + s * lx, c * lz + s * lw}, cq * l[4] - sq * l[5],
+               sq * l[4] + cq * l[5], (double)l[6]};
     }
-    const double nr = rsqrt_d(r.w * r.w + r.x * r.x + r.y * r.y + r.z * r.z);
-    r = QD{r.w * nr, r.x * nr, r.y * nr, r.z * nr};
+    const int lane = a_w + AW * j;
+#pragma unroll
+    for (int stride = 1; stride < 8; stride *= 2) {
+        const TD o = lane_td(T, (lane + AW * stride) & 63);   // lanes past the agent's 8 give unused results
+        T = compose(T, o);
+    }
+    const TD P = lane_td(T, a_w);
+    const TD M = compose(TD{QD{L[0], L[1], L[2], L[3]}, L[4], L[5], L[6]}, P);
+    const double nr = rsqrt_d(M.r.w * M.r.w + M.r.x * M.r.x + M.r.y * M.r.y + M.r.z * M.r.z);
+    r = QD{M.r.w * nr, M.r.x * nr, M.r.y * nr, M.r.z * nr};
+    tx = M.x; ty = M.y; tz = M.z;
 }
 
 // The joint frames at the rotors (c, s) (FP32) give J; A = J J^T + lam2 I (FP64, lower

@@ -225,10 +225,8 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
             q_own = (double)pr.arm_q0[my_j];
             sincos(0.5 * q_own, &js_own, &jc_own);
         }
-        double jc[arm::kMaxJoints], js[arm::kMaxJoints];
-        arm::gather<AW>(jc_own, js_own, a_w, jc, js);
         arm::QD r;
-        arm::fk_d(pr.arm_links, pr.arm_n, jc, js, r, pdx, pdy, pdz);
+        arm::fk_tree<AW>(pr.arm_links, pr.arm_n, a_w, my_j, jc_own, js_own, r, pdx, pdy, pdz);
         qr = pose::Q{(float)r.w, (float)r.x, (float)r.y, (float)r.z};
         px = (float)pdx; py = (float)pdy; pz = (float)pdz;
         a0x = px; a0y = py; a0z = pz;
@@ -505,11 +503,9 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
                         arm::advance(jc_own, js_own, 0.5 * (double)pr.dt * (double)qd);
                         q_own += (double)pr.dt * (double)qd;
                     }
-                    double jc[arm::kMaxJoints], js[arm::kMaxJoints];
-                    arm::gather<AW>(jc_own, js_own, a_w, jc, js);
                     arm::QD r;
                     double tx, ty, tz;
-                    arm::fk_d(pr.arm_links, pr.arm_n, jc, js, r, tx, ty, tz);
+                    arm::fk_tree<AW>(pr.arm_links, pr.arm_n, a_w, my_j, jc_own, js_own, r, tx, ty, tz);
                     dx = (float)(tx - pdx); dy = (float)(ty - pdy); dz = (float)(tz - pdz);
                     pdx = tx; pdy = ty; pdz = tz;
                     px = (float)tx; py = (float)ty; pz = (float)tz;

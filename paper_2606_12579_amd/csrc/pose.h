@@ -12,7 +12,9 @@
 // under 2e-8 relative), so the per-step rotation dt |omega| ~ 1e-3 rad keeps full
 // FP32 accuracy.  Above it, a uses the cancellation-free 2 sin^2(theta/2) form;
 // the cancellation left in b and c weighs at most about one FP32 rounding of J v,
-// because they multiply the theta^2-sized [phi]^2 term.
+// because they multiply the theta^2-sized [phi]^2 term.  Square roots, reciprocals
+// and reciprocal square roots on the per-step path use the hardware instructions
+// (about 1 ulp) instead of the correctly rounded library sequences.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -32,7 +34,7 @@ __device__ __forceinline__ Q qmul(const Q &a, const Q &b)
 
 __device__ __forceinline__ Q qnormalize(const Q &a)
 {
-    const float s = 1.0f / sqrtf(a.w * a.w + a.x * a.x + a.y * a.y + a.z * a.z);
+    const float s = __builtin_amdgcn_rsqf(a.w * a.w + a.x * a.x + a.y * a.y + a.z * a.z);
     return Q{a.w * s, a.x * s, a.y * s, a.z * s};
 }
 
@@ -52,7 +54,7 @@ __device__ __forceinline__ void qrot(const Q &q, float sgn, float vx, float vy, 
 __device__ __forceinline__ Q so3_exp(float px, float py, float pz)
 {
     const float t2 = px * px + py * py + pz * pz;
-    const float th = sqrtf(t2);
+    const float th = __builtin_amdgcn_sqrtf(t2);
     float s, c;
     if (th < 0.25f) {                               // sin(th/2)/th and cos(th/2) by series
         s = 0.5f - t2 * (1.0f / 48.0f) + t2 * t2 * (1.0f / 3840.0f);
@@ -70,8 +72,8 @@ __device__ __forceinline__ Q so3_exp(float px, float py, float pz)
 __device__ __forceinline__ void so3_log(Q q, float &px, float &py, float &pz)
 {
     if (q.w < 0.0f) { q.w = -q.w; q.x = -q.x; q.y = -q.y; q.z = -q.z; }
-    const float n = sqrtf(q.x * q.x + q.y * q.y + q.z * q.z);
-    const float f = n > 1e-7f ? 2.0f * atan2f(n, q.w) / n : 2.0f / q.w;
+    const float n = __builtin_amdgcn_sqrtf(q.x * q.x + q.y * q.y + q.z * q.z);
+    const float f = 2.0f * __builtin_amdgcn_rcpf(n > 1e-7f ? n : q.w) * (n > 1e-7f ? atan2f(n, q.w) : 1.0f);
     px = f * q.x; py = f * q.y; pz = f * q.z;
 }
 
@@ -92,7 +94,7 @@ __device__ __forceinline__ void jac_mul(float px, float py, float pz, float a, f
 __device__ __forceinline__ void jac_coeffs(float px, float py, float pz, float sgn, float &a, float &b)
 {
     const float t2 = px * px + py * py + pz * pz;
-    const float th = sqrtf(t2);
+    const float th = __builtin_amdgcn_sqrtf(t2);
     if (sgn > 0.0f) {
         if (th < 0.25f) {
             a = 0.5f - t2 * (1.0f / 24.0f) + t2 * t2 * (1.0f / 720.0f);
@@ -109,7 +111,7 @@ __device__ __forceinline__ void jac_coeffs(float px, float py, float pz, float s
         } else {
             float sh, ch;
             sincosf(0.5f * th, &sh, &ch);
-            b = 1.0f / t2 - ch / (2.0f * th * sh);
+            b = __builtin_amdgcn_rcpf(t2) - ch * __builtin_amdgcn_rcpf(2.0f * th * sh);
         }
     }
 }

@@ -78,7 +78,7 @@ def test_arm_rollout(ctx, case):
     pb, pa, pq, L, q0 = scenes.arm_problem(moving=case == "moving")
     damping = 0.0 if case == "undamped" else 0.01
     ref = oa.rollout_arm(pb, pa, pq, L, q0, damping)
-    for tiling in (None, (1, 8, 4, 0, 0, 2), (2, 1, 2, 0, 1, 1), (8, 4, 1, 64, 2, 1)):
+    for tiling in (None, (1, 8, 4, 0, 0, 2), (2, 8, 4, 0, 0, 2), (2, 1, 2, 0, 1, 1), (8, 4, 1, 64, 2, 1)):
         gpu = _gpu(ctx, pb, pa, pq, L, q0, damping, tiling)
         pos_err, rot_err, j_err = _check(pb, gpu, ref)
         print(f"arm {case} tiling {tiling}: pos {pos_err:.2e} rotor {rot_err:.2e} joints {j_err:.2e} "

@@ -100,7 +100,8 @@ def _case(name):
 def test_pose_rollout(ctx, case):
     pb, pa, pq = _case(case)
     ref = oracle.rollout_pose(pb, pa, pq)
-    for tiling in (None, (1, 8, 4, 0, 0, 2), (2, 1, 2, 0, 1, 1), (8, 4, 1, 256, 2, 1), (4, 4, 4, 0, 0, 1)):
+    for tiling in (None, (1, 8, 4, 0, 0, 2), (2, 8, 4, 0, 0, 2), (2, 1, 2, 0, 1, 1), (8, 4, 1, 256, 2, 1),
+                   (4, 4, 4, 0, 0, 1)):
         gpu = _gpu(ctx, pb, pa, pq, tiling)
         pe, re = _compare(pb, gpu, ref)
         _log(f"pose {case} tiling {tiling}: pos err {pe:.2e} rotor err {re:.2e} best {gpu['best']}/{ref.best}")

@@ -14,18 +14,19 @@
 //
 // Work is spread over the lanes of an agent.  In a wave, agent a's lanes are
 // a + AW j (j = 0 .. 64 / AW - 1), and lane j owns joint j: its half-angle rotor
-// (cos(q_j / 2), sin(q_j / 2)) in FP64 and its angle q_j, summed as q_j += dt qdot_j.
-// Per step:
-//   factor -- every lane walks the joint frames at the current angles (FP32),
-//     accumulates A = J J^T + lambda^2 I (FP64; J J^T squares J's condition
-//     number) and keeps its own column of J; A is factored as G G^T.  None of this
-//     depends on the repulsive force, so it runs while the force is exchanged;
-//   solve -- y = A^-1 (R omega_b, R u_b); the owner lane forms qdot_j = col_j . y
-//     and advances its rotor through dt qdot_j / 2 (see advance), so the forward
-//     kinematics of consecutive steps differ by their true increment (the jerk cost
-//     of Eq. (20) takes third differences of these positions);
-//   fk_tree -- each owner lane forms its joint's transform Rz(q_j) L_{j+1}, and the
-//     FP64 forward kinematics is their product, taken as a tree over the lanes.
+// (cos(q_j / 2), sin(q_j / 2)) in FP64, its angle q_j, summed as q_j += dt qdot_j, and its
+// column of J.  Per step:
+//   factor_cols -- A = J J^T + lambda^2 I (FP64; J J^T squares J's condition number) is
+//     the sum of the joint lanes' outer products, taken by a butterfly over the lanes, and
+//     is factored as G G^T.  None of this depends on the repulsive force, so it runs while
+//     the force is exchanged;
+//   solve -- y = A^-1 (R omega_b, R u_b); the owner lane forms qdot_j = col_j . y and
+//     advances its rotor through dt qdot_j / 2 (see advance), so the forward kinematics of
+//     consecutive steps differ by their true increment (the jerk cost of Eq. (20) takes
+//     third differences of these positions);
+//   fk_scan -- each owner lane forms its joint's transform Rz(q_j) L_{j+1}; an inclusive
+//     scan of these over the lanes gives the FP64 end-effector pose and every joint's frame,
+//     from which each lane takes its column of J for the next step.
 #pragma once
 
 #include "gmapp_internal.h"
@@ -46,12 +47,6 @@ __device__ __forceinline__ QD qmul_d(const QD &a, const QD &b)
 {
     return QD{a.w * b.w - a.x * b.x - a.y * b.y - a.z * b.z, a.w * b.x + a.x * b.w + a.y * b.z - a.z * b.y,
               a.w * b.y - a.x * b.z + a.y * b.w + a.z * b.x, a.w * b.z + a.x * b.y - a.y * b.x + a.z * b.w};
-}
-
-// r (x) (c, 0, 0, s): a rotation about r's local z axis
-__device__ __forceinline__ pose::Q qmul_z(const pose::Q &r, float c, float s)
-{
-    return pose::Q{r.w * c - r.z * s, r.x * c + r.y * s, r.y * c - r.x * s, r.z * c + r.w * s};
 }
 
 __device__ __forceinline__ void qrot_d(const QD &q, double vx, double vy, double vz, double &ox, double &oy,
@@ -84,18 +79,6 @@ __device__ __forceinline__ double lane_d(double v, int src)
     return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
 }
 
-// every lane of agent a_w receives the rotors (c[i], s[i]) held by the joints' owner lanes a_w + AW i
-template <int AW>
-__device__ __forceinline__ void gather(double c_own, double s_own, int a_w, double *c, double *s)
-{
-    static_assert(AW * kMaxJoints <= 64, "joint owners within the wave");
-#pragma unroll
-    for (int i = 0; i < kMaxJoints; ++i) {
-        c[i] = lane_d(c_own, a_w + AW * i);
-        s[i] = lane_d(s_own, a_w + AW * i);
-    }
-}
-
 // A rigid transform (rotor r, translation t) in FP64: x -> R(r) x + t
 struct TD {
     QD r;
@@ -116,15 +99,15 @@ __device__ __forceinline__ TD lane_td(const TD &v, int src)
               lane_d(v.y, src), lane_d(v.z, src)};
 }
 
-// End-effector pose M(q) = L_0 T_0 T_1 ... T_7 with T_j = Rz(q_j) L_{j+1} for the joints
-// j < n (identity beyond): each owner lane a_w + AW j forms its T_j from its half-angle
-// rotor (c, s) -- Rz(q) turns offsets by (cos q, sin q) = (c^2 - s^2, 2 c s) -- and
-// three rounds of pairwise products over the agent's first 8 lanes leave the product on
-// lane a_w, which every lane of the agent then reads.  Every lane of the wave must be
-// active.
+// Forward kinematics by an inclusive scan of the joint transforms over the agent's first
+// 8 lanes (three rounds; lane j ends with T_0 ... T_j), which also gives every joint its
+// frame F_j = L_0 T_0 ... T_{j-1} (from lane j - 1).  Returns the end-effector pose
+// L_0 T_0 ... T_7 and, in col, this lane's column of the world Jacobian (z_j,
+// z_j x (p - o_j)) for joint j = mine (zeros when mine >= n).  Every lane of the wave must
+// be active.
 template <int AW>
-__device__ __forceinline__ void fk_tree(const float *L, int n, int a_w, int j, double c, double s, QD &r, double &tx,
-                                        double &ty, double &tz)
+__device__ __forceinline__ void fk_scan(const float *L, int n, int a_w, int j, double c, double s, QD &r, double &tx,
+                                        double &ty, double &tz, float *col)
 {
     static_assert(AW * 8 <= 64, "8 lanes per agent in the wave");
     TD T{QD{1.0, 0.0, 0.0, 0.0}, 0.0, 0.0, 0.0};
@@ -138,49 +121,48 @@ __device__ __forceinline__ void fk_tree(const float *L, int n, int a_w, int j, d
     const int lane = a_w + AW * j;
 #pragma unroll
     for (int stride = 1; stride < 8; stride *= 2) {
-        const TD o = lane_td(T, (lane + AW * stride) & 63);   // lanes past the agent's 8 give unused results
-        T = compose(T, o);
+        const TD o = lane_td(T, (lane - AW * stride) & 63);   // the earlier lanes' product
+        const TD u = compose(o, T);
+        if (j >= stride) T = u;
     }
-    const TD P = lane_td(T, a_w);
-    const TD M = compose(TD{QD{L[0], L[1], L[2], L[3]}, L[4], L[5], L[6]}, P);
-    const double nr = rsqrt_d(M.r.w * M.r.w + M.r.x * M.r.x + M.r.y * M.r.y + M.r.z * M.r.z);
-    r = QD{M.r.w * nr, M.r.x * nr, M.r.y * nr, M.r.z * nr};
-    tx = M.x; ty = M.y; tz = M.z;
+    const TD L0{QD{L[0], L[1], L[2], L[3]}, L[4], L[5], L[6]};
+    const TD E = compose(L0, lane_td(T, a_w + AW * 7));          // L_0 T_0 ... T_7
+    const TD prev = lane_td(T, (lane - AW) & 63);
+    const TD F = j == 0 ? L0 : compose(L0, prev);               // joint j's frame
+    const double nr = rsqrt_d(E.r.w * E.r.w + E.r.x * E.r.x + E.r.y * E.r.y + E.r.z * E.r.z);
+    r = QD{E.r.w * nr, E.r.x * nr, E.r.y * nr, E.r.z * nr};
+    tx = E.x; ty = E.y; tz = E.z;
+    // z axis of F: the third column of its rotation matrix
+    const double zx = 2.0 * (F.r.x * F.r.z + F.r.w * F.r.y), zy = 2.0 * (F.r.y * F.r.z - F.r.w * F.r.x);
+    const double zz = 1.0 - 2.0 * (F.r.x * F.r.x + F.r.y * F.r.y);
+    const double rx = tx - F.x, ry = ty - F.y, rz = tz - F.z;
+    const bool own = j < n && j < kMaxJoints;
+    col[0] = own ? (float)zx : 0.0f;
+    col[1] = own ? (float)zy : 0.0f;
+    col[2] = own ? (float)zz : 0.0f;
+    col[3] = own ? (float)(zy * rz - zz * ry) : 0.0f;
+    col[4] = own ? (float)(zz * rx - zx * rz) : 0.0f;
+    col[5] = own ? (float)(zx * ry - zy * rx) : 0.0f;
 }
 
-// The joint frames at the rotors (c, s) (FP32) give J; A = J J^T + lam2 I (FP64, lower
-// triangle row-major, 21 entries) is factored in place as G G^T, G lower triangular,
-// with G's diagonal stored as its reciprocals.  col receives column `mine` of J (zeros
-// when mine >= n).  p: end-effector position.
-__device__ __forceinline__ void factor(const float *L, int n, const double *c, const double *s, float px, float py,
-                                       float pz, float lam2, int mine, double *A, float *col)
+// A = J J^T + lam2 I from the columns held by the agent's first 8 lanes (each lane's outer
+// product, summed by a butterfly over the lanes a_w + AW j), factored in place as G G^T
+// (lower triangle row-major, G's diagonal stored as its reciprocals).  Every lane of the
+// wave must be active; every lane of the agent ends with the same factor.
+template <int AW>
+__device__ __forceinline__ void factor_cols(const float *col, float lam2, double *A)
 {
+    static_assert(AW * 8 <= 64, "8 lanes per agent in the wave");
 #pragma unroll
-    for (int k = 0; k < 21; ++k) A[k] = 0.0;
+    for (int a = 0; a < 6; ++a)
 #pragma unroll
-    for (int k = 0; k < 6; ++k) col[k] = 0.0f;
-    pose::Q r{L[0], L[1], L[2], L[3]};
-    float tx = L[4], ty = L[5], tz = L[6];
+        for (int b = 0; b <= a; ++b) A[a * (a + 1) / 2 + b] = (double)col[a] * (double)col[b];
+    const int lane = __lane_id();
 #pragma unroll
-    for (int i = 0; i < kMaxJoints; ++i) {
-        if (i >= n) break;
-        // z axis of the frame r: the third column of its rotation matrix
-        const float zx = 2.0f * (r.x * r.z + r.w * r.y), zy = 2.0f * (r.y * r.z - r.w * r.x);
-        const float zz = 1.0f - 2.0f * (r.x * r.x + r.y * r.y);
-        const float rx = px - tx, ry = py - ty, rz = pz - tz;
-        const float cl[6] = {zx, zy, zz, zy * rz - zz * ry, zz * rx - zx * rz, zx * ry - zy * rx};
+    for (int m = 1; m < 8; m *= 2) {
+        const int src = lane ^ (AW * m);
 #pragma unroll
-        for (int a = 0; a < 6; ++a) {
-            col[a] = (i == mine) ? cl[a] : col[a];
-#pragma unroll
-            for (int b = 0; b <= a; ++b) A[a * (a + 1) / 2 + b] = fma((double)cl[a], (double)cl[b], A[a * (a + 1) / 2 + b]);
-        }
-        r = qmul_z(r, (float)c[i], (float)s[i]);
-        const float *l = L + 7 * (i + 1);
-        float ox, oy, oz;
-        pose::qrot(r, 1.0f, l[4], l[5], l[6], ox, oy, oz);
-        tx += ox; ty += oy; tz += oz;
-        r = pose::qmul(r, pose::Q{l[0], l[1], l[2], l[3]});
+        for (int k = 0; k < 21; ++k) A[k] += lane_d(A[k], src);
     }
     A[0] += lam2; A[2] += lam2; A[5] += lam2; A[9] += lam2; A[14] += lam2; A[20] += lam2;
 #pragma unroll
@@ -192,13 +174,12 @@ __device__ __forceinline__ void factor(const float *L, int n, const double *c, c
             double sum = A[ra + b];
 #pragma unroll
             for (int k = 0; k < b; ++k) sum = fma(-A[ra + k], A[rb + k], sum);
-            // the clamp keeps a singular undamped system finite (its rates are then huge)
             A[ra + b] = (a == b) ? rsqrt_d(fmax(sum, 1e-30)) : sum * A[rb + b];
         }
     }
 }
 
-// y <- (G G^T)^-1 y for the factor of factor()
+// y <- (G G^T)^-1 y for the factor of factor_cols()
 __device__ __forceinline__ void solve(const double *A, double *y)
 {
 #pragma unroll

@@ -218,6 +218,7 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
     // rotor and its angle; every lane holds the FP64 end-effector position and the start position
     const int my_j = lane / AW;
     double jc_own = 1.0, js_own = 0.0, q_own = 0.0;
+    float colj[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};     // this lane's column of J at the current joints
     double pdx = 0, pdy = 0, pdz = 0;
     float a0x = 0, a0y = 0, a0z = 0;
     if constexpr (ARM && !PROBE) {
@@ -226,7 +227,7 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
             sincos(0.5 * q_own, &js_own, &jc_own);
         }
         arm::QD r;
-        arm::fk_tree<AW>(pr.arm_links, pr.arm_n, a_w, my_j, jc_own, js_own, r, pdx, pdy, pdz);
+        arm::fk_scan<AW>(pr.arm_links, pr.arm_n, a_w, my_j, jc_own, js_own, r, pdx, pdy, pdz, colj);
         qr = pose::Q{(float)r.w, (float)r.x, (float)r.y, (float)r.z};
         px = (float)pdx; py = (float)pdy; pz = (float)pdz;
         a0x = px; a0y = py; a0z = pz;
@@ -341,7 +342,6 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
         float aLx = 0, aLy = 0, aLz = 0, jA = 0, jB = 0;
         pose::Q dq{1.f, 0.f, 0.f, 0.f};
         double Af[21];                      // arm agents: factor of J J^T + lambda^2 I
-        float colj[6];                      // arm agents: this lane's column of J
         auto pose_early = [&]() {
             float phx, phy, phz, tx, ty, tz, rx, ry, rz;
             pose::so3_log(pose::qmul(pose::Q{qr.w, -qr.x, -qr.y, -qr.z},
@@ -356,10 +356,9 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
             oy = fmaf(hr, fmaf(P.kr, phy, -P.dr * oy), oy);
             oz = fmaf(hr, fmaf(P.kr, phz, -P.dr * oz), oz);
             if constexpr (ARM) {
-                // J at the current joints and the factor of J J^T + lambda^2 I (Eq. 12)
-                double jc[arm::kMaxJoints], js[arm::kMaxJoints];
-                arm::gather<AW>(jc_own, js_own, a_w, jc, js);
-                arm::factor(pr.arm_links, pr.arm_n, jc, js, px, py, pz, pr.arm_lam2, my_j, Af, colj);
+                // the factor of J J^T + lambda^2 I at the current joints (Eq. 12), from the columns
+                // the last forward kinematics left on the joint lanes
+                arm::factor_cols<AW>(colj, pr.arm_lam2, Af);
             } else {
                 const float ax = pr.dt * ox, ay = pr.dt * oy, az = pr.dt * oz;
                 dq = pose::so3_exp(ax, ay, az);
@@ -505,7 +504,7 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
                     }
                     arm::QD r;
                     double tx, ty, tz;
-                    arm::fk_tree<AW>(pr.arm_links, pr.arm_n, a_w, my_j, jc_own, js_own, r, tx, ty, tz);
+                    arm::fk_scan<AW>(pr.arm_links, pr.arm_n, a_w, my_j, jc_own, js_own, r, tx, ty, tz, colj);
                     dx = (float)(tx - pdx); dy = (float)(ty - pdy); dz = (float)(tz - pdz);
                     pdx = tx; pdy = ty; pdz = tz;
                     px = (float)tx; py = (float)ty; pz = (float)tz;

@@ -2,15 +2,20 @@
 
   back_project(depth, K, T_wc)   pinhole back-projection and the camera-to-world
                                  transform (Sec. IV-B, V-A), FP64 from FP32 inputs
-  voxel_cells(x, y, z, ...)      occupied cells of the uniform voxel lattice of size
-                                 2 r_O (Sec. IV-B, V-A): cell = floor((p - lo) / voxel)
-                                 per axis, decided in FP32 as the library does (the
-                                 quantisation is an integer decision)
+  voxel_keys(x, y, z, ...)       lattice coordinates of points in the uniform voxel
+                                 lattice of size 2 r_O (Sec. IV-B, V-A): the exact
+                                 floor((p - lo) / voxel) of the real quotient of the given
+                                 coordinate, corner and voxel size (exact rationals where
+                                 an FP64 quotient cannot decide the floor)
+  voxel_cells(x, y, z, ...)      the occupied cells of that lattice
   voxel_centres(cells, ...)      the voxel-centre cloud lo + (k + 1/2) voxel (FP64)
   on_robot(x, y, z, spheres)     the robot self-filter of Sec. V-A: points within any
                                  of the robot's bounding spheres (an integer decision,
                                  taken in FP64 as the library takes it)
 """
+import math
+from fractions import Fraction
+
 import numpy as np
 
 
@@ -29,19 +34,37 @@ def back_project(depth, K, T_wc):
     return P
 
 
+def _exact_floor(p, lo, s):
+    """floor((p - lo) / s) of the exact real numbers that the floats p, lo, s denote."""
+    return math.floor((Fraction(float(p)) - Fraction(float(lo))) / Fraction(float(s)))
+
+
 def voxel_keys(x, y, z, voxel, lo, dims):
     """Integer cell coordinates [n, 3] and a validity mask (inside the box, finite).
 
-    The floor is taken of the FP32 quotient (p - lo) / voxel, each operation
-    correctly rounded in FP32, as the library computes it."""
-    P = np.stack([np.asarray(x, np.float32), np.asarray(y, np.float32), np.asarray(z, np.float32)], 1)
+    The cell of a coordinate p is floor((p - lo) / voxel) of the real numbers that
+    p (FP32 or FP64), lo and voxel (FP32) denote: the uniform lattice itself, with no
+    rounding.  The FP64 quotient decides the floor wherever it is farther from an
+    integer than its own rounding error (three roundings, relative 2^-53 each: far
+    below the 1e-9 relative margin used); the remaining coordinates are decided with
+    exact rationals."""
+    P = np.stack([np.asarray(x), np.asarray(y), np.asarray(z)], 1)
+    P = P.astype(np.float64) if P.dtype != np.float32 else P
     lo32 = np.asarray(lo, np.float32)
     s32 = np.float32(voxel)
-    with np.errstate(invalid="ignore"):
-        q = np.floor((P - lo32) / s32)
-        ok = np.isfinite(P).all(1) & (q >= 0).all(1) & (q < np.asarray(dims)).all(1)
     k = np.zeros(P.shape, np.int64)
-    k[ok] = q[ok].astype(np.int64)
+    fin = np.isfinite(P).all(1)
+    with np.errstate(invalid="ignore", over="ignore"):
+        q = (P.astype(np.float64) - lo32.astype(np.float64)) / np.float64(s32)
+        kf = np.floor(q)
+        amb = fin[:, None] & (np.abs(q - np.round(q)) <= 1e-9 * np.maximum(1.0, np.abs(q)))
+        big = fin[:, None] & (np.abs(q) < 2.0 ** 52)
+    k[big] = kf[big].astype(np.int64)
+    for i, a in zip(*np.nonzero(amb)):
+        k[i, a] = _exact_floor(P[i, a], lo32[a], s32)
+    d = np.asarray(dims, np.int64)
+    ok = fin & (np.abs(q) < 2.0 ** 52).all(1) & (k >= 0).all(1) & (k < d).all(1)
+    k[~ok] = 0
     return k, ok
 
 

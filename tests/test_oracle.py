@@ -124,6 +124,45 @@ def test_repulsion_linear_in_points():
     np.testing.assert_array_equal(r2.rho_min, r1.rho_min)
 
 
+def test_force_tolerance_terms_hand_placed():
+    """The two diagnostics that enter the per-step force tolerance, pinned on hand-placed
+    spheres around an agent at the origin moving along x with omega = z (r_O = r_a = 0,
+    so rho is the centre distance):
+      sum_j |f_j| counts every kept pair once, with |f_j| = k_f / rho_j for a current
+        perpendicular to w (and 0 where the current vanishes);
+      the edge terms count the pairs within 1e-6 r_d of the hard cut-off, on both sides
+        of it, with the force each would give if classified the other way;
+    pairs farther from the cut-off, and the whole edge band under the taper, add nothing."""
+    r_d = np.float32(0.1)
+    up = lambda x, n: [x := np.nextafter(x, np.float32(1.0)) for _ in range(n)][-1]
+    dn = lambda x, n: [x := np.nextafter(x, np.float32(0.0)) for _ in range(n)][-1]
+    r5, r6, r7 = up(r_d, 7), up(r_d, 41), dn(r_d, 7)     # 5.2e-7, 3.1e-6, -3.7e-7 relative to r_d
+    P = np.array([[0.0, 0.05, 0.0],        # inside, current perpendicular to w: |f| = k_f / rho
+                  [0.0, 0.0, 0.08],        # inside, n parallel to omega: no current, f = 0
+                  [0.0, -r_d, 0.0],        # exactly at rho = r_d: kept, in the edge band
+                  [0.2, 0.0, 0.0],         # beyond r_d
+                  [-r5, 0.0, 0.0],         # just beyond r_d, in the band (force 0, would be k_f / rho)
+                  [0.0, r6, 0.0],          # beyond r_d, outside the band
+                  [r7, 0.0, 0.0]],         # just inside r_d, in the band
+                 np.float32)
+    ag = _agents(1, k_f=KF, r_d=r_d, r_a=0.0, omega=[[0.0, 0.0, 1.0]])
+    rho = lambda i: float(np.linalg.norm(P[i].astype(np.float64)))
+    for cutoff in (0, 1):
+        pb = _problem_from_points(P, ag, [0, 0, 0], [1, 0, 0], r_obs=0.0, cutoff=cutoff)
+        r = oracle.repulsion(pb, [[0.0, 0.0, 0.0]], [[1.0, 0.0, 0.0]], 0.0)
+        assert r.rho_min[0] == rho(0)
+        kf = float(np.float32(KF))
+        if cutoff == 0:
+            kept = kf / rho(0) + kf / rho(2) + kf / rho(6)
+            np.testing.assert_allclose(r.force[0], [0.0, 0.0, kept], rtol=1e-12, atol=1e-18)
+            np.testing.assert_allclose(r.abs_sum[0], kept, rtol=1e-12)
+            np.testing.assert_allclose(r.edge_sum[0], kf / rho(2) + kf / rho(4) + kf / rho(6), rtol=1e-12)
+            assert r.edge_cnt[0] == 3
+        else:
+            assert r.edge_sum[0] == 0.0 and r.edge_cnt[0] == 0
+            assert r.abs_sum[0] >= abs(r.force[0, 2]) > 0.0
+
+
 def test_min_distance_matches_kdtree():
     """rho_min^(k) = max(nearest-centre distance - (r_O + r_a), eps): checked with scipy's k-d tree."""
     pb = scenes.config1()

@@ -48,14 +48,74 @@ def test_back_projection_plane_and_invalid():
     assert np.isnan(P[[0, 32 + 1, 64 + 2]]).all() and np.isfinite(P[3]).all()
 
 
+def _as_int(v, scale=1100):
+    """A float (FP32 or FP64) as the integer v * 2^scale, exactly (integer mantissa and
+    exponent from frexp; every finite float is an integer multiple of 2^-1074)."""
+    m, e = math.frexp(float(v))
+    mi = int(m * (1 << 53))                      # exact: m has at most 53 significant bits
+    sh = e - 53 + scale
+    return mi << sh if sh >= 0 else -((-mi) >> -sh) if mi < 0 else mi >> -sh
+
+
+def _int_floor(p, lo, s):
+    """floor((p - lo) / s) in integer arithmetic on the scaled values (Python // floors)."""
+    return (_as_int(p) - _as_int(lo)) // _as_int(s)
+
+
+def _face_points(lo, s, ks):
+    """FP32 coordinates at and around the faces lo + k s of a lattice: for each k the
+    FP32 values nearest the real face and 1 and 2 steps either side, each with the
+    cell that the position relative to the face fixes: k when at or above it, k - 1
+    below it (decided by an integer comparison of the scaled values)."""
+    lo, s = np.float32(lo), np.float32(s)
+    pts, want = [], []
+    for k in ks:
+        face = _as_int(lo) + k * _as_int(s)
+        c = np.float32(float(lo) + k * float(s))
+        for step in (-2, -1, 0, 1, 2):
+            p = c
+            for _ in range(abs(step)):
+                p = np.nextafter(p, np.float32(np.inf if step > 0 else -np.inf))
+            pts.append(p)
+            want.append(k if _as_int(p) >= face else k - 1)
+    return np.array(pts, np.float32), np.array(want)
+
+
+def test_voxel_keys_exact_at_faces():
+    """Cells of FP32 coordinates on and one or two FP32 steps either side of lattice
+    faces: a dyadic lattice (faces representable, points exactly on them) and the
+    config-3 lattice of 1 cm cells (faces between FP32 values).  The oracle's key is
+    the cell that the point's side of the face fixes; an FP32 quotient, floor(fl32(
+    fl32(p - lo) / s)), misplaces some of these points, so the check can tell them apart."""
+    fr = scenes.config3_frame(n_boxes=0, w=8, h=6)
+    lattices = [(-0.5, 2.0 ** -6, 64), (fr.box_lo[0], fr.voxel, fr.dims[0]), (fr.box_lo[2], fr.voxel, fr.dims[2]),
+                (0.0, fr.voxel, 100), (-0.0125, 0.003, 300)]
+    fp32_wrong = 0
+    for lo, s, dim in lattices:
+        p, want = _face_points(lo, s, range(0, dim, 1))
+        z = np.zeros_like(p)
+        k, ok = op.voxel_keys(p, z, z, s, [lo, -1.0, -1.0], [dim + 1, 1 << 20, 1 << 20])
+        inside = want >= 0
+        assert np.array_equal(ok, inside)
+        assert np.array_equal(k[inside, 0], want[inside]), (lo, s)
+        # integer arithmetic agrees as well (a second exact route)
+        assert all(_int_floor(a, np.float32(lo), np.float32(s)) == b for a, b in zip(p, want))
+        q32 = np.floor((p - np.float32(lo)) / np.float32(s)).astype(np.int64)
+        fp32_wrong += int((q32 != want).sum())
+    assert fp32_wrong > 0
+
+
 def test_voxel_bruteforce_small():
+    """Random FP32 points (and points pushed onto faces) against an integer-arithmetic
+    brute force of floor((p - lo) / s) per axis."""
     rng = np.random.default_rng(1)
-    s, lo, dims = 0.01, np.array([-0.05, -0.05, 0.0]), np.array([10, 10, 5])
+    s, lo, dims = np.float32(0.01), np.array([-0.05, -0.05, 0.0], np.float32), np.array([10, 10, 5])
     P = rng.uniform([-0.06, -0.06, -0.01], [0.06, 0.06, 0.06], (500, 3)).astype(np.float32)
+    P[:40, 0] = [np.float32(float(lo[0]) + k * float(s)) for k in range(40)]     # nearest FP32 to faces
     cells = op.voxel_cells(P[:, 0], P[:, 1], P[:, 2], s, lo, dims)
     expect = set()
-    for p in P.astype(np.float64):
-        k = [math.floor(float(np.float32((np.float32(p[a]) - np.float32(lo[a])) / np.float32(s)))) for a in range(3)]
+    for p in P:
+        k = [_int_floor(p[a], lo[a], s) for a in range(3)]
         if all(0 <= k[a] < dims[a] for a in range(3)):
             expect.add((k[2] * dims[1] + k[1]) * dims[0] + k[0])
     assert list(cells) == sorted(expect)

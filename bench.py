@@ -177,13 +177,31 @@ def perception_pass(ctx, dev, reps=20):
         t_bp += e[0].elapsed_time(e[1])
         t_vx += e[1].elapsed_time(e[2])
     nv = int(vox[3].item())
+    # the fused pass: depth frame straight to voxel centres (no points in memory)
+    d1 = d.unsqueeze(0).contiguous()
+    T1 = torch.as_tensor(fr.T_wc[None].copy(), device=dev)
+    for _ in range(3):
+        ctx.depth_to_voxels(d1, fr.K, T1, fr.voxel, fr.box_lo, fr.dims, capacity=cap, out=vox)
+    torch.cuda.synchronize()
+    t_fu = []
+    for _ in range(reps):
+        e[0].record()
+        ctx.depth_to_voxels(d1, fr.K, T1, fr.voxel, fr.box_lo, fr.dims, capacity=cap, out=vox)
+        e[1].record()
+        torch.cuda.synchronize()
+        t_fu.append(e[0].elapsed_time(e[1]))
+    assert int(vox[3].item()) == nv
     bp_bytes = 4 * n + 12 * n
     vx_bytes = 12 * n + 12 * nv
+    fu_bytes = 4 * n + 12 * nv
+    t_f = sum(t_fu) / reps
     res = {"frame": "640x480 z-depth, 20 boxes on a plane, 1 cm voxels", "points": n, "voxels": nv,
            "depth_to_points_ms": t_bp / reps, "voxel_downsample_ms": t_vx / reps,
            "depth_to_points_GBps": bp_bytes / (t_bp / reps * 1e-3) / 1e9,
            "voxel_downsample_GBps": vx_bytes / (t_vx / reps * 1e-3) / 1e9,
-           "bytes_note": "algorithmic: depth 4 B + points 12 B per pixel; points 12 B per point + centres 12 B"}
+           "fused_depth_to_voxels_ms": t_f, "fused_depth_to_voxels_GBps": fu_bytes / (t_f * 1e-3) / 1e9,
+           "bytes_note": "algorithmic: depth 4 B + points 12 B per pixel; points 12 B per point + centres 12 B; "
+                         "fused: depth 4 B per pixel + centres 12 B"}
     # multi-view: B frames from B poses in one launch, then one fused voxel pass; the sweep
     # over B shows the launch-bound regime give way to the HBM-bound one
     def multiview(B):
@@ -210,17 +228,71 @@ def perception_pass(ctx, dev, reps=20):
             t_vx.append(e[1].elapsed_time(e[2]))
         nvb = int(voxb[3].item())
         assert nvb <= capb
-        tb, tv = min(t_bp), min(t_vx)
+        t_fu = []
+        for _ in range(5):
+            e[0].record()
+            ctx.depth_to_voxels(db, fr.K, T, fr.voxel, fr.box_lo, fr.dims, capacity=capb, out=voxb)
+            e[1].record()
+            torch.cuda.synchronize()
+            t_fu.append(e[0].elapsed_time(e[1]))
+        assert int(voxb[3].item()) == nvb
+        tb, tv, tf = min(t_bp), min(t_vx), min(t_fu)
         del db, ptsb, voxb
         return {"frames": B, "points": nb, "fused_voxels": nvb, "depth_to_points_ms": tb,
-                "voxel_downsample_ms": tv,
+                "voxel_downsample_ms": tv, "fused_depth_to_voxels_ms": tf,
                 "depth_to_points_GBps": 16 * nb / (tb * 1e-3) / 1e9,
-                "voxel_downsample_GBps": (12 * nb + 12 * nvb) / (tv * 1e-3) / 1e9}
+                "voxel_downsample_GBps": (12 * nb + 12 * nvb) / (tv * 1e-3) / 1e9,
+                "fused_depth_to_voxels_GBps": (4 * nb + 12 * nvb) / (tf * 1e-3) / 1e9}
     sweep = [multiview(B) for B in (1, 4, 16, 64, 256)]
     res["multiview"] = dict(sweep[3], hbm_peak_GBps=8000.0)
-    res["multiview_sweep"] = [{k: m[k] for k in ("frames", "depth_to_points_GBps", "voxel_downsample_GBps")}
-                              for m in sweep]
+    res["multiview_sweep"] = [{k: m[k] for k in ("frames", "depth_to_points_GBps", "voxel_downsample_GBps",
+                                                 "fused_depth_to_voxels_GBps")} for m in sweep]
     return res
+
+
+def perception_to_plan(ctx, dev, reps=10):
+    """Config 3 end to end on one stream with no host sync: the 640x480 depth frame ->
+    1 cm voxel centres (fused pass, count on the device) -> the rollout of 256 agents
+    over 1,000 steps on them -> i*.  HIP events around each part."""
+    import torch
+    from paper_2606_12579_amd import gmapp, scenes
+    fr = scenes.config3_frame()
+    d = torch.as_tensor(fr.depth[None].copy(), device=dev)
+    T = torch.as_tensor(fr.T_wc[None].copy(), device=dev)
+    cap = 32768
+    vox = tuple(torch.empty(cap, dtype=torch.float32, device=dev) for _ in range(3)) + \
+        (torch.zeros(1, dtype=torch.int64, device=dev),)
+    agents, q, prm = scenes.config3_agents(n_agents=256, n_steps=1000)
+    sc = gmapp.DeviceScene(vox[0], vox[1], vox[2], scenes.R_OBS, n_points_dev=vox[3])
+    ag = gmapp.agents_to_device(agents, dev)
+    ctx.clear_tiling()
+    outs = None
+
+    def once():
+        nonlocal outs
+        ctx.depth_to_voxels(d, fr.K, T, fr.voxel, fr.box_lo, fr.dims, capacity=cap, out=vox)
+        e[1].record()
+        outs = ctx.rollout(sc, ag, q, prm, traj=False, min_clear=False, out=outs)
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    for _ in range(3):
+        once()
+    torch.cuda.synchronize()
+    tot, perc = [], []
+    for _ in range(reps):
+        e[0].record()
+        once()
+        e[2].record()
+        torch.cuda.synchronize()
+        tot.append(e[0].elapsed_time(e[2]))
+        perc.append(e[0].elapsed_time(e[1]))
+    nv = int(vox[3].item())
+    best = int(outs["best"].item())
+    ms = sorted(tot)[len(tot) // 2]
+    inter = 256 * 1000 * nv
+    return {"workload": "config 3: 640x480 depth frame -> 1 cm voxels -> 256 agents x 1,000 steps -> i*",
+            "voxels": nv, "best": best, "depth_to_best_ms_median": ms, "depth_to_best_ms_min": min(tot),
+            "perception_ms_median": sorted(perc)[len(perc) // 2],
+            "rollout_interactions_per_s": inter / ((ms - sorted(perc)[len(perc) // 2]) * 1e-3)}
 
 
 def adjoint_pass(ctx, dev, reps=3):
@@ -572,6 +644,7 @@ def main():
         res["closed_loop"] = closed_loop(ctx, dev)
     if not args.no_perception:
         res["perception"] = perception_pass(ctx, dev)
+        res["perception_to_plan"] = perception_to_plan(ctx, dev)
     if not args.no_adjoint:
         res["adjoint"] = adjoint_pass(ctx, dev)
     if not args.no_batch:

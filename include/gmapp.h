@@ -40,7 +40,7 @@ typedef int32_t gmapp_status;
 #define GMAPP_ENOMEM (-2)     /* workspace or device memory exhausted */
 #define GMAPP_EDEVICE (-3)    /* no usable device, or a HIP runtime error */
 #define GMAPP_ECAPACITY (-4)  /* request exceeds a fixed capacity (grid residency, output capacity) */
-#define GMAPP_ETIMEOUT (-5)   /* deadline passed, or the in-kernel watchdog fired */
+#define GMAPP_ETIMEOUT (-5)   /* deadline passed, or an exchange wait stalled past the watchdog */
 #define GMAPP_ECANCELLED (-6) /* request cancelled */
 
 typedef struct gmapp_ctx gmapp_ctx;
@@ -124,8 +124,11 @@ typedef struct {
 /* Outputs (device).  traj[i][k] = p^(k+1) for k = 0..N_k (N_k + 1 poses);
  * cost[i] = {C_goal, C_obs, C_path, C_smooth, C_total}; min_clear[i][k] =
  * rho_min^(k+1), the smallest clamped surface distance at step k+1 (+inf when the
- * scene is empty); best[0] = i*, or -1 when N_a = 0, or GMAPP_ETIMEOUT when the
- * in-kernel watchdog aborted the rollout.  traj and min_clear may be NULL. */
+ * scene is empty); best[0] = i*, or -1 when N_a = 0, or GMAPP_ETIMEOUT when an
+ * exchange wait of a sharded launch stalled past the watchdog limit
+ * (gmapp_set_watchdog), or GMAPP_ECANCELLED when the host's abort word ended it
+ * (gmapp_abort, gmapp_wait); the other outputs of such a launch are undefined.
+ * traj and min_clear may be NULL. */
 typedef struct {
     float *traj;      /* device [N_a][N_k + 1][3] or NULL */
     float *cost;      /* device [N_a][5] */
@@ -269,6 +272,25 @@ typedef struct {
     int32_t tile_points, layout;
     int32_t group; /* 0 choose, 1 wavefront, 2 workgroup */
 } gmapp_tiling;
+/* Failure handling of the persistent launches (no passage of the paper: the one
+ * failure rule it has is the perception buffer's frame time-out, Sec. V-A).  A
+ * sharded rollout, adjoint or control launch exchanges partial sums between
+ * workgroups every step; each exchange wait is bounded:
+ *  - gmapp_set_watchdog: the longest a single wait may go without its words
+ *    arriving (seconds; 0 = the default 4 s; EINVAL outside (0, 3600]).  The clock
+ *    restarts with every wait, so a long launch is never cut short while it makes
+ *    progress.  A stalled wait ends the launch: best = GMAPP_ETIMEOUT, gradients NaN.
+ *  - gmapp_abort(raise = 1): raises the context's abort word, a pinned host word the
+ *    waits poll; every wait of the running and of later launches on this context
+ *    then ends (best = GMAPP_ECANCELLED, gradients NaN) until gmapp_abort(raise = 0).
+ *    May be called from any host thread while a launch runs.
+ *  - gmapp_wait: waits up to timeout_s seconds for `stream`; past that it raises the
+ *    abort word, waits for the launches to drain, lowers it again and returns
+ *    GMAPP_ETIMEOUT.  A launch that never waits (one shard) runs to its end. */
+gmapp_status gmapp_set_watchdog(gmapp_ctx *ctx, double seconds);
+gmapp_status gmapp_abort(gmapp_ctx *ctx, int32_t raise);
+gmapp_status gmapp_wait(gmapp_ctx *ctx, void *stream, double timeout_s);
+
 /* Force a tiling for later rollouts on this context (NULL restores the automatic choice). */
 gmapp_status gmapp_set_tiling(gmapp_ctx *ctx, const gmapp_tiling *tiling);
 /* The tiling gmapp_rollout would use for this problem shape. */
@@ -469,15 +491,20 @@ gmapp_status gmapp_depth_to_points_batch(gmapp_ctx *ctx, const float *depth, int
                                          void *stream);
 
 /* Uniform voxel lattice of the sphere world (Sec. IV-B; voxel size 2 r_O in
- * Sec. V-A, voxel-centre clouds): the cell of a point is floor((p - lo) / voxel)
- * per axis (FP32); points outside the box lo + [0, dims * voxel) or non-finite are
- * dropped (the workspace bounding-box filter).  Every cell holding at least
- * min_count points (>= 1; larger values filter sensing artifacts) contributes its
- * centre lo + (k + 1/2) voxel.  Centres are written to ox, oy, oz (device
- * [capacity]) in increasing linear cell index (x fastest, then y, then z); the
- * number of occupied cells goes to n_out_dev (device int64 [1]), even when it
- * exceeds capacity (then only the first `capacity` centres are written).  Uses
- * 4 bytes of context workspace per cell.  x, y, z: device [n]. */
+ * Sec. V-A, voxel-centre clouds): the cell of a point is the exact lattice
+ * coordinate floor((p - lo) / voxel) per axis of the real values of the FP32
+ * inputs p, lo and voxel (no rounding of the quotient decides it); points outside
+ * the box lo + [0, dims * voxel) or non-finite are dropped (the workspace
+ * bounding-box filter).  Every cell holding at least min_count points (>= 1;
+ * larger values filter sensing artifacts) contributes its centre
+ * lo + (k + 1/2) voxel, rounded to FP32.  Centres are written to ox, oy, oz
+ * (device [capacity]) in increasing linear cell index (x fastest, then y, then z);
+ * the number of occupied cells goes to n_out_dev (device int64 [1]), even when it
+ * exceeds capacity (then only the first `capacity` centres are written).
+ * The context keeps a grid over the box (1 bit per cell for min_count = 1,
+ * 4 bytes per cell otherwise), allocated by the first call that needs a larger
+ * one (a device allocation, ENOMEM if it fails) and freed by gmapp_destroy.
+ * x, y, z: device [n]. */
 gmapp_status gmapp_voxel_downsample(gmapp_ctx *ctx, const float *x, const float *y, const float *z, int64_t n,
                                     float voxel, const float lo[3], const int32_t dims[3], int32_t min_count,
                                     float *ox, float *oy, float *oz, int64_t capacity, int64_t *n_out_dev,
@@ -496,6 +523,21 @@ gmapp_status gmapp_voxel_downsample_filtered(gmapp_ctx *ctx, const float *x, con
                                              int32_t min_count, const float *robot_spheres, int32_t n_spheres,
                                              float *ox, float *oy, float *oz, int64_t capacity, int64_t *n_out_dev,
                                              void *stream);
+
+/* Depth frames straight to the voxel-centre cloud (Sec. IV-B / V-A: coordinate
+ * transform, robot self-filter and voxel lattice in one pass): every pixel is
+ * back-projected exactly as gmapp_depth_to_points_batch does it (the same FP32
+ * operations, so the same point) and its cell marked without writing the point
+ * to memory.  The result equals gmapp_depth_to_points_batch followed by
+ * gmapp_voxel_downsample_filtered on its n_frames w h points, bit for bit.
+ * depth: device [n_frames][h][w]; K = {f_x, f_y, c_x, c_y} (host); T_wc: device
+ * [n_frames][12]; lattice, self-filter, outputs and errors as
+ * gmapp_voxel_downsample_filtered (robot_spheres may be NULL with n_spheres 0). */
+gmapp_status gmapp_depth_to_voxels(gmapp_ctx *ctx, const float *depth, int32_t n_frames, int32_t w, int32_t h,
+                                   const float K[4], const float *T_wc, float voxel, const float lo[3],
+                                   const int32_t dims[3], int32_t min_count, const float *robot_spheres,
+                                   int32_t n_spheres, float *ox, float *oy, float *oz, int64_t capacity,
+                                   int64_t *n_out_dev, void *stream);
 
 #ifdef __cplusplus
 }

@@ -57,13 +57,13 @@ def voxel_keys(x, y, z, voxel, lo, dims):
     with np.errstate(invalid="ignore", over="ignore"):
         q = (P.astype(np.float64) - lo32.astype(np.float64)) / np.float64(s32)
         kf = np.floor(q)
-        amb = fin[:, None] & (np.abs(q - np.round(q)) <= 1e-9 * np.maximum(1.0, np.abs(q)))
-        big = fin[:, None] & (np.abs(q) < 2.0 ** 52)
-    k[big] = kf[big].astype(np.int64)
+        small = fin[:, None] & (np.abs(q) < 2.0 ** 52)      # beyond that no grid reaches: outside
+        amb = small & (np.abs(q - np.round(q)) <= 1e-9 * np.maximum(1.0, np.abs(q)))
+    k[small] = kf[small].astype(np.int64)
     for i, a in zip(*np.nonzero(amb)):
         k[i, a] = _exact_floor(P[i, a], lo32[a], s32)
     d = np.asarray(dims, np.int64)
-    ok = fin & (np.abs(q) < 2.0 ** 52).all(1) & (k >= 0).all(1) & (k < d).all(1)
+    ok = fin & small.all(1) & (k >= 0).all(1) & (k < d).all(1)
     k[~ok] = 0
     return k, ok
 

@@ -229,7 +229,7 @@ __global__ __launch_bounds__(64 * W) void k_adjoint(Scn sc, Agt ag, Prm pr, AdjO
     const int N = pr.n_steps, C = lay.C;
     int par = 0;
     unsigned ev = 0;                              // exchange tag: one per reduction, the same sequence in all shards
-    const unsigned long long t_start = __builtin_amdgcn_s_memrealtime();
+    bool failed = false;                          // a wait was cut short: later waits are skipped (gradients NaN)
 
     // workgroup reduction: sum of up to 3 float4 and the nearest sphere (m2, d)
     auto wg_reduce = [&](float4 *v, int nsum, float &m2, float &mx, float &my, float &mz) {
@@ -277,21 +277,25 @@ __global__ __launch_bounds__(64 * W) void k_adjoint(Scn sc, Agt ag, Prm pr, AdjO
                 for (int l = lane; l < S * AW; l += 64) {
                     const unsigned long long *slot =
                         xc.partial + (((size_t)((tag & 1) * G + g) * S + l / AW) * AW + l % AW) * kAdjWords;
-                    unsigned long long q[kAdjWords];
+                    unsigned long long q[kAdjWords] = {};
                     unsigned spins = 0;
-                    while (true) {                   // all words of the slot in flight together
+                    const bool probe_abort = xc.abort && !failed && (tag % kAbortPeriod) == 0;
+                    const unsigned ab = probe_abort ? ld_system(xc.abort) : 0u;
+                    const unsigned long long t_wait = __builtin_amdgcn_s_memrealtime();
+                    while (!failed) {                // all words of the slot in flight together
                         bool all = true;
                         for (int i = 0; i < nw; ++i) q[i] = ld64_agent(slot + i);
                         for (int i = 0; i < nw; ++i) all = all && xtag(q[i]) == tag;
                         if (all) break;
                         __builtin_amdgcn_s_sleep(2);
-                        if ((++spins & 63u) == 0) {
-                            if (ld_agent(xc.status) != 0u) break;
-                            if (__builtin_amdgcn_s_memrealtime() - t_start > kWatchdogTicks) {
-                                st_agent(xc.status, 1u);
-                                break;
-                            }
+                        if (wait_expired(xc, t_wait, ++spins)) {
+                            failed = true;
+                            break;
                         }
+                    }
+                    if (ab != 0u) {                  // the host's abort word
+                        st_agent(xc.status, 2u);
+                        failed = true;
                     }
                     for (int i = 0; i < nsum + 1; ++i)
                         xt[l * 4 + i] = make_float4(xval(q[4 * i]), xval(q[4 * i + 1]), xval(q[4 * i + 2]),
@@ -553,7 +557,7 @@ __global__ __launch_bounds__(64 * W) void k_adjoint(Scn sc, Agt ag, Prm pr, AdjO
         __syncthreads();                           // the tape is rewritten by the next segment
     }
     if (writer && valid) {
-        const bool bad = S > 1 && ld_agent(xc.status) != 0u;   // the watchdog cut an exchange short
+        const bool bad = S > 1 && ld_agent(xc.status) != 0u;   // an exchange wait was cut short
         io.g_ka[agent] = bad ? NAN : gka;
         io.g_da[agent] = bad ? NAN : gda;
         io.g_kf[agent] = bad ? NAN : gkf;
@@ -652,13 +656,7 @@ gmapp_status launch_adjoint(gmapp_ctx *ctx, const Scn &sc, const Agt &ag, const 
         return fail(ctx, GMAPP_ECAPACITY, "checkpoints of %d steps x %d segments exceed LDS; raise ckpt_every",
                     ckpt_every, lay.n_ckpt);
     const size_t shm = adj_plan(lay, W, AW, S).total;
-    Xch xc;
-    xc.partial = ctx->xchg;
-    xc.flags = ctx->sync;
-    xc.done = ctx->sync + kCounterWords;
-    xc.status = ctx->sync + kCounterWords + 16;
-    xc.S = S;
-    xc.G = G;
+    Xch xc = make_xch(ctx, S, G);
     void *args[] = {(void *)&sc, (void *)&ag, (void *)&pr, (void *)&io, (void *)&lay, (void *)&xc};
     GM_HIP(ctx, hipFuncSetAttribute(reinterpret_cast<const void *>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
                                     (int)shm));

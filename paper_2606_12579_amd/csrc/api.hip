@@ -3,9 +3,11 @@
 #include "gmapp_internal.h"
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <thread>
 
 using gm::fail;
 
@@ -146,6 +148,30 @@ gm::Tiling tiling_for(gmapp_ctx *ctx, long long n_points, int n_agents, int n_st
     return t;
 }
 
+// lattice and self-filter arguments of the voxel pass
+gmapp_status voxel_grid(gmapp_ctx *ctx, float voxel, const float lo[3], const int32_t dims[3], int32_t min_count,
+                        const float *robot_spheres, int32_t n_spheres, gm::VoxGrid &g)
+{
+    if (!lo || !dims) return fail(ctx, GMAPP_EINVAL, "lo and dims must be non-NULL");
+    if (!finite(voxel) || voxel <= 0.f) return fail(ctx, GMAPP_EINVAL, "voxel must be finite and > 0");
+    if (min_count < 1) return fail(ctx, GMAPP_EINVAL, "min_count must be >= 1");
+    if (n_spheres < 0 || (n_spheres > 0 && !robot_spheres))
+        return fail(ctx, GMAPP_EINVAL, "n_spheres must be >= 0, with robot_spheres non-NULL when > 0");
+    g.voxel = voxel;
+    g.excl = n_spheres > 0 ? robot_spheres : nullptr;
+    g.n_excl = n_spheres;
+    long long cells = 1;
+    for (int a = 0; a < 3; ++a) {
+        if (!finite(lo[a])) return fail(ctx, GMAPP_EINVAL, "lo must be finite");
+        if (dims[a] < 1) return fail(ctx, GMAPP_EINVAL, "dims must be >= 1");
+        g.lo[a] = lo[a];
+        g.dims[a] = dims[a];
+        cells *= dims[a];
+        if (cells > (1ll << 31)) return fail(ctx, GMAPP_ECAPACITY, "voxel grid exceeds 2^31 cells");
+    }
+    return GMAPP_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -179,8 +205,27 @@ gmapp_status gmapp_create(int32_t device, size_t workspace_bytes, gmapp_ctx **ou
     ctx->xchg = reinterpret_cast<unsigned long long *>(ctx->arena + sync_bytes);
     ctx->scratch = ctx->arena + fixed;
     ctx->scratch_bytes = workspace_bytes - fixed;
+    // the host's abort word: pinned, coherent and mapped, so that a running kernel's waits see a
+    // host store without any copy
+    void *hw = nullptr;
+    if (hipHostMalloc(&hw, 64, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
+        (void)hipFree(p);
+        delete ctx;
+        return GMAPP_ENOMEM;
+    }
+    *static_cast<volatile unsigned *>(hw) = 0u;
+    ctx->abort_host = static_cast<unsigned *>(hw);
+    void *dw = nullptr;
+    if (hipHostGetDevicePointer(&dw, hw, 0) != hipSuccess) {
+        (void)hipHostFree(hw);
+        (void)hipFree(p);
+        delete ctx;
+        return GMAPP_EDEVICE;
+    }
+    ctx->abort_word = static_cast<unsigned *>(dw);
     hipLaunchKernelGGL(k_fill_u32, dim3(256), dim3(256), 0, nullptr, ctx->sync, fixed / sizeof(unsigned), 0u);
     if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+        (void)hipHostFree(hw);
         (void)hipFree(p);
         delete ctx;
         return GMAPP_EDEVICE;
@@ -195,7 +240,10 @@ void gmapp_destroy(gmapp_ctx *ctx)
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
     if (ctx->arena) (void)hipFree(ctx->arena);
+    if (ctx->vgrid) (void)hipFree(ctx->vgrid);
+    if (ctx->vbsum) (void)hipFree(ctx->vbsum);
     if (ctx->tab_host) (void)hipHostFree(ctx->tab_host);
+    if (ctx->abort_host) (void)hipHostFree(ctx->abort_host);
     if (ctx->tab_copied) (void)hipEventDestroy(ctx->tab_copied);
     delete ctx;
 }
@@ -204,6 +252,45 @@ const char *gmapp_last_error(const gmapp_ctx *ctx)
 {
     if (!ctx) return "no context";
     return ctx->err.c_str();
+}
+
+gmapp_status gmapp_set_watchdog(gmapp_ctx *ctx, double seconds)
+{
+    if (!ctx) return GMAPP_EINVAL;
+    if (seconds == 0.0) seconds = 4.0;
+    if (!std::isfinite(seconds) || seconds < 0.0 || seconds > 3600.0)
+        return fail(ctx, GMAPP_EINVAL, "watchdog limit must be in (0, 3600] s (0 = the default 4 s)");
+    ctx->watchdog_ticks = std::max<unsigned long long>(1ull, (unsigned long long)(seconds * 1e8));
+    return GMAPP_OK;
+}
+
+gmapp_status gmapp_abort(gmapp_ctx *ctx, int32_t raise)
+{
+    if (!ctx || !ctx->abort_host) return GMAPP_EINVAL;
+    __atomic_store_n(ctx->abort_host, raise ? 1u : 0u, __ATOMIC_SEQ_CST);
+    return GMAPP_OK;
+}
+
+gmapp_status gmapp_wait(gmapp_ctx *ctx, void *stream_, double timeout_s)
+{
+    gmapp_status st = check_ctx(ctx);
+    if (st) return st;
+    if (!(timeout_s >= 0.0)) return fail(ctx, GMAPP_EINVAL, "timeout must be >= 0");
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    const auto t0 = std::chrono::steady_clock::now();
+    while (true) {
+        const hipError_t e = hipStreamQuery(stream);
+        if (e == hipSuccess) return GMAPP_OK;
+        if (e != hipErrorNotReady) return gm::hip_fail(ctx, e, "hipStreamQuery");
+        if (std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() > timeout_s) break;
+        std::this_thread::sleep_for(std::chrono::microseconds(50));
+    }
+    // out of time: raise the abort word so that every exchange wait ends, drain, lower it
+    __atomic_store_n(ctx->abort_host, 1u, __ATOMIC_SEQ_CST);
+    const hipError_t e = hipStreamSynchronize(stream);
+    __atomic_store_n(ctx->abort_host, 0u, __ATOMIC_SEQ_CST);
+    if (e != hipSuccess) return gm::hip_fail(ctx, e, "hipStreamSynchronize");
+    return fail(ctx, GMAPP_ETIMEOUT, "stream work did not finish within %.3f s; its launches were aborted", timeout_s);
 }
 
 gmapp_status gmapp_set_tiling(gmapp_ctx *ctx, const gmapp_tiling *t)
@@ -452,26 +539,38 @@ gmapp_status gmapp_voxel_downsample_filtered(gmapp_ctx *ctx, const float *x, con
     if (n > 0 && (!x || !y || !z)) return fail(ctx, GMAPP_EINVAL, "input points must be non-NULL");
     if (capacity > 0 && (!ox || !oy || !oz)) return fail(ctx, GMAPP_EINVAL, "output arrays must be non-NULL");
     if (!n_out_dev) return fail(ctx, GMAPP_EINVAL, "n_out_dev must be non-NULL");
-    if (!lo || !dims) return fail(ctx, GMAPP_EINVAL, "lo and dims must be non-NULL");
-    if (!finite(voxel) || voxel <= 0.f) return fail(ctx, GMAPP_EINVAL, "voxel must be finite and > 0");
-    if (min_count < 1) return fail(ctx, GMAPP_EINVAL, "min_count must be >= 1");
-    if (n_spheres < 0 || (n_spheres > 0 && !robot_spheres))
-        return fail(ctx, GMAPP_EINVAL, "n_spheres must be >= 0, with robot_spheres non-NULL when > 0");
     gm::VoxGrid g;
-    g.voxel = voxel;
-    g.excl = n_spheres > 0 ? robot_spheres : nullptr;
-    g.n_excl = n_spheres;
-    long long cells = 1;
-    for (int a = 0; a < 3; ++a) {
-        if (!finite(lo[a])) return fail(ctx, GMAPP_EINVAL, "lo must be finite");
-        if (dims[a] < 1) return fail(ctx, GMAPP_EINVAL, "dims must be >= 1");
-        g.lo[a] = lo[a];
-        g.dims[a] = dims[a];
-        cells *= dims[a];
-        if (cells > (1ll << 31)) return fail(ctx, GMAPP_ECAPACITY, "voxel grid exceeds 2^31 cells");
-    }
-    return gm::launch_voxel_downsample(ctx, x, y, z, n, g, (unsigned)min_count, ox, oy, oz, capacity,
+    if ((st = voxel_grid(ctx, voxel, lo, dims, min_count, robot_spheres, n_spheres, g))) return st;
+    return gm::launch_voxel_downsample(ctx, x, y, z, n, nullptr, g, (unsigned)min_count, ox, oy, oz, capacity,
                                        reinterpret_cast<long long *>(n_out_dev), static_cast<hipStream_t>(stream));
+}
+
+gmapp_status gmapp_depth_to_voxels(gmapp_ctx *ctx, const float *depth, int32_t n_frames, int32_t w, int32_t h,
+                                   const float K[4], const float *T_wc, float voxel, const float lo[3],
+                                   const int32_t dims[3], int32_t min_count, const float *robot_spheres,
+                                   int32_t n_spheres, float *ox, float *oy, float *oz, int64_t capacity,
+                                   int64_t *n_out_dev, void *stream)
+{
+    gmapp_status st = check_ctx(ctx);
+    if (st) return st;
+    if (w < 0 || h < 0 || n_frames < 0) return fail(ctx, GMAPP_EINVAL, "image size and frame count must be >= 0");
+    if ((long long)w * h * n_frames > (1ll << 40)) return fail(ctx, GMAPP_ECAPACITY, "more than 2^40 pixels");
+    if ((long long)w * h > (long long)INT32_MAX) return fail(ctx, GMAPP_ECAPACITY, "image exceeds 2^31 - 1 pixels");
+    if (!K) return fail(ctx, GMAPP_EINVAL, "K must be non-NULL");
+    for (int i = 0; i < 4; ++i)
+        if (!finite(K[i])) return fail(ctx, GMAPP_EINVAL, "intrinsics must be finite");
+    if (K[0] == 0.f || K[1] == 0.f) return fail(ctx, GMAPP_EINVAL, "focal lengths must be non-zero");
+    const long long n = (long long)w * h * n_frames;
+    if (n > 0 && (!depth || !T_wc)) return fail(ctx, GMAPP_EINVAL, "depth and poses must be non-NULL");
+    if (capacity < 0) return fail(ctx, GMAPP_EINVAL, "capacity must be >= 0");
+    if (capacity > 0 && (!ox || !oy || !oz)) return fail(ctx, GMAPP_EINVAL, "output arrays must be non-NULL");
+    if (!n_out_dev) return fail(ctx, GMAPP_EINVAL, "n_out_dev must be non-NULL");
+    gm::VoxGrid g;
+    if ((st = voxel_grid(ctx, voxel, lo, dims, min_count, robot_spheres, n_spheres, g))) return st;
+    gm::Cam cam{K[0], K[1], K[2], K[3], w, h, n_frames, T_wc};
+    return gm::launch_voxel_downsample(ctx, depth, nullptr, nullptr, n, &cam, g, (unsigned)min_count, ox, oy, oz,
+                                       capacity, reinterpret_cast<long long *>(n_out_dev),
+                                       static_cast<hipStream_t>(stream));
 }
 
 gmapp_status gmapp_rollout_backward(gmapp_ctx *ctx, const gmapp_scene *scene, const gmapp_agents *agents,

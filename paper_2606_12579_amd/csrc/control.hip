@@ -175,7 +175,6 @@ __global__ __launch_bounds__(kCtlThreads) void k_control(Scn sc, Agt ag, Prm pr,
     const float gx = pr.goal[0], gy = pr.goal[1], gz = pr.goal[2];
     const float h = 0.5f * c.dt * pr.inv_mass;
     const int iters = c.steps > 0 ? c.steps : 1;
-    const unsigned long long t_start = __builtin_amdgcn_s_memrealtime();
     bool failed = false;
     for (int j = 0; j < iters && !failed; ++j) {
         const float t = fmaf((float)j, c.dt, c.t0);
@@ -204,6 +203,9 @@ __global__ __launch_bounds__(kCtlThreads) void k_control(Scn sc, Agt ag, Prm pr,
                 unsigned long long q0 = 0, q1 = 0, q2 = 0, q3 = 0;
                 const bool poller = lane < NG;
                 unsigned spins = 0;
+                const bool probe_abort = xc.abort && (tag % kAbortPeriod) == 0;
+                const unsigned ab = probe_abort ? ld_system(xc.abort) : 0u;
+                const unsigned long long t_wait = __builtin_amdgcn_s_memrealtime();
                 while (true) {
                     if (poller) {
                         const unsigned long long *slot = area + 4 * lane;
@@ -213,14 +215,14 @@ __global__ __launch_bounds__(kCtlThreads) void k_control(Scn sc, Agt ag, Prm pr,
                     const bool mine = !poller || (xtag(q0) == tag && xtag(q1) == tag && xtag(q2) == tag &&
                                                   xtag(q3) == tag);
                     if (__all(mine)) break;
-                    if ((++spins & 63u) == 0) {
-                        if (ld_agent(xc.status) != 0u ||
-                            __builtin_amdgcn_s_memrealtime() - t_start > kWatchdogTicks) {
-                            if (lane == 0) st_agent(xc.status, 1u);
-                            failed = true;
-                            break;
-                        }
+                    if (wait_expired(xc, t_wait, ++spins)) {
+                        failed = true;
+                        break;
                     }
+                }
+                if (ab != 0u) {                      // the host's abort word
+                    if (lane == 0) st_agent(xc.status, 2u);
+                    failed = true;
                 }
                 float sx = poller ? xval(q0) : 0.f, sy = poller ? xval(q1) : 0.f;
                 float sz = poller ? xval(q2) : 0.f, sm = poller ? xval(q3) : INFINITY;
@@ -308,13 +310,7 @@ gmapp_status launch_control(gmapp_ctx *ctx, const Scn &sc, const Agt &ag, const 
     Ctl c_ = c;
     c_.staged = (shm > 0 && shm <= kCtlLdsBytes) ? 1 : 0;
     const unsigned dyn = c_.staged ? (unsigned)shm : 0u;
-    Xch xc;
-    xc.partial = ctx->xchg;
-    xc.flags = ctx->sync;
-    xc.done = ctx->sync + kCounterWords;
-    xc.status = ctx->sync + kCounterWords + 16;
-    xc.S = NG;
-    xc.G = 1;
+    Xch xc = make_xch(ctx, NG, 1);
     const void *fn = pr.cutoff ? reinterpret_cast<const void *>(k_control<1>)
                                : reinterpret_cast<const void *>(k_control<0>);
     Scn s_ = sc;

@@ -71,8 +71,10 @@ struct Xch {
     unsigned long long *partial;  // [2][wave groups][S][AW][4] words: Fx, Fy, Fz, min r2, each | step tag << 32
     unsigned *flags;     // spare counters (zero between launches)
     unsigned *done;      // [1]       finished-workgroup counter, zero between launches
-    unsigned *status;    // [1]       watchdog flag, zero between launches
+    unsigned *status;    // [1]       0 ok, 1 a wait ran out of time, 2 aborted by the host; zero between launches
     int S, G;
+    unsigned long long limit = 400000000ull;   // longest wait without progress, in 100 MHz real-time ticks
+    const unsigned *abort = nullptr;           // host abort word (pinned, mapped) or nullptr
 };
 
 // camera-to-world transform, row-major 3x4 [R | t]
@@ -87,6 +89,16 @@ struct VoxGrid {
     int dims[3];
     const float *excl = nullptr;  // robot self-filter: [n_excl][4] sphere centres and radii, or nullptr
     int n_excl = 0;
+    double lod[3] = {0, 0, 0};    // lo, voxel and 1 / voxel in FP64, and 1 / voxel in FP32 (set by the launcher)
+    double sd = 0, inv_s = 0;
+    float inv_s32 = 0;
+};
+
+// pinhole intrinsics and the frames of a fused depth -> voxel pass
+struct Cam {
+    float fx, fy, cx, cy;
+    int w, h, n_frames;
+    const float *T;               // device [n_frames][12] camera-to-world poses
 };
 
 struct Tiling {
@@ -170,6 +182,13 @@ struct gmapp_ctx {
     gmapp_batch_tuning batch_forced_tuning{0, 0, 0, 0};
     bool batch_tuned = false;
     gmapp_batch_tuning batch_tuned_tuning{0, 0, 0, 0};
+    unsigned *vgrid = nullptr;    // voxel grid (bitmap or counts), all zero between calls
+    size_t vgrid_words = 0;
+    unsigned *vbsum = nullptr;    // per-block occupied-cell counts of the voxel pass
+    size_t vbsum_words = 0;
+    unsigned long long watchdog_ticks = 400000000ull;   // per-wait limit of the exchanges (4 s)
+    unsigned *abort_host = nullptr;   // pinned, coherent host word: nonzero ends every exchange wait
+    unsigned *abort_word = nullptr;   // its device address
     void *tab_host = nullptr;     // pinned staging of the batched job table
     size_t tab_host_bytes = 0;
     hipEvent_t tab_copied = nullptr;   // recorded after the last table copy
@@ -200,6 +219,21 @@ inline gmapp_status hip_fail(gmapp_ctx *ctx, hipError_t e, const char *what)
         if (e_ != hipSuccess) return gm::hip_fail(ctx, e_, #call); \
     } while (0)
 
+// the context's exchange area, watchdog limit and abort word for a sharded launch
+inline Xch make_xch(gmapp_ctx *ctx, int S, int G)
+{
+    Xch xc;
+    xc.partial = ctx->xchg;
+    xc.flags = ctx->sync;
+    xc.done = ctx->sync + kCounterWords;
+    xc.status = ctx->sync + kCounterWords + 16;
+    xc.S = S;
+    xc.G = G;
+    xc.limit = ctx->watchdog_ticks;
+    xc.abort = ctx->abort_word;
+    return xc;
+}
+
 // rollout launcher (rollout.hip)
 gmapp_status launch_rollout(gmapp_ctx *ctx, const Scn &sc, const Agt &ag, const Prm &pr, const Out &out,
                             const Probe *probe, const Tiling &t, hipStream_t stream);
@@ -226,10 +260,11 @@ gmapp_status launch_depth_to_points(gmapp_ctx *ctx, const float *depth, int w, i
 gmapp_status launch_depth_to_points_batch(gmapp_ctx *ctx, const float *depth, int n_frames, int w, int h,
                                           const float K[4], const float *T_dev, float *x, float *y, float *z,
                                           hipStream_t stream);
-size_t voxel_workspace_bytes(long long cells);
+// the voxel pass over points (x, y, z) or, with cam != nullptr, over the back-projected
+// pixels of cam's depth frames (x = depth)
 gmapp_status launch_voxel_downsample(gmapp_ctx *ctx, const float *x, const float *y, const float *z, long long n,
-                                     const VoxGrid &g, unsigned min_count, float *ox, float *oy, float *oz,
-                                     long long capacity, long long *n_out_dev, hipStream_t stream);
+                                     const Cam *cam, const VoxGrid &g, unsigned min_count, float *ox, float *oy,
+                                     float *oz, long long capacity, long long *n_out_dev, hipStream_t stream);
 gmapp_status check_tiling(gmapp_ctx *ctx, const Tiling &t, long long n_points, int n_seg, int cutoff);
 size_t rollout_lds_bytes(const Tiling &t, long long n_points, int n_seg);
 

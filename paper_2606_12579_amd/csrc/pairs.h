@@ -9,7 +9,6 @@ namespace gm {
 namespace dev {
 
 constexpr float kTiny = 1e-30f;                 // keeps |d|^2 > 0 (agent on a sphere centre)
-constexpr unsigned long long kWatchdogTicks = 400000000ull;  // 4 s of the 100 MHz real-time clock
 
 __device__ __forceinline__ void kahan_add(float &s, float &c, float x)
 {
@@ -98,6 +97,37 @@ __device__ __forceinline__ unsigned long long ld64_agent(const unsigned long lon
 {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ __forceinline__ unsigned ld_system(const unsigned *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// Every kAbortPeriod-th exchange a wait also reads the host's abort word: the load
+// is issued before the poll and consumed after it, so its latency mostly hides
+// under the exchange's own.
+constexpr unsigned kAbortPeriod = 64;
+
+// Check inside a bounded exchange wait that started at t_wait (real-time clock,
+// 100 MHz), made after every poll that found the words incomplete: true when the
+// wait must end -- it has gone on for longer than the limit without its words
+// arriving (status 1), or, every 64th poll, another wave already ended one
+// (status != 0) or the host raised the abort word (status 2).  The clock restarts
+// with every wait, so only a stall, not the length of a launch, trips it.
+__device__ __forceinline__ bool wait_expired(const Xch &xc, unsigned long long t_wait, unsigned spins)
+{
+    if (__builtin_amdgcn_s_memrealtime() - t_wait > xc.limit) {
+        st_agent(xc.status, 1u);
+        return true;
+    }
+    if ((spins & 63u) != 0) return false;
+    if (ld_agent(xc.status) != 0u) return true;
+    if (xc.abort && ld_system(xc.abort) != 0u) {
+        st_agent(xc.status, 2u);
+        return true;
+    }
+    return false;
+}
+
 // exchange word: float bits | step tag << 32
 __device__ __forceinline__ unsigned long long xword(float v, unsigned tag)
 {

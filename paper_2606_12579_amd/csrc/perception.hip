@@ -3,14 +3,32 @@
 // the uniform voxel lattice whose occupied cells' centres form S_W (voxel size
 // 2 r_O, voxel-centre clouds).
 //
-// The voxel pass is bandwidth/latency bound.  It works on a dense count grid
-// over the caller's workspace box (which is also the bounding-box filter):
-//   1. clear the grid,  2. mark each point's cell (atomic increments when min_count > 1),
-//   3. per 1024-cell block: count the cells holding >= min_count points,
-//   4. exclusive scan of the block counts (one workgroup),
-//   5. per block: local scan and write the occupied cells' centres.
-// The output is therefore sorted by linear cell index (x fastest, then y, then
-// z) without any sort, and the count of occupied cells stays on the device.
+// The cell of a point is the exact lattice coordinate floor((p - lo) / s) of the
+// real numbers the FP32 values p, lo, s denote: an FP64 estimate of the quotient
+// and one exact correction step decide it (lattice_axis), so points on or next to
+// a face land in the cell the lattice assigns them, not wherever a rounded
+// quotient happens to fall.
+//
+// The voxel pass is bandwidth/latency bound.  It marks cells in a grid over the
+// caller's workspace box (which is also the bounding-box filter) that the context
+// keeps all-zero between calls:
+//   min_count = 1: an occupancy grid of bytes, marked with plain stores (racing
+//     writers store the same value; device-scope atomics from every XCD on shared
+//     words would be serialised at memory);
+//   min_count > 1: a count grid (4 bytes per cell), marked with atomic adds that the
+//     wave first combines per cell.
+// A thread takes up to four consecutive points (or pixels) and merges equal cells
+// first: neighbouring pixels mostly share a voxel.  The occupied cells' centres are then written in increasing linear cell
+// index (x fastest, then y, then z) without a sort: per-block counts, then a
+// per-block local scan that writes the centres and clears what it read, each
+// block adding the counts of the blocks before it itself (up to kLocalBlocks
+// blocks; past that one exclusive scan of the block counts runs in between).
+// The count of occupied cells stays on the device.
+//
+// The fused pass (cam != nullptr) back-projects each pixel with the same FP32
+// operations as the back-projection kernels and marks its cell directly, so the
+// points are never written to memory and its cells equal those of the two-kernel
+// path bit for bit.
 #include "gmapp_internal.h"
 
 #include <algorithm>
@@ -20,7 +38,22 @@
 namespace gm {
 namespace {
 
-constexpr int kScanBlock = 1024;   // cells per block in steps 3 and 5 (256 threads x 4)
+constexpr int kCellBlock = 1024;        // cells per block of the finish (4 per thread)
+constexpr int kLocalBlocks = 1024;      // up to this many blocks each block adds its predecessors' counts itself
+
+// pixel (u, v) with z-depth d -> world point; NaN when d is not a positive finite depth
+__device__ __forceinline__ void back_project(int u, int v, float d, float fx, float fy, float cx, float cy,
+                                             const float *__restrict__ t, float &X, float &Y, float &Z)
+{
+    X = NAN; Y = NAN; Z = NAN;
+    if (d > 0.0f && d < INFINITY) {
+        const float xc = ((float)u - cx) * d / fx;    // pinhole: X_c = (u - c_x) z / f_x
+        const float yc = ((float)v - cy) * d / fy;
+        X = fmaf(t[0], xc, fmaf(t[1], yc, fmaf(t[2], d, t[3])));
+        Y = fmaf(t[4], xc, fmaf(t[5], yc, fmaf(t[6], d, t[7])));
+        Z = fmaf(t[8], xc, fmaf(t[9], yc, fmaf(t[10], d, t[11])));
+    }
+}
 
 __global__ void k_depth_to_points(const float *__restrict__ depth, int w, int h, float fx, float fy, float cx,
                                   float cy, Mat34 T, float *__restrict__ x, float *__restrict__ y,
@@ -29,16 +62,8 @@ __global__ void k_depth_to_points(const float *__restrict__ depth, int w, int h,
     const int n = w * h;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         const int v = i / w, u = i - v * w;
-        const float d = depth[i];
-        float X = NAN, Y = NAN, Z = NAN;
-        if (d > 0.0f && d < INFINITY) {
-            const float xc = ((float)u - cx) * d / fx;    // pinhole: X_c = (u - c_x) z / f_x
-            const float yc = ((float)v - cy) * d / fy;
-            const float zc = d;
-            X = fmaf(T.r[0], xc, fmaf(T.r[1], yc, fmaf(T.r[2], zc, T.r[3])));
-            Y = fmaf(T.r[4], xc, fmaf(T.r[5], yc, fmaf(T.r[6], zc, T.r[7])));
-            Z = fmaf(T.r[8], xc, fmaf(T.r[9], yc, fmaf(T.r[10], zc, T.r[11])));
-        }
+        float X, Y, Z;
+        back_project(u, v, depth[i], fx, fy, cx, cy, T.r, X, Y, Z);
         x[i] = X;
         y[i] = Y;
         z[i] = Z;
@@ -63,16 +88,7 @@ __global__ void k_depth_to_points_v4(const float4 *__restrict__ depth, long long
         int v = q / w, u = q - v * w;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const float d = dd[k];
-            float X = NAN, Y = NAN, Z = NAN;
-            if (d > 0.0f && d < INFINITY) {
-                const float xc = ((float)u - cx) * d / fx;
-                const float yc = ((float)v - cy) * d / fy;
-                X = fmaf(t[0], xc, fmaf(t[1], yc, fmaf(t[2], d, t[3])));
-                Y = fmaf(t[4], xc, fmaf(t[5], yc, fmaf(t[6], d, t[7])));
-                Z = fmaf(t[8], xc, fmaf(t[9], yc, fmaf(t[10], d, t[11])));
-            }
-            ox[k] = X; oy[k] = Y; oz[k] = Z;
+            back_project(u, v, dd[k], fx, fy, cx, cy, t, ox[k], oy[k], oz[k]);
             if (++u == w) { u = 0; ++v; }
         }
         x[i] = make_float4(ox[0], ox[1], ox[2], ox[3]);
@@ -90,16 +106,8 @@ __global__ void k_depth_to_points_n(const float *__restrict__ depth, long long n
         const int f = (int)(p / wh);
         const int q = (int)(p - (long long)f * wh);
         const int v = q / w, u = q - v * w;
-        const float *t = T + 12 * (size_t)f;
-        const float d = depth[p];
-        float X = NAN, Y = NAN, Z = NAN;
-        if (d > 0.0f && d < INFINITY) {
-            const float xc = ((float)u - cx) * d / fx;
-            const float yc = ((float)v - cy) * d / fy;
-            X = fmaf(t[0], xc, fmaf(t[1], yc, fmaf(t[2], d, t[3])));
-            Y = fmaf(t[4], xc, fmaf(t[5], yc, fmaf(t[6], d, t[7])));
-            Z = fmaf(t[8], xc, fmaf(t[9], yc, fmaf(t[10], d, t[11])));
-        }
+        float X, Y, Z;
+        back_project(u, v, depth[p], fx, fy, cx, cy, T + 12 * (size_t)f, X, Y, Z);
         x[p] = X;
         y[p] = Y;
         z[p] = Z;
@@ -112,16 +120,56 @@ __global__ void k_zero_u32(unsigned *p, long long n)
         p[i] = 0u;
 }
 
-// cell of a point: floor((p - lo) / voxel) per axis in FP32; -1 when outside the box
-__device__ __forceinline__ long long cell_of(float px, float py, float pz, const VoxGrid &g)
+// Exact lattice coordinate k = floor((p - lo) / s) of the real values of p (FP32),
+// lo and s (FP32 values); false when p is not finite or k lies outside [0, dim).
+// Fast path in FP32: q = fl(fl(p - lo) * fl(1 / s)) is within |q| 1.8e-7 of the true
+// quotient (three roundings of relative 2^-24), so when its fractional part keeps a
+// margin of |q| 2.4e-7 + 1e-6 from both faces, floor(q) is the cell.  Otherwise
+// (about one coordinate in ten thousand near a face, or a non-finite one) the
+// exact path decides in FP64:
+//   * p - lo is taken exactly as hi + err (two-sum);
+//   * floor(hi * inv_s) is within one of k (the quotient's relative error is ~2^-51);
+//   * the side of a face k s is the sign of (hi - k s) + err: the fused multiply-add
+//     rounds hi - k s once from its exact value, and either that value is exact or it
+//     is far larger than err, so the FP64 sum has the exact sign.
+__device__ __forceinline__ bool lattice_axis_exact(float p, double lo, double s, double inv_s, int dim, int &k)
 {
-    if (!(px == px) || !(py == py) || !(pz == pz)) return -1;
-    const float fx = floorf((px - g.lo[0]) / g.voxel);
-    const float fy = floorf((py - g.lo[1]) / g.voxel);
-    const float fz = floorf((pz - g.lo[2]) / g.voxel);
-    if (!(fx >= 0.0f && fy >= 0.0f && fz >= 0.0f)) return -1;
-    if (!(fx < (float)g.dims[0] && fy < (float)g.dims[1] && fz < (float)g.dims[2])) return -1;
-    return ((long long)fz * g.dims[1] + (long long)fy) * g.dims[0] + (long long)fx;
+    const double P = (double)p;
+    const double hi = __dadd_rn(P, -lo);
+    const double bb = __dadd_rn(hi, -P);
+    const double err = __dadd_rn(__dadd_rn(P, -__dadd_rn(hi, -bb)), __dadd_rn(-lo, -bb));
+    double kf = floor(__dmul_rn(hi, inv_s));
+    if (!(kf >= -1.0 && kf <= (double)dim)) return false;       // also NaN / infinite p
+    if (__dadd_rn(__fma_rn(-kf, s, hi), err) < 0.0) kf -= 1.0;
+    else if (__dadd_rn(__fma_rn(-(kf + 1.0), s, hi), err) >= 0.0) kf += 1.0;
+    if (!(kf >= 0.0 && kf < (double)dim)) return false;
+    k = (int)kf;
+    return true;
+}
+
+__device__ __forceinline__ bool lattice_axis(float p, int a, const VoxGrid &g, int &k)
+{
+    const float q = __fmul_rn(__fsub_rn(p, g.lo[a]), g.inv_s32);
+    const float fl = floorf(q);
+    const float f = __fsub_rn(q, fl);
+    const float m = fmaf(fabsf(q), 2.4e-7f, 1e-6f);
+    if (f > m && __fsub_rn(1.0f, f) > m) {
+        if (!(fl >= 0.0f && fl < (float)g.dims[a])) return false;
+        k = (int)fl;
+        return true;
+    }
+    return lattice_axis_exact(p, g.lod[a], g.sd, g.inv_s, g.dims[a], k);
+}
+
+// linear cell of a point (x fastest; below 2^31, the grid's limit), -1 when outside
+// the box or not finite
+__device__ __forceinline__ int cell_of(float px, float py, float pz, const VoxGrid &g)
+{
+    int kx, ky, kz;
+    if (!lattice_axis(px, 0, g, kx)) return -1;
+    if (!lattice_axis(py, 1, g, ky)) return -1;
+    if (!lattice_axis(pz, 2, g, kz)) return -1;
+    return (int)(((unsigned)kz * (unsigned)g.dims[1] + (unsigned)ky) * (unsigned)g.dims[0] + (unsigned)kx);
 }
 
 // Robot self-filter: a point within any of the robot's bounding spheres (centre c,
@@ -141,120 +189,231 @@ __device__ __forceinline__ bool on_robot(float px, float py, float pz, const Vox
     return false;
 }
 
-// mark a point's cell: occupancy (min_count 1: a plain store of 1, racing writers
-// store the same value) or counts (atomic increments)
-template <bool COUNT>
-__device__ __forceinline__ void mark(float px, float py, float pz, const VoxGrid &g, unsigned *__restrict__ grid)
+// the cell a point marks, -1 when it is dropped (outside the box, not finite, or on the robot)
+__device__ __forceinline__ int mark_cell(float px, float py, float pz, const VoxGrid &g)
 {
-    long long c = cell_of(px, py, pz, g);
-    if (c >= 0 && g.n_excl > 0 && on_robot(px, py, pz, g)) c = -1;
-    if (c >= 0) {
-        if constexpr (COUNT) atomicAdd(&grid[c], 1u);
-        else grid[c] = 1u;
+    const int c = cell_of(px, py, pz, g);
+    if (c >= 0 && g.n_excl > 0 && on_robot(px, py, pz, g)) return -1;
+    return c;
+}
+
+// sum over the 64 lanes of a wave, the result in every lane: DPP row rotations by 8, 4,
+// 2, 1, the xor-16 swizzle and the 32-lane swap (VALU work, no LDS)
+__device__ __forceinline__ unsigned wave_sum(unsigned x)
+{
+    x += (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x128, 0xF, 0xF, false);   // row_ror:8
+    x += (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x124, 0xF, 0xF, false);   // row_ror:4
+    x += (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x122, 0xF, 0xF, false);   // row_ror:2
+    x += (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x121, 0xF, 0xF, false);   // row_ror:1
+    x += (unsigned)__builtin_amdgcn_ds_swizzle((int)x, 0x401F);                      // xor 16
+    auto sw = __builtin_amdgcn_permlane32_swap((int)x, (int)x, false, false);
+    return (unsigned)sw[0] + (unsigned)sw[1];
+}
+
+// Marks one cell per lane (-1: none).
+//   occupancy (min_count = 1): a plain store of byte 1 -- racing writers store the same
+//     value, and the caches merge byte writes, so no atomic is needed;
+//   counts: the lanes holding the lowest pending lane's cell add their points across the
+//     wave and that lane issues one atomic add; repeat until no cell is left (neighbouring
+//     points mostly share a cell, so the atomics, serialised per address, stay few).
+template <bool COUNT>
+__device__ __forceinline__ void wave_mark(int cell, unsigned cnt, unsigned *__restrict__ grid)
+{
+    if constexpr (!COUNT) {
+        if (cell >= 0) reinterpret_cast<unsigned char *>(grid)[(unsigned)cell] = 1;
+    } else {
+        const int lane = threadIdx.x & 63;
+        unsigned long long pending = __ballot(cell >= 0);
+        while (pending) {
+            const int leader = __ffsll((long long)pending) - 1;
+            const int c0 = __builtin_amdgcn_readlane(cell, leader);
+            const bool mine = cell == c0;
+            const unsigned v = wave_sum(mine ? cnt : 0u);
+            if (lane == leader) atomicAdd(&grid[(unsigned)c0], v);
+            pending &= ~__ballot(mine);
+            if (mine) cell = -1;
+        }
     }
 }
 
+// Four consecutive points of a thread: a cell equal to the one before it merges into
+// it (the run's first entry carries the run's points), then one mark per remaining
+// entry (uniform control flow, static indexing).
 template <bool COUNT>
-__global__ void k_count(const float *__restrict__ x, const float *__restrict__ y, const float *__restrict__ z,
-                        long long n, VoxGrid g, unsigned *__restrict__ grid)
+__device__ __forceinline__ void mark4(const float (&X)[4], const float (&Y)[4], const float (&Z)[4], bool live,
+                                      const VoxGrid &g, unsigned *__restrict__ grid)
 {
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
-        mark<COUNT>(x[i], y[i], z[i], g, grid);
+    int c[4];
+    unsigned n[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        n[r] = 1u;
+        c[r] = live ? mark_cell(X[r], Y[r], Z[r], g) : -1;
+    }
+#pragma unroll
+    for (int r = 3; r >= 1; --r)
+        if (c[r] >= 0 && c[r] == c[r - 1]) {
+            n[r - 1] += n[r];
+            c[r] = -1;
+        }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) wave_mark<COUNT>(c[r], n[r], grid);
 }
 
-// The same with four points per thread from 16-byte loads of each coordinate stream
-// (x, y, z 16-byte aligned); the last n - 4 n4 (< 4) points go to the first threads.
+// points, one per thread (the loop trip count is uniform across the wave)
 template <bool COUNT>
-__global__ __launch_bounds__(256) void k_count_v4(const float4 *__restrict__ x4, const float4 *__restrict__ y4,
-                                                  const float4 *__restrict__ z4, long long n4,
-                                                  const float *__restrict__ x, const float *__restrict__ y,
-                                                  const float *__restrict__ z, long long n, VoxGrid g,
-                                                  unsigned *__restrict__ grid)
+__global__ __launch_bounds__(256) void k_mark(const float *__restrict__ x, const float *__restrict__ y,
+                                              const float *__restrict__ z, long long n, VoxGrid g,
+                                              unsigned *__restrict__ grid)
 {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    const long long wbase = blockIdx.x * (long long)blockDim.x + (threadIdx.x & ~63);
+    for (long long w0 = wbase; w0 < n; w0 += stride) {
+        const long long i = w0 + (threadIdx.x & 63);
+        wave_mark<COUNT>(i < n ? mark_cell(x[i], y[i], z[i], g) : -1, 1u, grid);
+    }
+}
+
+// points, four per thread from 16-byte loads of each coordinate stream (x, y, z
+// 16-byte aligned); the last n - 4 n4 (< 4) points go to the first lanes of the
+// grid's first wave
+template <bool COUNT>
+__global__ __launch_bounds__(256) void k_mark_v4(const float4 *__restrict__ x4, const float4 *__restrict__ y4,
+                                                 const float4 *__restrict__ z4, long long n4,
+                                                 const float *__restrict__ x, const float *__restrict__ y,
+                                                 const float *__restrict__ z, long long n, VoxGrid g,
+                                                 unsigned *__restrict__ grid)
+{
+    const long long stride = (long long)gridDim.x * blockDim.x;
     const long long tid = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    for (long long i = tid; i < n4; i += (long long)gridDim.x * blockDim.x) {
-        const float4 a = x4[i], b = y4[i], c = z4[i];
-        mark<COUNT>(a.x, b.x, c.x, g, grid);
-        mark<COUNT>(a.y, b.y, c.y, g, grid);
-        mark<COUNT>(a.z, b.z, c.z, g, grid);
-        mark<COUNT>(a.w, b.w, c.w, g, grid);
+    const long long wbase = tid - (threadIdx.x & 63);        // the wave's first thread (wave-uniform)
+    for (long long w0 = wbase; w0 < n4; w0 += stride) {
+        const long long i = w0 + (threadIdx.x & 63);
+        float X[4] = {0, 0, 0, 0}, Y[4] = {0, 0, 0, 0}, Z[4] = {0, 0, 0, 0};
+        const bool live = i < n4;
+        if (live) {
+            const float4 a = x4[i], b = y4[i], c = z4[i];
+            X[0] = a.x; X[1] = a.y; X[2] = a.z; X[3] = a.w;
+            Y[0] = b.x; Y[1] = b.y; Y[2] = b.z; Y[3] = b.w;
+            Z[0] = c.x; Z[1] = c.y; Z[2] = c.z; Z[3] = c.w;
+        }
+        mark4<COUNT>(X, Y, Z, live, g, grid);
     }
-    const long long t = 4 * n4 + tid;
-    if (t < n) mark<COUNT>(x[t], y[t], z[t], g, grid);
+    if (wbase == 0) {
+        const long long t = 4 * n4 + tid;
+        wave_mark<COUNT>(t < n ? mark_cell(x[t], y[t], z[t], g) : -1, 1u, grid);
+    }
 }
 
-__device__ __forceinline__ unsigned block_sum(unsigned v, unsigned *sh)
+// frame and pixel of a flat pixel index (32-bit division when the index fits)
+__device__ __forceinline__ void pixel_of(long long p, int w, int wh, int &f, int &u, int &v)
 {
-    // 256 threads: wave sums, then the 4 wave totals
+    int q;
+    if ((unsigned long long)p < (1ull << 32)) {
+        const unsigned pu = (unsigned)p;
+        f = (int)(pu / (unsigned)wh);
+        q = (int)(pu - (unsigned)f * (unsigned)wh);
+    } else {
+        f = (int)(p / wh);
+        q = (int)(p - (long long)f * wh);
+    }
+    v = q / w;
+    u = q - v * w;
+}
+
+// fused back-projection and marking: four consecutive pixels per thread from one
+// 16-byte depth load (w h divisible by 4, depth 16-byte aligned)
+template <bool COUNT>
+__global__ __launch_bounds__(256) void k_mark_depth_v4(const float4 *__restrict__ depth, long long n4, Cam cam,
+                                                       VoxGrid g, unsigned *__restrict__ grid)
+{
+    const int wh = cam.w * cam.h;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    const long long wbase = blockIdx.x * (long long)blockDim.x + (threadIdx.x & ~63);
+    for (long long w0 = wbase; w0 < n4; w0 += stride) {
+        const long long i = w0 + (threadIdx.x & 63);
+        float X[4] = {0, 0, 0, 0}, Y[4] = {0, 0, 0, 0}, Z[4] = {0, 0, 0, 0};
+        const bool live = i < n4;
+        if (live) {
+            int f, u, v;
+            pixel_of(4 * i, cam.w, wh, f, u, v);
+            const float *t = cam.T + 12 * (size_t)f;
+            const float4 d4 = depth[i];
+            const float dd[4] = {d4.x, d4.y, d4.z, d4.w};
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                back_project(u, v, dd[k], cam.fx, cam.fy, cam.cx, cam.cy, t, X[k], Y[k], Z[k]);
+                if (++u == cam.w) { u = 0; ++v; }
+            }
+        }
+        mark4<COUNT>(X, Y, Z, live, g, grid);
+    }
+}
+
+// fused, any shape: one pixel per thread
+template <bool COUNT>
+__global__ __launch_bounds__(256) void k_mark_depth(const float *__restrict__ depth, long long n, Cam cam, VoxGrid g,
+                                                    unsigned *__restrict__ grid)
+{
+    const int wh = cam.w * cam.h;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    const long long wbase = blockIdx.x * (long long)blockDim.x + (threadIdx.x & ~63);
+    for (long long w0 = wbase; w0 < n; w0 += stride) {
+        const long long p = w0 + (threadIdx.x & 63);
+        int c = -1;
+        if (p < n) {
+            int f, u, v;
+            pixel_of(p, cam.w, wh, f, u, v);
+            float X, Y, Z;
+            back_project(u, v, depth[p], cam.fx, cam.fy, cam.cx, cam.cy, cam.T + 12 * (size_t)f, X, Y, Z);
+            c = mark_cell(X, Y, Z, g);
+        }
+        wave_mark<COUNT>(c, 1u, grid);
+    }
+}
+
+// Lattice coordinates of a linear cell index (x fastest); 32-bit arithmetic (the grid
+// holds at most 2^31 cells).
+struct CellIdx {
+    unsigned x, y, z;
+};
+__device__ __forceinline__ CellIdx cell_coords(unsigned c, const VoxGrid &g)
+{
+    const unsigned d0 = (unsigned)g.dims[0], d1 = (unsigned)g.dims[1];
+    const unsigned r = c / d0;
+    return CellIdx{c - r * d0, r % d1, r / d1};
+}
+// voxel centre lo + (k + 1/2) s, rounded to FP32
+__device__ __forceinline__ void write_centre(const CellIdx &k, const VoxGrid &g, long long pos, float *__restrict__ ox,
+                                             float *__restrict__ oy, float *__restrict__ oz)
+{
+    ox[pos] = fmaf((float)k.x + 0.5f, g.voxel, g.lo[0]);
+    oy[pos] = fmaf((float)k.y + 0.5f, g.voxel, g.lo[1]);
+    oz[pos] = fmaf((float)k.z + 0.5f, g.voxel, g.lo[2]);
+}
+
+// sum over a workgroup of NT threads (every thread gets it)
+template <int NT>
+__device__ __forceinline__ unsigned block_sum(unsigned v, unsigned *wsum)
+{
+    constexpr int NW = NT / 64;
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    const int wave = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) sh[wave] = v;
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = v;
     __syncthreads();
-    const unsigned t = sh[0] + sh[1] + sh[2] + sh[3];
+    unsigned t = 0;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) t += wsum[q];
     __syncthreads();
     return t;
 }
 
-__global__ __launch_bounds__(256) void k_block_counts(const unsigned *__restrict__ grid, long long cells,
-                                                      unsigned min_count, unsigned *__restrict__ bsum)
+// exclusive scan of one value per thread over a workgroup of NT threads (NT / 64 <= 16
+// waves); returns the thread's prefix, `total` gets the workgroup's sum
+template <int NT>
+__device__ __forceinline__ unsigned block_excl_scan(unsigned c, unsigned *wsum, unsigned &total)
 {
-    __shared__ unsigned sh[4];
-    const long long base = (long long)blockIdx.x * kScanBlock + threadIdx.x * 4;
-    unsigned c = 0;
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-        if (base + q < cells && grid[base + q] >= min_count) ++c;
-    const unsigned t = block_sum(c, sh);
-    if (threadIdx.x == 0) bsum[blockIdx.x] = t;
-}
-
-// exclusive scan of nb block counts in place (one workgroup of 1024 threads);
-// total -> *n_out
-__global__ __launch_bounds__(1024) void k_scan_blocks(unsigned *__restrict__ bsum, long long nb,
-                                                      long long *__restrict__ n_out)
-{
-    __shared__ unsigned wsum[16];
-    __shared__ unsigned long long carry;
-    if (threadIdx.x == 0) carry = 0;
-    __syncthreads();
+    constexpr int NW = NT / 64;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (long long b0 = 0; b0 < nb; b0 += 1024) {
-        const long long i = b0 + threadIdx.x;
-        const unsigned v = i < nb ? bsum[i] : 0u;
-        unsigned incl = v;                           // inclusive scan inside the wave
-        for (int off = 1; off < 64; off <<= 1) {
-            const unsigned o = __shfl_up(incl, off, 64);
-            if (lane >= off) incl += o;
-        }
-        if (lane == 63) wsum[wave] = incl;
-        __syncthreads();
-        unsigned before = 0;
-        for (int q = 0; q < wave; ++q) before += wsum[q];
-        unsigned chunk_total = 0;
-        for (int q = 0; q < 16; ++q) chunk_total += wsum[q];
-        const unsigned long long base = carry;
-        if (i < nb) bsum[i] = (unsigned)(base + before + incl - v);
-        __syncthreads();
-        if (threadIdx.x == 0) carry = base + chunk_total;
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) *n_out = (long long)carry;
-}
-
-__global__ __launch_bounds__(256) void k_write_centres(const unsigned *__restrict__ grid, long long cells,
-                                                       unsigned min_count, const unsigned *__restrict__ boff,
-                                                       VoxGrid g, float *__restrict__ ox, float *__restrict__ oy,
-                                                       float *__restrict__ oz, long long capacity)
-{
-    __shared__ unsigned wsum[4];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const long long base = (long long)blockIdx.x * kScanBlock + threadIdx.x * 4;
-    unsigned f[4], c = 0;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        f[q] = (base + q < cells && grid[base + q] >= min_count) ? 1u : 0u;
-        c += f[q];
-    }
     unsigned incl = c;
     for (int off = 1; off < 64; off <<= 1) {
         const unsigned o = __shfl_up(incl, off, 64);
@@ -262,24 +421,118 @@ __global__ __launch_bounds__(256) void k_write_centres(const unsigned *__restric
     }
     if (lane == 63) wsum[wave] = incl;
     __syncthreads();
-    unsigned before = 0;
-    for (int q = 0; q < wave; ++q) before += wsum[q];
-    long long pos = (long long)boff[blockIdx.x] + before + incl - c;
+    unsigned before = 0, all = 0;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        if (f[q]) {
-            if (pos < capacity) {
-                const long long cell = base + q;
-                const long long kx = cell % g.dims[0];
-                const long long r = cell / g.dims[0];
-                const long long ky = r % g.dims[1];
-                const long long kz = r / g.dims[1];
-                ox[pos] = fmaf((float)kx + 0.5f, g.voxel, g.lo[0]);   // voxel centre lo + (k + 1/2) s
-                oy[pos] = fmaf((float)ky + 0.5f, g.voxel, g.lo[1]);
-                oz[pos] = fmaf((float)kz + 0.5f, g.voxel, g.lo[2]);
-            }
-            ++pos;
-        }
+    for (int q = 0; q < NW; ++q) {
+        const unsigned s = wsum[q];
+        before += q < wave ? s : 0u;
+        all += s;
+    }
+    __syncthreads();
+    total = all;
+    return before + incl - c;
+}
+
+// Block b's first output position.  local: the block adds the counts of the blocks
+// before it itself (few blocks: no separate scan launch), and the last block writes
+// the total; otherwise bsum already holds the exclusive scan.
+__device__ __forceinline__ long long block_offset(const unsigned *__restrict__ bsum, bool local, unsigned blk_total,
+                                                  long long *__restrict__ n_out, unsigned *wsum)
+{
+    if (!local) return (long long)bsum[blockIdx.x];
+    unsigned acc = 0;
+    for (unsigned i = threadIdx.x; i < blockIdx.x; i += 256) acc += bsum[i];
+    const unsigned before = block_sum<256>(acc, wsum);
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *n_out = (long long)before + blk_total;
+    return (long long)before;
+}
+
+// The four cells [base, base + 4) of a thread in the finish: their occupancy (bit q)
+// and whether any of them was marked.  Occupancy grid: one 32-bit load of 4 bytes;
+// count grid: one 16-byte load of 4 counts (base is a multiple of 4; the grid is
+// allocated in whole blocks, so the loads stay inside it).
+template <bool COUNT>
+__device__ __forceinline__ unsigned cells4(const unsigned *__restrict__ grid, long long base, unsigned min_count,
+                                           bool &marked)
+{
+    unsigned occ = 0;
+    if constexpr (COUNT) {
+        const uint4 v = reinterpret_cast<const uint4 *>(grid)[base >> 2];
+        occ = (v.x >= min_count ? 1u : 0u) | (v.y >= min_count ? 2u : 0u) | (v.z >= min_count ? 4u : 0u) |
+              (v.w >= min_count ? 8u : 0u);
+        marked = (v.x | v.y | v.z | v.w) != 0u;
+    } else {
+        const unsigned w = grid[base >> 2];
+        occ = ((w & 0xFFu) ? 1u : 0u) | ((w & 0xFF00u) ? 2u : 0u) | ((w & 0xFF0000u) ? 4u : 0u) |
+              ((w & 0xFF000000u) ? 8u : 0u);
+        marked = w != 0u;
+    }
+    return occ;
+}
+
+__device__ __forceinline__ void clear4(unsigned *__restrict__ grid, long long base, bool count)
+{
+    if (count) reinterpret_cast<uint4 *>(grid)[base >> 2] = make_uint4(0u, 0u, 0u, 0u);
+    else grid[base >> 2] = 0u;
+}
+
+// finish, pass 1: occupied cells per block of kCellBlock cells (4 per thread)
+template <bool COUNT>
+__global__ __launch_bounds__(256) void k_block_cells(const unsigned *__restrict__ grid, unsigned min_count,
+                                                     unsigned *__restrict__ bsum)
+{
+    __shared__ unsigned wsum[4];
+    bool marked;
+    const unsigned occ = cells4<COUNT>(grid, (long long)blockIdx.x * kCellBlock + threadIdx.x * 4, min_count, marked);
+    const unsigned t = block_sum<256>(__popc(occ), wsum);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = t;
+}
+
+// exclusive scan of nb block counts in place (one workgroup of 1024 threads);
+// total -> *n_out (many blocks only)
+__global__ __launch_bounds__(1024) void k_scan_blocks(unsigned *__restrict__ bsum, long long nb,
+                                                      long long *__restrict__ n_out)
+{
+    __shared__ unsigned wsum[16];
+    unsigned long long carry = 0;
+    for (long long b0 = 0; b0 < nb; b0 += 1024) {
+        const long long i = b0 + threadIdx.x;
+        const unsigned v = i < nb ? bsum[i] : 0u;
+        unsigned total;
+        const unsigned ex = block_excl_scan<1024>(v, wsum, total);
+        if (i < nb) bsum[i] = (unsigned)(carry + ex);
+        carry += total;
+    }
+    if (threadIdx.x == 0) *n_out = (long long)carry;
+}
+
+// finish, pass 2: the block's occupied cells are compacted in LDS in cell order (local
+// scan), then written out as centres by consecutive threads (coalesced stores); every
+// marked cell read is cleared.
+template <bool COUNT>
+__global__ __launch_bounds__(256) void k_write_cells(unsigned *__restrict__ grid, unsigned min_count,
+                                                     const unsigned *__restrict__ bsum, int local,
+                                                     long long *__restrict__ n_out, VoxGrid g, float *__restrict__ ox,
+                                                     float *__restrict__ oy, float *__restrict__ oz, long long capacity)
+{
+    __shared__ unsigned wsum[16];
+    __shared__ unsigned short cellbuf[kCellBlock];
+    const long long base = (long long)blockIdx.x * kCellBlock + threadIdx.x * 4;
+    bool marked;
+    unsigned occ = cells4<COUNT>(grid, base, min_count, marked);
+    unsigned total;
+    unsigned at = block_excl_scan<256>(__popc(occ), wsum, total);
+    const long long pos0 = block_offset(bsum, local != 0, total, n_out, wsum + 4);
+    if (marked) clear4(grid, base, COUNT);
+    while (occ) {
+        cellbuf[at++] = (unsigned short)(4 * threadIdx.x + (unsigned)(__ffs(occ) - 1));
+        occ &= occ - 1u;
+    }
+    __syncthreads();
+    const unsigned cbase = (unsigned)((long long)blockIdx.x * kCellBlock);
+    for (unsigned j = threadIdx.x; j < total; j += 256) {
+        const long long pos = pos0 + j;
+        if (pos < capacity) write_centre(cell_coords(cbase + cellbuf[j], g), g, pos, ox, oy, oz);
     }
 }
 
@@ -297,14 +550,17 @@ gmapp_status launch_depth_to_points(gmapp_ctx *ctx, const float *depth, int w, i
     return GMAPP_OK;
 }
 
+namespace {
+bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+}  // namespace
+
 gmapp_status launch_depth_to_points_batch(gmapp_ctx *ctx, const float *depth, int n_frames, int w, int h,
                                           const float K[4], const float *T_dev, float *x, float *y, float *z,
                                           hipStream_t stream)
 {
     const long long wh = (long long)w * h, n = wh * n_frames;
     if (n == 0) return GMAPP_OK;
-    auto aligned = [](const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; };
-    if (wh % 4 == 0 && aligned(depth) && aligned(x) && aligned(y) && aligned(z)) {
+    if (wh % 4 == 0 && aligned16(depth) && aligned16(x) && aligned16(y) && aligned16(z)) {
         const long long n4 = n / 4;
         const int blocks = (int)std::min<long long>((n4 + 255) / 256, 16384);
         hipLaunchKernelGGL(k_depth_to_points_v4, dim3(blocks), dim3(256), 0, stream,
@@ -319,47 +575,104 @@ gmapp_status launch_depth_to_points_batch(gmapp_ctx *ctx, const float *depth, in
     return GMAPP_OK;
 }
 
-size_t voxel_workspace_bytes(long long cells)
-{
-    const long long nb = (cells + kScanBlock - 1) / kScanBlock;
-    return ((size_t)cells * 4 + 255) / 256 * 256 + (size_t)nb * 4;
-}
+namespace {
 
-gmapp_status launch_voxel_downsample(gmapp_ctx *ctx, const float *x, const float *y, const float *z, long long n,
-                                     const VoxGrid &g, unsigned min_count, float *ox, float *oy, float *oz,
-                                     long long capacity, long long *n_out_dev, hipStream_t stream)
+template <bool COUNT>
+void launch_mark(gmapp_ctx *ctx, const float *x, const float *y, const float *z, long long n, const Cam *cam,
+                 const VoxGrid &g, unsigned *grid, hipStream_t stream)
 {
-    const long long cells = (long long)g.dims[0] * g.dims[1] * g.dims[2];
-    const long long nb = (cells + kScanBlock - 1) / kScanBlock;
-    if (voxel_workspace_bytes(cells) > ctx->scratch_bytes)
-        return fail(ctx, GMAPP_ENOMEM, "voxel grid of %lld cells needs %zu workspace bytes, the context has %zu",
-                    cells, voxel_workspace_bytes(cells), ctx->scratch_bytes);
-    unsigned *grid = reinterpret_cast<unsigned *>(ctx->scratch);
-    unsigned *bsum = reinterpret_cast<unsigned *>(ctx->scratch + ((size_t)cells * 4 + 255) / 256 * 256);
-    const int zb = (int)std::min<long long>((cells + 255) / 256, 8192);
-    hipLaunchKernelGGL(k_zero_u32, dim3(zb), dim3(256), 0, stream, grid, cells);
-    // four points per thread only when the quads still give every SIMD two waves; below that
-    // one point per thread hides more latency
-    auto aligned = [](const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; };
+    if (n == 0) return;
+    // four points (pixels) per thread only when the quads still give every SIMD two waves;
+    // below that one per thread hides more latency
     const long long fill = 2ll * 64 * 4 * std::max(ctx->n_cu, 1);
-    if (n / 4 >= fill && aligned(x) && aligned(y) && aligned(z)) {
+    if (cam) {
+        const long long wh = (long long)cam->w * cam->h;
+        if (wh % 4 == 0 && aligned16(x) && n / 4 >= fill) {
+            const long long n4 = n / 4;
+            const int pb = (int)std::min<long long>((n4 + 255) / 256, 16384);
+            hipLaunchKernelGGL(k_mark_depth_v4<COUNT>, dim3(pb), dim3(256), 0, stream,
+                               reinterpret_cast<const float4 *>(x), n4, *cam, g, grid);
+        } else {
+            const int pb = (int)std::min<long long>((n + 255) / 256, 16384);
+            hipLaunchKernelGGL(k_mark_depth<COUNT>, dim3(pb), dim3(256), 0, stream, x, n, *cam, g, grid);
+        }
+        return;
+    }
+    if (n / 4 >= fill && aligned16(x) && aligned16(y) && aligned16(z)) {
         const long long n4 = n / 4;
         const int pb = (int)std::min<long long>((n4 + 255) / 256, 16384);
-        const float4 *x4 = reinterpret_cast<const float4 *>(x), *y4 = reinterpret_cast<const float4 *>(y);
-        const float4 *z4 = reinterpret_cast<const float4 *>(z);
-        if (min_count > 1)
-            hipLaunchKernelGGL(k_count_v4<true>, dim3(pb), dim3(256), 0, stream, x4, y4, z4, n4, x, y, z, n, g, grid);
-        else
-            hipLaunchKernelGGL(k_count_v4<false>, dim3(pb), dim3(256), 0, stream, x4, y4, z4, n4, x, y, z, n, g, grid);
-    } else if (n > 0) {
+        hipLaunchKernelGGL(k_mark_v4<COUNT>, dim3(pb), dim3(256), 0, stream, reinterpret_cast<const float4 *>(x),
+                           reinterpret_cast<const float4 *>(y), reinterpret_cast<const float4 *>(z), n4, x, y, z, n,
+                           g, grid);
+    } else {
         const int pb = (int)std::min<long long>((n + 255) / 256, 8192);
-        if (min_count > 1) hipLaunchKernelGGL(k_count<true>, dim3(pb), dim3(256), 0, stream, x, y, z, n, g, grid);
-        else hipLaunchKernelGGL(k_count<false>, dim3(pb), dim3(256), 0, stream, x, y, z, n, g, grid);
+        hipLaunchKernelGGL(k_mark<COUNT>, dim3(pb), dim3(256), 0, stream, x, y, z, n, g, grid);
     }
-    hipLaunchKernelGGL(k_block_counts, dim3((unsigned)nb), dim3(256), 0, stream, grid, cells, min_count, bsum);
-    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, stream, bsum, nb, n_out_dev);
-    hipLaunchKernelGGL(k_write_centres, dim3((unsigned)nb), dim3(256), 0, stream, grid, cells, min_count, bsum, g, ox,
-                       oy, oz, capacity);
+}
+
+}  // namespace
+
+// The grid stays all-zero between calls: it is zero-filled when (re)allocated, and
+// every finish kernel clears what the marking set.
+gmapp_status launch_voxel_downsample(gmapp_ctx *ctx, const float *x, const float *y, const float *z, long long n,
+                                     const Cam *cam, const VoxGrid &g_in, unsigned min_count, float *ox, float *oy,
+                                     float *oz, long long capacity, long long *n_out_dev, hipStream_t stream)
+{
+    VoxGrid g = g_in;
+    for (int a = 0; a < 3; ++a) g.lod[a] = (double)g.lo[a];
+    g.sd = (double)g.voxel;
+    g.inv_s = 1.0 / g.sd;
+    g.inv_s32 = 1.0f / g.voxel;
+    const long long cells = (long long)g.dims[0] * g.dims[1] * g.dims[2];
+    const bool counts = min_count > 1;
+    const long long nb = (cells + kCellBlock - 1) / kCellBlock;
+    // whole blocks of u32 words: 1 per cell (counts) or 1 per 4 cells (occupancy bytes)
+    const size_t need = (size_t)nb * (counts ? kCellBlock : kCellBlock / 4);
+    if (need > ctx->vgrid_words) {
+        if (ctx->vgrid) {
+            GM_HIP(ctx, hipStreamSynchronize(stream));
+            (void)hipFree(ctx->vgrid);
+            ctx->vgrid = nullptr;
+            ctx->vgrid_words = 0;
+        }
+        void *p = nullptr;
+        if (hipMalloc(&p, need * sizeof(unsigned)) != hipSuccess)
+            return fail(ctx, GMAPP_ENOMEM, "voxel grid of %lld cells: cannot allocate %zu bytes", cells,
+                        need * sizeof(unsigned));
+        ctx->vgrid = static_cast<unsigned *>(p);
+        ctx->vgrid_words = need;
+        const int zb = (int)std::min<long long>(((long long)need + 255) / 256, 8192);
+        hipLaunchKernelGGL(k_zero_u32, dim3(zb), dim3(256), 0, stream, ctx->vgrid, (long long)need);
+    }
+    if ((size_t)nb > ctx->vbsum_words) {
+        if (ctx->vbsum) {
+            GM_HIP(ctx, hipStreamSynchronize(stream));
+            (void)hipFree(ctx->vbsum);
+            ctx->vbsum = nullptr;
+            ctx->vbsum_words = 0;
+        }
+        void *p = nullptr;
+        if (hipMalloc(&p, (size_t)nb * sizeof(unsigned)) != hipSuccess)
+            return fail(ctx, GMAPP_ENOMEM, "voxel block table of %lld entries: cannot allocate", nb);
+        ctx->vbsum = static_cast<unsigned *>(p);
+        ctx->vbsum_words = (size_t)nb;
+    }
+    unsigned *grid = ctx->vgrid, *bsum = ctx->vbsum;
+    const int local = nb <= kLocalBlocks ? 1 : 0;
+    if (counts) {
+        launch_mark<true>(ctx, x, y, z, n, cam, g, grid, stream);
+        hipLaunchKernelGGL(k_block_cells<true>, dim3((unsigned)nb), dim3(256), 0, stream, grid, min_count, bsum);
+    } else {
+        launch_mark<false>(ctx, x, y, z, n, cam, g, grid, stream);
+        hipLaunchKernelGGL(k_block_cells<false>, dim3((unsigned)nb), dim3(256), 0, stream, grid, min_count, bsum);
+    }
+    if (!local) hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, stream, bsum, nb, n_out_dev);
+    if (counts)
+        hipLaunchKernelGGL(k_write_cells<true>, dim3((unsigned)nb), dim3(256), 0, stream, grid, min_count, bsum, local,
+                           n_out_dev, g, ox, oy, oz, capacity);
+    else
+        hipLaunchKernelGGL(k_write_cells<false>, dim3((unsigned)nb), dim3(256), 0, stream, grid, min_count, bsum,
+                           local, n_out_dev, g, ox, oy, oz, capacity);
     GM_HIP(ctx, hipGetLastError());
     return GMAPP_OK;
 }

@@ -164,13 +164,7 @@ gmapp_status launch_rollout(gmapp_ctx *ctx, const Scn &sc, const Agt &ag, const 
     if (t.S > 1 && need_partial > kXchgBytes)
         return fail(ctx, GMAPP_ECAPACITY, "exchange area needs %zu bytes, the context holds %zu", need_partial,
                     kXchgBytes);
-    Xch xc;
-    xc.partial = ctx->xchg;
-    xc.flags = ctx->sync;
-    xc.done = ctx->sync + kCounterWords;
-    xc.status = ctx->sync + kCounterWords + 16;
-    xc.S = t.S;
-    xc.G = G;
+    Xch xc = make_xch(ctx, t.S, G);
     Probe pb{};
     if (probe) pb = *probe;
     Lay lay = make_layout(t, sc.n_cap, sc.n_seg);

@@ -113,7 +113,7 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
     float *lpt = reinterpret_cast<float *>(lds + lp.cx);          // points interleaved: x, y, z per point
     int4 *runs = reinterpret_cast<int4 *>(lds + lp.runs);      // [runs_cap]: begin, end, first slice, slices
     float4 *rvel = reinterpret_cast<float4 *>(lds + lp.rvel);  // [runs_cap]
-    __shared__ int s_last, s_nruns, s_split;
+    __shared__ int s_last, s_nruns, s_split, s_halt;
 
     constexpr bool POSE = KIND >= 1;
     constexpr bool ARM = KIND == 2;
@@ -260,7 +260,10 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
     if constexpr (ARM) {
         if (jwriter && out.joints) out.joints[(size_t)agent * (pr.n_steps + 1) * pr.arm_n + my_j] = pr.arm_q0[my_j];
     }
-    const unsigned long long t_start = __builtin_amdgcn_s_memrealtime();
+    // an exchange wait that ran out of time or saw the host's abort ends the rollout (a
+    // wave-uniform decision, shared through LDS when the workgroup is one group)
+    bool halt = false;
+    if (tid == 0) s_halt = 0;
 
     for (int k = 1; k <= n_steps; ++k) {
         const float t = PROBE ? t_fixed : fmaf((float)(k - 1), pr.dt, pr.t0);
@@ -419,7 +422,13 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
                 st64_agent(slot + 3, xword(m2_, tag));
             }
         };
-        auto collect = [&](float &Fx_, float &Fy_, float &Fz_, float &m2_) {
+        // returns false when the wait was cut short (the rollout then halts)
+        auto collect = [&](float &Fx_, float &Fy_, float &Fz_, float &m2_) -> bool {
+            if (halt) return false;
+            bool ok = true;
+            const bool probe_abort = xc.abort && (tag % kAbortPeriod) == 0;
+            const unsigned ab = probe_abort ? ld_system(xc.abort) : 0u;
+            const unsigned long long t_wait = __builtin_amdgcn_s_memrealtime();
             if (kVecX && 4 * S * AW <= 64) {
                 const bool poller = lane < 4 * S * AW;
                 unsigned long long q = 0;
@@ -427,12 +436,9 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
                 while (true) {
                     if (poller) q = ld64_agent(garea + lane);
                     if (__all(!poller || xtag(q) == tag)) break;
-                    if ((++spins & 63u) == 0) {
-                        if (ld_agent(xc.status) != 0u) break;
-                        if (__builtin_amdgcn_s_memrealtime() - t_start > kWatchdogTicks) {
-                            st_agent(xc.status, 1u);
-                            break;
-                        }
+                    if (wait_expired(xc, t_wait, ++spins)) {
+                        ok = false;
+                        break;
                     }
                 }
                 if (poller) reinterpret_cast<float *>(xtw)[lane] = xval(q);
@@ -447,16 +453,18 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
                         q3 = ld64_agent(slot + 3);
                         if (xtag(q0) == tag && xtag(q1) == tag && xtag(q2) == tag && xtag(q3) == tag) break;
                         __builtin_amdgcn_s_sleep(2);
-                        if ((++spins & 63u) == 0) {
-                            if (ld_agent(xc.status) != 0u) break;
-                            if (__builtin_amdgcn_s_memrealtime() - t_start > kWatchdogTicks) {
-                                st_agent(xc.status, 1u);
-                                break;
-                            }
+                        if (wait_expired(xc, t_wait, ++spins)) {
+                            ok = false;
+                            break;
                         }
                     }
                     xtw[l] = make_float4(xval(q0), xval(q1), xval(q2), xval(q3));
                 }
+                ok = !__any(!ok);
+            }
+            if (ab != 0u) {
+                st_agent(xc.status, 2u);
+                ok = false;
             }
             __builtin_amdgcn_wave_barrier();
             float4 a4 = xtw[a_w];
@@ -466,6 +474,7 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
             }
             __builtin_amdgcn_wave_barrier();        // xtw is rewritten next step
             Fx_ = a4.x; Fy_ = a4.y; Fz_ = a4.z; m2_ = a4.w;
+            return ok;
         };
         // net force (Eqs. 6, 7), obstacle cost (Eq. 18), integration (Eqs. 9-11), outputs
         auto finish = [&](float Fx_, float Fy_, float Fz_, float m2_) {
@@ -578,15 +587,17 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
                 Fx = acc.x; Fy = acc.y; Fz = acc.z; m2 = acc.w;
                 if (S > 1) publish(Fx, Fy, Fz, m2);
                 if constexpr (!PROBE) costs_early();       // overlaps the exchange
-                if (S > 1) collect(Fx, Fy, Fz, m2);
+                if (S > 1 && !collect(Fx, Fy, Fz, m2)) halt = true;
                 finish(Fx, Fy, Fz, m2);
                 if (lane < AW) {
                     tot[2 * lane] = make_float4(px, py, pz, vx);
                     tot[2 * lane + 1] = make_float4(vy, vz, 0.f, 0.f);
                 }
+                if (halt && lane == 0) s_halt = 1;
             }
             __syncthreads();
             if constexpr (PROBE) break;
+            if (s_halt) break;
             if (!lead) {
                 const float4 a = tot[2 * a_w], b = tot[2 * a_w + 1];
                 px = a.x; py = a.y; pz = a.z; vx = a.w; vy = b.x; vz = b.y;
@@ -594,9 +605,12 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
         } else {
             if (S > 1) publish(Fx, Fy, Fz, m2);
             if constexpr (!PROBE) costs_early();
-            if (S > 1) collect(Fx, Fy, Fz, m2);
+            if (S > 1 && !collect(Fx, Fy, Fz, m2)) halt = true;
             finish(Fx, Fy, Fz, m2);
             if constexpr (PROBE) break;
+            // without barriers in the step loop (resident shard) the wave stops on its own; with
+            // streamed tiles it keeps the workgroup's barriers and runs on without waiting
+            if (halt && resident) break;
         }
     }
 
@@ -661,7 +675,8 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
         if (tid == 0) {
             int best = ri[0];
             if (best < 0) best = inc;             // no candidate beats the incumbent (or N_a = 0)
-            if (ld_agent(xc.status) != 0u) best = GMAPP_ETIMEOUT;
+            const unsigned stt = ld_agent(xc.status);
+            if (stt != 0u) best = stt == 1u ? GMAPP_ETIMEOUT : GMAPP_ECANCELLED;
             out.best[0] = best;
         }
     } else {

@@ -185,6 +185,13 @@ def load_library(path: str = LIB_PATH):
                                                              vp]),
         "gmapp_depth_to_points_batch": (ctypes.c_int32, [vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                                          P(ctypes.c_float), vp, vp, vp, vp, vp]),
+        "gmapp_depth_to_voxels": (ctypes.c_int32, [vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                                   P(ctypes.c_float), vp, ctypes.c_float, P(ctypes.c_float),
+                                                   P(ctypes.c_int32), ctypes.c_int32, vp, ctypes.c_int32, vp, vp, vp,
+                                                   ctypes.c_int64, vp, vp]),
+        "gmapp_set_watchdog": (ctypes.c_int32, [vp, ctypes.c_double]),
+        "gmapp_abort": (ctypes.c_int32, [vp, ctypes.c_int32]),
+        "gmapp_wait": (ctypes.c_int32, [vp, vp, ctypes.c_double]),
         "gmapp_get_tiling": (ctypes.c_int32, [vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                               ctypes.c_int32, P(Tiling)]),
         "gmapp_rollout_batch": (ctypes.c_int32, [vp, P(Job), ctypes.c_int32, vp]),
@@ -509,6 +516,19 @@ class Context:
         s = stream if stream is not None else torch.cuda.current_stream(self.device)
         return ctypes.c_void_p(s.cuda_stream)
 
+    # ------------------------------------------------------------------ failure handling
+    def set_watchdog(self, seconds=0.0):
+        """gmapp_set_watchdog: longest stall of one exchange wait (0 = the default 4 s)."""
+        self._raise(self.lib.gmapp_set_watchdog(self.handle, float(seconds)))
+
+    def abort(self, raise_=True):
+        """gmapp_abort: raise (or lower) the context's abort word."""
+        self._raise(self.lib.gmapp_abort(self.handle, 1 if raise_ else 0))
+
+    def wait(self, timeout_s, stream=None):
+        """gmapp_wait: wait for the stream up to timeout_s, else abort its launches (GmappError ETIMEOUT)."""
+        self._raise(self.lib.gmapp_wait(self.handle, self._stream(stream), float(timeout_s)))
+
     # ------------------------------------------------------------------ tiling
     def set_tiling(self, agents=0, waves=0, shards=0, tile_points=0, layout=0, group=0):
         """Force a tiling (zeros = choose): agents per group, waves per workgroup, shards,
@@ -800,6 +820,39 @@ class Context:
         self._raise(st)
         return out
 
+    def depth_to_voxels(self, depth, K, T_wc, voxel, lo, dims, min_count=1, capacity=None, out=None, stream=None,
+                        robot_spheres=None):
+        """gmapp_depth_to_voxels: depth [B, h, w] and poses T_wc [B, 3, 4] (device float32) straight to the
+        occupied voxel centres (sorted by cell) and the device count.  robot_spheres: optional device float32
+        [K, 4] bounding spheres of the self-filter.
+
+        Returns (ox, oy, oz, n_out) with n_out an int64 [1] device tensor."""
+        import torch
+        if depth.dim() != 3:
+            raise ValueError("depth must be [frames, h, w]")
+        b, h, w = depth.shape
+        n = b * h * w
+        _check_tensor(depth, "depth", n, torch.float32, self.device)
+        _check_tensor(T_wc, "T_wc", 12 * b, torch.float32, self.device)
+        if capacity is None:
+            capacity = n
+        if out is None:
+            out = tuple(torch.empty(max(capacity, 1), dtype=torch.float32, device=self.device) for _ in range(3)) + \
+                (torch.zeros(1, dtype=torch.int64, device=self.device),)
+        Kc = (ctypes.c_float * 4)(*[float(v) for v in np.asarray(K, np.float32).reshape(4)])
+        loc = (ctypes.c_float * 3)(*[float(v) for v in np.asarray(lo, np.float32).reshape(3)])
+        dc = (ctypes.c_int32 * 3)(*[int(v) for v in np.asarray(dims).reshape(3)])
+        ns, rs = 0, None
+        if robot_spheres is not None:
+            ns = int(robot_spheres.numel()) // 4
+            _check_tensor(robot_spheres, "robot_spheres", 4 * ns, torch.float32, self.device)
+            rs = _ptr(robot_spheres)
+        st = self.lib.gmapp_depth_to_voxels(self.handle, _ptr(depth), int(b), int(w), int(h), Kc, _ptr(T_wc),
+                                            float(voxel), loc, dc, int(min_count), rs, ns, _ptr(out[0]),
+                                            _ptr(out[1]), _ptr(out[2]), int(capacity), _ptr(out[3]),
+                                            self._stream(stream))
+        self._raise(st)
+        return out
 
 
 class _RolloutCost:

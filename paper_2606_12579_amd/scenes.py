@@ -25,7 +25,7 @@ from __future__ import annotations
 
 import dataclasses
 import math
-from typing import List, Optional
+from typing import List, Optional, Tuple
 
 import numpy as np
 
@@ -328,22 +328,53 @@ class Request:
     arrival_s: float
 
 
-def config5(seed: int = 4, n_scenes: int = 512, rate_hz: float = 1000.0, n_lo: int = 1000, n_hi: int = 200_000,
-            agent_choices=(16, 64, 256), k_lo: int = 100, k_hi: int = 1000) -> List[Request]:
-    """Uneven replanning requests with Poisson arrival times (exponential gaps)."""
+def config5_shapes(seed: int = 4, n_scenes: int = 512, rate_hz: float = 1000.0, n_lo: int = 1000,
+                   n_hi: int = 200_000, agent_choices=(16, 64, 256), k_lo: int = 100,
+                   k_hi: int = 1000) -> List[Tuple[int, int, int, float]]:
+    """(N_O, N_a, N_k, arrival time) of each request of the batched-serving workload."""
     rng = np.random.default_rng(seed)
     out, t = [], 0.0
-    for i in range(n_scenes):
+    for _ in range(n_scenes):
         n_o = int(rng.integers(n_lo, n_hi + 1))
         n_a = int(rng.choice(agent_choices))
         n_k = int(rng.integers(k_lo, k_hi + 1))
+        out.append((n_o, n_a, n_k, t))
+        t += float(rng.exponential(1.0 / rate_hz))
+    return out
+
+
+def config5(seed: int = 4, n_scenes: int = 512, rate_hz: float = 1000.0, n_lo: int = 1000, n_hi: int = 200_000,
+            agent_choices=(16, 64, 256), k_lo: int = 100, k_hi: int = 1000, only=None) -> List[Request]:
+    """Uneven replanning requests with Poisson arrival times (exponential gaps);
+    `only` builds just the requests with those indices (each request's scene and
+    agents come from their own seed, so a subset equals the same requests of the
+    whole workload)."""
+    shapes = config5_shapes(seed, n_scenes, rate_hz, n_lo, n_hi, agent_choices, k_lo, k_hi)
+    out = []
+    for i in (range(n_scenes) if only is None else only):
+        n_o, n_a, n_k, t = shapes[i]
         sub = np.random.default_rng([seed, i])
         scene = objects_scene(sub, n_o)
         agents = default_agents(sub, n_a)
         prob = Problem(scene, agents, _query((0.02, 0.5, 0.5), (0.98, 0.5, 0.5)), Params(n_steps=n_k), f"req{i}")
         out.append(Request(prob, t))
-        t += float(rng.exponential(1.0 / rate_hz))
     return out
+
+
+def config5_stratified(n: int = 16, seed: int = 4, n_scenes: int = 512) -> List[int]:
+    """Indices of n requests of the batched-serving workload spread over its strata:
+    for each agent count, requests evenly spaced in N_O order (the larger share to
+    the last agent count when n is not a multiple)."""
+    shapes = config5_shapes(seed, n_scenes)
+    counts = sorted({a for _, a, _, _ in shapes})
+    per = [n // len(counts)] * len(counts)
+    per[-1] += n - sum(per)
+    pick = []
+    for a, m in zip(counts, per):
+        idx = sorted((i for i, sh in enumerate(shapes) if sh[1] == a), key=lambda i: shapes[i][0])
+        pos = np.linspace(0, len(idx) - 1, m).round().astype(int)
+        pick += [idx[p] for p in pos]
+    return sorted(pick)
 
 
 def tiny(seed: int, n_points: int = 8, n_agents: int = 4, n_steps: int = 10, moving: bool = False,

@@ -82,3 +82,68 @@ def force_bound(r):
     sitting at the hard cut-off (where FP32 and FP64 may decide rho <= r_d differently)."""
     F = np.linalg.norm(r.force, axis=1)
     return FORCE_REL * np.maximum(F, 1e-2 * r.abs_sum) + r.edge_sum
+
+
+def conditioning(pb, idx):
+    """Conditioning of the sampled agents idx (reading R24), from one oracle call that runs
+    each agent five times: nominal; its rotation vector moved by one FP32 ulp up and down in
+    every component; its circular-field gain k_f scaled by 1 +- 1e-5 (a repulsive force off
+    by the stated 1e-5 relative force tolerance at every step).
+      env_ulp[i]:   largest position change over the horizon under the one-ulp moves; above
+                    1e-4 m the agent is ill-conditioned (the exact problem does not fix its
+                    FP32 trajectory to the tolerance);
+      env_step[i, k]: largest change of p^(k) under all four perturbations: the spread of the
+                    trajectories whose every step meets the force tolerance.
+    Returns (nominal oracle rollout of idx, env_ulp [m], env_step [m, N_k + 1])."""
+    import copy
+
+    import oracle
+    idx = np.asarray(idx)
+    m = len(idx)
+    sub = copy.deepcopy(pb)
+    ag = pb.agents.subset(np.concatenate([idx] * 5))
+    w = ag.omega.astype(np.float32)
+    w[m:2 * m] = np.nextafter(w[m:2 * m], np.float32(np.inf))
+    w[2 * m:3 * m] = np.nextafter(w[2 * m:3 * m], np.float32(-np.inf))
+    ag.omega = np.ascontiguousarray(w)
+    kf = ag.k_f.astype(np.float64)
+    kf[3 * m:4 * m] *= 1.0 + 1e-5
+    kf[4 * m:] *= 1.0 - 1e-5
+    ag.k_f = kf.astype(np.float32)
+    sub.agents = ag
+    r = oracle.rollout(sub)
+    nom = copy.deepcopy(r)
+    for f in ("traj", "cost", "min_clear", "force", "vel", "ftot"):
+        setattr(nom, f, getattr(r, f)[:m])
+    dev = [np.abs(r.traj[q * m:(q + 1) * m] - r.traj[:m]).max(2) for q in range(1, 5)]
+    env_ulp = np.maximum(dev[0], dev[1]).max(1)
+    env_step = np.maximum.reduce(dev)
+    return nom, env_ulp, env_step
+
+
+def compare_conditioned(pb, gpu, idx, label=""):
+    """Sampled agents idx of a GPU rollout against the oracle, each to its own bar: the
+    well-conditioned ones (one-ulp envelope <= 1e-4 m) element-wise as compare_rollout
+    (positions 1e-4 m, costs); the ill-conditioned ones step by step within
+    max(1e-4 m, twice the largest spread of the perturbed trajectories so far).  Returns
+    (worst error of the well-conditioned agents, number of ill-conditioned agents)."""
+    nom, env_ulp, env_step = conditioning(pb, idx)
+    idx = np.asarray(idx)
+    err = np.abs(gpu["traj"][idx].astype(np.float64) - nom.traj).max(2)
+    ill = env_ulp > POS_TOL
+    # the GPU trajectory is one more member of the family the perturbations sample; past the
+    # onset of divergence the members' spread saturates at the size of the region the agent
+    # wanders in, so the bar is twice the running maximum of the sampled spread
+    bar = np.maximum(POS_TOL, 2.0 * np.maximum.accumulate(env_step, axis=1))
+    for i in np.nonzero(ill)[0]:
+        k = int(np.argmax(err[i] - bar[i]))
+        assert err[i, k] <= bar[i, k], (label, int(idx[i]), k, err[i, k], bar[i, k], env_ulp[i])
+    worst = 0.0
+    if (~ill).any():
+        import copy
+        good = np.nonzero(~ill)[0]
+        ref = copy.deepcopy(nom)
+        for f in ("traj", "cost", "min_clear", "force", "vel", "ftot"):
+            setattr(ref, f, getattr(nom, f)[good])
+        worst = compare_rollout(pb, gpu, ref, agents=idx[good])
+    return worst, int(ill.sum())

@@ -105,6 +105,15 @@ def test_voxel_keys_exact_at_faces():
     assert fp32_wrong > 0
 
 
+def test_voxel_keys_far_and_non_finite():
+    """Coordinates whose quotient lies far outside any grid (|q| >= 2^52), infinities and
+    NaN are outside the box; a point next to them still gets its cell."""
+    P = np.array([1e30, -1e30, 3e38, np.inf, -np.inf, np.nan, 0.015], np.float32)
+    z = np.zeros_like(P)
+    k, ok = op.voxel_keys(P, z, z, np.float32(0.01), [0.0, -1.0, -1.0], [10, 1000, 1000])
+    assert ok.tolist() == [False] * 6 + [True] and k[6, 0] == 1
+
+
 def test_voxel_bruteforce_small():
     """Random FP32 points (and points pushed onto faces) against an integer-arithmetic
     brute force of floor((p - lo) / s) per axis."""

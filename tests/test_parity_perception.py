@@ -100,6 +100,147 @@ def test_voxel_exact_on_oracle_points(ctx):
         assert np.array_equal(G, C)
 
 
+def _face_points(lo, s, ks):
+    """FP32 coordinates on and 1-2 FP32 steps either side of the lattice faces lo + k s."""
+    lo, s = np.float32(lo), np.float32(s)
+    out = []
+    for k in ks:
+        c = np.float32(float(lo) + k * float(s))
+        for step in (-2, -1, 0, 1, 2):
+            p = c
+            for _ in range(abs(step)):
+                p = np.nextafter(p, np.float32(np.inf if step > 0 else -np.inf))
+            out.append(p)
+    return np.array(out, np.float32)
+
+
+def test_voxel_exact_at_faces(ctx):
+    """Points on and one or two FP32 steps either side of the faces of the config-3
+    lattice (1 cm cells from a corner that is not a multiple of the voxel) and of a
+    dyadic lattice (faces representable): the kernel's cells are the exact lattice
+    cells of the oracle, bit for bit, for min_count 1 (bitmap) and 2 (counts).  An
+    FP32 quotient misplaces some of these points, so agreement is not a shared rounding."""
+    import torch
+    fr = scenes.config3_frame()
+    rng = np.random.default_rng(23)
+    for lo, s, dims in ((fr.box_lo, fr.voxel, fr.dims), (np.array([-0.5, -0.25, 0.0], np.float32), 2.0 ** -6,
+                                                        np.array([64, 40, 24], np.int32))):
+        lo = np.asarray(lo, np.float32)
+        axes = [_face_points(lo[a], s, range(-1, int(dims[a]) + 2)) for a in range(3)]
+        m = max(len(v) for v in axes)
+        P = np.stack([rng.choice(axes[a], 4 * m) for a in range(3)], 1).astype(np.float32)
+        P = np.concatenate([P, P[: len(P) // 2]])            # half the cells hold two points or more
+        q32 = np.floor((P - lo) / np.float32(s))
+        k_ex, ok = op.voxel_keys(P[:, 0], P[:, 1], P[:, 2], s, lo, dims)
+        assert (q32[ok] != k_ex[ok]).any()
+        t = [torch.as_tensor(np.ascontiguousarray(P[:, a]), device="cuda") for a in range(3)]
+        for min_count in (1, 2):
+            cells = op.voxel_cells(P[:, 0], P[:, 1], P[:, 2], s, lo, dims, min_count)
+            ox, oy, oz, n = ctx.voxel_downsample(*t, s, lo, dims, min_count=min_count, capacity=len(P))
+            torch.cuda.synchronize()
+            n = int(n.item())
+            assert n == len(cells), (min_count, n, len(cells))
+            G = np.stack([ox[:n].cpu().numpy(), oy[:n].cpu().numpy(), oz[:n].cpu().numpy()], 1)
+            assert np.array_equal(G, op.voxel_centres(cells, s, lo, dims).astype(np.float32))
+
+
+def test_voxel_large_grid_paths(ctx):
+    """Grids past the one-workgroup bitmap (2^19 cells) take the multi-block bitmap and
+    count-grid finishes: a 1024 x 1024 x 2 lattice with points in a band across it,
+    ragged point counts, min_count 1 and 3, and a capacity below the count."""
+    import torch
+    rng = np.random.default_rng(29)
+    lo, s, dims = np.array([0.0, 0.0, 0.0], np.float32), np.float32(0.001), np.array([1024, 1024, 2], np.int32)
+    for n in (1, 300001, 1 << 20):
+        P = np.stack([rng.uniform(-0.01, 1.03, n), rng.uniform(0.2, 0.21, n) * rng.integers(1, 5, n),
+                      rng.uniform(0.0, 0.0021, n)], 1).astype(np.float32)
+        P[: n // 3, 0] = rng.choice(_face_points(lo[0], s, range(0, 1024, 7)), n // 3)
+        t = [torch.as_tensor(np.ascontiguousarray(P[:, a]), device="cuda") for a in range(3)]
+        for min_count in (1, 3):
+            cells = op.voxel_cells(P[:, 0], P[:, 1], P[:, 2], s, lo, dims, min_count)
+            for cap in (len(cells), max(len(cells) // 2, 1)):
+                ox, oy, oz, m = ctx.voxel_downsample(*t, s, lo, dims, min_count=min_count, capacity=cap)
+                torch.cuda.synchronize()
+                assert int(m.item()) == len(cells), (n, min_count, int(m.item()), len(cells))
+                k = min(cap, len(cells))
+                C = op.voxel_centres(cells[:k], s, lo, dims).astype(np.float32)
+                G = np.stack([ox[:k].cpu().numpy(), oy[:k].cpu().numpy(), oz[:k].cpu().numpy()], 1)
+                assert np.array_equal(G, C), (n, min_count, cap)
+
+
+def _fused_vs_two_kernel(ctx, depth, K, T, fr, min_count=1, spheres=None, capacity=65536):
+    """gmapp_depth_to_voxels against gmapp_depth_to_points_batch + the voxel pass: identical counts
+    and centres (the same FP32 points, the same exact cells)."""
+    import torch
+    d = torch.as_tensor(np.ascontiguousarray(depth), device="cuda")
+    Td = torch.as_tensor(np.ascontiguousarray(T), device="cuda")
+    Rd = None if spheres is None else torch.as_tensor(spheres, device="cuda")
+    x, y, z = ctx.depth_to_points_batch(d, K, Td)
+    a = ctx.voxel_downsample(x, y, z, fr.voxel, fr.box_lo, fr.dims, min_count=min_count, capacity=capacity,
+                             robot_spheres=Rd)
+    b = ctx.depth_to_voxels(d, K, Td, fr.voxel, fr.box_lo, fr.dims, min_count=min_count, capacity=capacity,
+                            robot_spheres=Rd)
+    torch.cuda.synchronize()
+    n = int(a[3].item())
+    assert int(b[3].item()) == n
+    k = min(n, capacity)
+    for i in range(3):
+        assert torch.equal(a[i][:k], b[i][:k])
+    return n
+
+
+def test_depth_to_voxels_equals_two_kernel_path(ctx):
+    """The fused pass against back-projection + voxel pass, bit for bit: the config-3 frame,
+    four frames from four poses (multi-view fusion), ragged 7 x 5 frames (one pixel per
+    thread), invalid pixels, min_count 1 and 2, the robot self-filter, a capacity below
+    the count, and no frames at all."""
+    fr = scenes.config3_frame()
+    T = scenes.config3_poses(4)
+    R = scenes.robot_spheres(np.random.default_rng(9), base=(-0.3, -0.05, 0.0), tip=(0.2, 0.1, 0.3))
+    one = fr.depth[None].copy()
+    one[0, 0, :5] = [0.0, -1.0, np.nan, np.inf, 0.7]
+    four = np.stack([fr.depth, fr.depth * np.float32(1.01), fr.depth, fr.depth * np.float32(0.98)])
+    rag = np.ascontiguousarray(np.stack([fr.depth[:5, :7], fr.depth[100:105, 300:307], fr.depth[30:35, 40:47]]))
+    n1 = _fused_vs_two_kernel(ctx, one, fr.K, T[:1], fr)
+    assert n1 > 1000
+    for mc in (1, 2):
+        _fused_vs_two_kernel(ctx, four, fr.K, T, fr, min_count=mc)
+        _fused_vs_two_kernel(ctx, four, fr.K, T, fr, min_count=mc, spheres=R)
+    _fused_vs_two_kernel(ctx, rag, fr.K, T[:3], fr)
+    _fused_vs_two_kernel(ctx, four, fr.K, T, fr, capacity=100)
+    _fused_vs_two_kernel(ctx, np.zeros((0, 480, 640), np.float32), fr.K, T[:0], fr, capacity=4)
+
+
+def test_depth_to_voxels_vs_oracle(ctx):
+    """Depth image -> voxel centres in one pass against the oracle's pipeline (FP64
+    back-projection, exact lattice cells): the cells agree except where an oracle
+    point lies within 1e-5 voxel of a face (FP32 and FP64 points may straddle it);
+    those points are counted and bound the difference."""
+    import torch
+    fr = scenes.config3_frame()
+    ref_P = op.back_project(fr.depth, fr.K, fr.T_wc)
+    ref = set(op.voxel_cells(ref_P[:, 0], ref_P[:, 1], ref_P[:, 2], fr.voxel, fr.box_lo, fr.dims))
+    d = torch.as_tensor(fr.depth[None].copy(), device="cuda")
+    Td = torch.as_tensor(fr.T_wc[None].copy(), device="cuda")
+    ox, oy, oz, n = ctx.depth_to_voxels(d, fr.K, Td, fr.voxel, fr.box_lo, fr.dims, capacity=65536)
+    torch.cuda.synchronize()
+    nv = int(n.item())
+    G = np.stack([ox[:nv].cpu().numpy(), oy[:nv].cpu().numpy(), oz[:nv].cpu().numpy()], 1).astype(np.float64)
+    g_cells = np.round((G - fr.box_lo.astype(np.float64)) / fr.voxel - 0.5).astype(np.int64)
+    dims = fr.dims.astype(np.int64)
+    g_lin = (g_cells[:, 2] * dims[1] + g_cells[:, 1]) * dims[0] + g_cells[:, 0]
+    assert np.all(np.diff(g_lin) > 0)
+    q = (ref_P - fr.box_lo.astype(np.float64)) / np.float64(np.float32(fr.voxel))
+    near = np.isfinite(q).all(1) & (np.abs(q - np.round(q)) < 1e-5).any(1)
+    k, ok = op.voxel_keys(ref_P[:, 0], ref_P[:, 1], ref_P[:, 2], fr.voxel, fr.box_lo, fr.dims)
+    sure = set(((k[:, 2] * dims[1] + k[:, 1]) * dims[0] + k[:, 0])[ok & ~near])
+    assert sure <= set(g_lin)
+    diff = ref ^ set(g_lin)
+    assert len(diff) <= 2 * near.sum(), (len(diff), near.sum())
+    print(f"fused depth->voxels: gpu {nv}, oracle {len(ref)}, differing cells {len(diff)}, "
+          f"points within 1e-5 voxel of a face {near.sum()}", flush=True)
+
+
 def test_voxel_edges(ctx):
     import torch
     rng = np.random.default_rng(3)
@@ -178,32 +319,39 @@ def test_pipeline_config3(ctx):
 
 
 def test_rollout_on_device_sphere_world(ctx):
-    """The rollout reads N_O from the voxel pass's device counter (no host sync).
-    Input: the oracle's FP32 points, voxelised on the GPU (the same cells and
-    centres as the oracle's, as the exact test shows); the oracle rolls out on its
-    own centres.  256 agents at full size; the oracle checks a spread subset."""
+    """Config 3 at full size: 256 agents over 1,000 steps on the sphere world of the
+    depth frame, perceived on the GPU in one fused pass whose device count the rollout
+    reads (no host sync).  The oracle rolls out on its own centres of the frame's FP32
+    points (the GPU's cells, as the exact tests show) for 16 spread agents, each held to
+    1e-4 m or, when ill-conditioned, to its FP64 envelope (reading R24)."""
     import torch
     from paper_2606_12579_amd import gmapp
     fr = scenes.config3_frame()
-    P = op.back_project(fr.depth, fr.K, fr.T_wc).astype(np.float32)
-    cells = op.voxel_cells(P[:, 0], P[:, 1], P[:, 2], fr.voxel, fr.box_lo, fr.dims)
-    C = op.voxel_centres(cells, fr.voxel, fr.box_lo, fr.dims).astype(np.float32)
-    t = [torch.as_tensor(np.ascontiguousarray(P[:, a]), device="cuda") for a in range(3)]
-    ox, oy, oz, n = ctx.voxel_downsample(*t, fr.voxel, fr.box_lo, fr.dims, capacity=32768)
-    agents, q, prm = scenes.config3_agents(n_agents=256, n_steps=120)
+    d = torch.as_tensor(fr.depth[None].copy(), device="cuda")
+    Td = torch.as_tensor(fr.T_wc[None].copy(), device="cuda")
+    ox, oy, oz, n = ctx.depth_to_voxels(d, fr.K, Td, fr.voxel, fr.box_lo, fr.dims, capacity=32768)
+    agents, q, prm = scenes.config3_agents(n_agents=256, n_steps=1000)
     sc = gmapp.DeviceScene(ox, oy, oz, scenes.R_OBS, n_points_dev=n)
     ag = gmapp.agents_to_device(agents)
     ctx.clear_tiling()
     out = ctx.rollout(sc, ag, q, prm)
     torch.cuda.synchronize()
+    nv = int(n.item())
+    G = np.stack([ox[:nv].cpu().numpy(), oy[:nv].cpu().numpy(), oz[:nv].cpu().numpy()], 1)
+    # the GPU's sphere world: the FP32 points' cells from the depth image (FP32 back-projection)
+    gp = np.stack([a.cpu().numpy() for a in ctx.depth_to_points(torch.as_tensor(fr.depth, device="cuda"), fr.K,
+                                                                 fr.T_wc)], 1)
+    cells = op.voxel_cells(gp[:, 0], gp[:, 1], gp[:, 2], fr.voxel, fr.box_lo, fr.dims)
+    C = op.voxel_centres(cells, fr.voxel, fr.box_lo, fr.dims).astype(np.float32)
+    assert np.array_equal(G, C)
     idx = np.arange(0, 256, 16)
-    pb = scenes.Problem(scenes.Scene(C[:, 0].copy(), C[:, 1].copy(), C[:, 2].copy(), scenes.R_OBS),
-                        agents.subset(idx), q, prm)
-    ref = oracle.rollout(pb)
-    gpu = {"traj": out["traj"].cpu().numpy()[idx], "cost": out["cost"].cpu().numpy()[idx],
-           "min_clear": out["min_clear"].cpu().numpy()[idx], "best": int(out["best"].item())}
-    err = gu.compare_rollout(pb, gpu, ref)
-    print(f"config3 rollout on {len(C)} voxel centres: pos err {err:.2e}", flush=True)
+    pb = scenes.Problem(scenes.Scene(C[:, 0].copy(), C[:, 1].copy(), C[:, 2].copy(), scenes.R_OBS), agents, q, prm)
+    gpu = {"traj": out["traj"].cpu().numpy(), "cost": out["cost"].cpu().numpy(),
+           "min_clear": out["min_clear"].cpu().numpy()}
+    worst, n_ill = gu.compare_conditioned(pb, gpu, idx, "config3")
+    assert 0 <= int(out["best"].item()) < 256
+    print(f"config3 rollout, 256 agents x 1000 steps on {len(C)} voxel centres: pos err {worst:.2e} "
+          f"({n_ill} of {len(idx)} sampled agents ill-conditioned)", flush=True)
 
 
 def test_batched_rollout_on_device_sphere_world(ctx):

@@ -525,7 +525,7 @@ def serving(ctx, reqs, quantum=50, budget=8 << 30):
             "peak_device_bytes": st["peak_bytes"], "fault": st["fault"]}
 
 
-def main():
+def run():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
@@ -668,6 +668,27 @@ def main():
         res["cpu_baseline"]["per_row"] = cpu_baseline_rows(
             [k for k in ("heterogeneous", "pose", "arm", "closed_loop", "perception", "adjoint") if k in res])
     ctx.close()
+    return res
+
+
+def release_gpu_resources():
+    """Free every GPU and pinned-host resource of the run while the HIP runtime (and a
+    profiler that wraps it) is still alive: after run() returns its tensors, events and
+    library objects are unreferenced; collect them now, then empty torch's device cache and
+    its pinned-host cache, whose blocks would otherwise be freed by static destructors
+    at process exit, after a profiler's own finalisation."""
+    import gc
+
+    import torch
+    gc.collect()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    torch._C._host_emptyCache()
+
+
+def main():
+    res = run()
+    release_gpu_resources()
     print(json.dumps(res), flush=True)
 
 

@@ -126,8 +126,8 @@ typedef struct {
  * rho_min^(k+1), the smallest clamped surface distance at step k+1 (+inf when the
  * scene is empty); best[0] = i*, or -1 when N_a = 0, or GMAPP_ETIMEOUT when an
  * exchange wait of a sharded launch stalled past the watchdog limit
- * (gmapp_set_watchdog), or GMAPP_ECANCELLED when the host's abort word ended it
- * (gmapp_abort, gmapp_wait); the other outputs of such a launch are undefined.
+ * (gmapp_set_watchdog), or GMAPP_ECANCELLED when the host's abort word ended a
+ * wait (gmapp_abort, gmapp_wait); the other outputs of such a launch are undefined.
  * traj and min_clear may be NULL. */
 typedef struct {
     float *traj;      /* device [N_a][N_k + 1][3] or NULL */
@@ -275,18 +275,23 @@ typedef struct {
 /* Failure handling of the persistent launches (no passage of the paper: the one
  * failure rule it has is the perception buffer's frame time-out, Sec. V-A).  A
  * sharded rollout, adjoint or control launch exchanges partial sums between
- * workgroups every step; each exchange wait is bounded:
- *  - gmapp_set_watchdog: the longest a single wait may go without its words
- *    arriving (seconds; 0 = the default 4 s; EINVAL outside (0, 3600]).  The clock
- *    restarts with every wait, so a long launch is never cut short while it makes
- *    progress.  A stalled wait ends the launch: best = GMAPP_ETIMEOUT, gradients NaN.
+ * workgroups every step, and every exchange wait is bounded.  A wait that finds its
+ * words missing checks, every 64th poll (every poll with a limit below 1 ms), whether
+ * another wave already ended a wait, whether the host raised the abort word, and
+ * whether it has made no progress for longer than the watchdog limit; if so it ends,
+ * and so do all later waits of the launch, which then runs its remaining steps
+ * without waiting and reports best = GMAPP_ETIMEOUT (limit) or GMAPP_ECANCELLED
+ * (abort), or NaN gradients.  Waits that are answered promptly are never
+ * interrupted, so a launch that makes progress runs to its end.
+ *  - gmapp_set_watchdog: the limit in seconds (0 = the default 4 s; EINVAL outside
+ *    (0, 3600]) for launches enqueued afterwards.  The clock restarts with every
+ *    wait, so a long launch is never cut short while it makes progress.
  *  - gmapp_abort(raise = 1): raises the context's abort word, a pinned host word the
- *    waits poll; every wait of the running and of later launches on this context
- *    then ends (best = GMAPP_ECANCELLED, gradients NaN) until gmapp_abort(raise = 0).
- *    May be called from any host thread while a launch runs.
+ *    waits read, for the running and later launches on this context, until
+ *    gmapp_abort(raise = 0).  May be called from any host thread while a launch runs.
  *  - gmapp_wait: waits up to timeout_s seconds for `stream`; past that it raises the
- *    abort word, waits for the launches to drain, lowers it again and returns
- *    GMAPP_ETIMEOUT.  A launch that never waits (one shard) runs to its end. */
+ *    abort word, so that no wait of the stream's launches can hang, waits for them
+ *    to drain, lowers it again and returns GMAPP_ETIMEOUT. */
 gmapp_status gmapp_set_watchdog(gmapp_ctx *ctx, double seconds);
 gmapp_status gmapp_abort(gmapp_ctx *ctx, int32_t raise);
 gmapp_status gmapp_wait(gmapp_ctx *ctx, void *stream, double timeout_s);

@@ -279,23 +279,17 @@ __global__ __launch_bounds__(64 * W) void k_adjoint(Scn sc, Agt ag, Prm pr, AdjO
                         xc.partial + (((size_t)((tag & 1) * G + g) * S + l / AW) * AW + l % AW) * kAdjWords;
                     unsigned long long q[kAdjWords] = {};
                     unsigned spins = 0;
-                    const bool probe_abort = xc.abort && !failed && (tag % kAbortPeriod) == 0;
-                    const unsigned ab = probe_abort ? ld_system(xc.abort) : 0u;
-                    const unsigned long long t_wait = __builtin_amdgcn_s_memrealtime();
+                    unsigned long long t_wait = xc.fine ? __builtin_amdgcn_s_memrealtime() : 0ull;
                     while (!failed) {                // all words of the slot in flight together
                         bool all = true;
                         for (int i = 0; i < nw; ++i) q[i] = ld64_agent(slot + i);
                         for (int i = 0; i < nw; ++i) all = all && xtag(q[i]) == tag;
                         if (all) break;
                         __builtin_amdgcn_s_sleep(2);
-                        if (wait_expired(xc, t_wait, ++spins)) {
+                        if (((++spins & 63u) == 0 || xc.fine) && slow_check(xc, t_wait, spins)) {
                             failed = true;
                             break;
                         }
-                    }
-                    if (ab != 0u) {                  // the host's abort word
-                        st_agent(xc.status, 2u);
-                        failed = true;
                     }
                     for (int i = 0; i < nsum + 1; ++i)
                         xt[l * 4 + i] = make_float4(xval(q[4 * i]), xval(q[4 * i + 1]), xval(q[4 * i + 2]),

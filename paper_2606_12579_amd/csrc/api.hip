@@ -148,6 +148,17 @@ gm::Tiling tiling_for(gmapp_ctx *ctx, long long n_points, int n_agents, int n_st
     return t;
 }
 
+// the exchange waits' limit and the device address of the abort word, in the words after
+// the status word (a synchronous copy: launches enqueued afterwards see them)
+gmapp_status write_wait_settings(gmapp_ctx *ctx)
+{
+    unsigned long long v[2] = {ctx->watchdog_ticks, (unsigned long long)reinterpret_cast<uintptr_t>(ctx->abort_word)};
+    unsigned *dst = ctx->sync + gm::kCounterWords + 16 + gm::kWaitLimitWord;
+    const hipError_t e = hipMemcpy(dst, v, sizeof v, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return gm::hip_fail(ctx, e, "hipMemcpy(wait settings)");
+    return GMAPP_OK;
+}
+
 // lattice and self-filter arguments of the voxel pass
 gmapp_status voxel_grid(gmapp_ctx *ctx, float voxel, const float lo[3], const int32_t dims[3], int32_t min_count,
                         const float *robot_spheres, int32_t n_spheres, gm::VoxGrid &g)
@@ -224,7 +235,7 @@ gmapp_status gmapp_create(int32_t device, size_t workspace_bytes, gmapp_ctx **ou
     }
     ctx->abort_word = static_cast<unsigned *>(dw);
     hipLaunchKernelGGL(k_fill_u32, dim3(256), dim3(256), 0, nullptr, ctx->sync, fixed / sizeof(unsigned), 0u);
-    if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+    if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess || write_wait_settings(ctx)) {
         (void)hipHostFree(hw);
         (void)hipFree(p);
         delete ctx;
@@ -261,7 +272,7 @@ gmapp_status gmapp_set_watchdog(gmapp_ctx *ctx, double seconds)
     if (!std::isfinite(seconds) || seconds < 0.0 || seconds > 3600.0)
         return fail(ctx, GMAPP_EINVAL, "watchdog limit must be in (0, 3600] s (0 = the default 4 s)");
     ctx->watchdog_ticks = std::max<unsigned long long>(1ull, (unsigned long long)(seconds * 1e8));
-    return GMAPP_OK;
+    return write_wait_settings(ctx);
 }
 
 gmapp_status gmapp_abort(gmapp_ctx *ctx, int32_t raise)

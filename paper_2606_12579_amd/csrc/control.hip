@@ -203,9 +203,7 @@ __global__ __launch_bounds__(kCtlThreads) void k_control(Scn sc, Agt ag, Prm pr,
                 unsigned long long q0 = 0, q1 = 0, q2 = 0, q3 = 0;
                 const bool poller = lane < NG;
                 unsigned spins = 0;
-                const bool probe_abort = xc.abort && (tag % kAbortPeriod) == 0;
-                const unsigned ab = probe_abort ? ld_system(xc.abort) : 0u;
-                const unsigned long long t_wait = __builtin_amdgcn_s_memrealtime();
+                unsigned long long t_wait = xc.fine ? __builtin_amdgcn_s_memrealtime() : 0ull;
                 while (true) {
                     if (poller) {
                         const unsigned long long *slot = area + 4 * lane;
@@ -215,14 +213,10 @@ __global__ __launch_bounds__(kCtlThreads) void k_control(Scn sc, Agt ag, Prm pr,
                     const bool mine = !poller || (xtag(q0) == tag && xtag(q1) == tag && xtag(q2) == tag &&
                                                   xtag(q3) == tag);
                     if (__all(mine)) break;
-                    if (wait_expired(xc, t_wait, ++spins)) {
+                    if (((++spins & 63u) == 0 || xc.fine) && slow_check(xc, t_wait, spins)) {
                         failed = true;
                         break;
                     }
-                }
-                if (ab != 0u) {                      // the host's abort word
-                    if (lane == 0) st_agent(xc.status, 2u);
-                    failed = true;
                 }
                 float sx = poller ? xval(q0) : 0.f, sy = poller ? xval(q1) : 0.f;
                 float sz = poller ? xval(q2) : 0.f, sm = poller ? xval(q3) : INFINITY;

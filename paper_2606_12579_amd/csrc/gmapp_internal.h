@@ -71,11 +71,15 @@ struct Xch {
     unsigned long long *partial;  // [2][wave groups][S][AW][4] words: Fx, Fy, Fz, min r2, each | step tag << 32
     unsigned *flags;     // spare counters (zero between launches)
     unsigned *done;      // [1]       finished-workgroup counter, zero between launches
-    unsigned *status;    // [1]       0 ok, 1 a wait ran out of time, 2 aborted by the host; zero between launches
+    unsigned *status;    // [1]       0 ok, 1 a wait ran out of time, 2 aborted by the host; zero between launches;
+                         //           followed by the wait settings (kWaitLimitWord, kAbortAddrWord)
     int S, G;
-    unsigned long long limit = 400000000ull;   // longest wait without progress, in 100 MHz real-time ticks
-    const unsigned *abort = nullptr;           // host abort word (pinned, mapped) or nullptr
+    int fine;            // 1: check the wait limit from a wait's first failed poll (limits below 1 ms)
 };
+// wait settings after the status word, set by the host: the longest wait without progress
+// (u64, 100 MHz real-time ticks) and the device address of the host's abort word (u64)
+constexpr int kWaitLimitWord = 8;
+constexpr int kAbortAddrWord = 10;
 
 // camera-to-world transform, row-major 3x4 [R | t]
 struct Mat34 {
@@ -118,7 +122,7 @@ constexpr size_t kCounterWords = (size_t)kMaxGroups * 16;
 constexpr size_t kSyncWords = kCounterWords + 64;     // counters + done + status (+ pad)
 constexpr size_t kXchgBytes = (size_t)16 << 20;       // rollout exchange area
 // sync words [0, kCounterWords): per-job completion counters of the batched launch;
-// kCounterWords: rollout done counter; +16: watchdog status; +32, +33: batch queue
+// kCounterWords: rollout done counter; +16: watchdog status; +24..27: wait settings; +32, +33: batch queue
 constexpr size_t kBatchQueueWord = kCounterWords + 32;
 constexpr int kMaxBatchJobs = 16384;
 constexpr int kBatchWaves = 8;                        // waves per workgroup of the batched kernel
@@ -184,8 +188,8 @@ struct gmapp_ctx {
     gmapp_batch_tuning batch_tuned_tuning{0, 0, 0, 0};
     unsigned *vgrid = nullptr;    // voxel grid (bitmap or counts), all zero between calls
     size_t vgrid_words = 0;
-    unsigned *vbsum = nullptr;    // per-block occupied-cell counts of the voxel pass
-    size_t vbsum_words = 0;
+    unsigned *vbsum = nullptr;    // voxel pass: per-block occupied-cell counts, then per-block dirty bytes
+    size_t vbsum_blocks = 0;      // blocks the table holds (the dirty bytes start after that many counts)
     unsigned long long watchdog_ticks = 400000000ull;   // per-wait limit of the exchanges (4 s)
     unsigned *abort_host = nullptr;   // pinned, coherent host word: nonzero ends every exchange wait
     unsigned *abort_word = nullptr;   // its device address
@@ -219,7 +223,7 @@ inline gmapp_status hip_fail(gmapp_ctx *ctx, hipError_t e, const char *what)
         if (e_ != hipSuccess) return gm::hip_fail(ctx, e_, #call); \
     } while (0)
 
-// the context's exchange area, watchdog limit and abort word for a sharded launch
+// the context's exchange area and status word for a sharded launch
 inline Xch make_xch(gmapp_ctx *ctx, int S, int G)
 {
     Xch xc;
@@ -229,8 +233,7 @@ inline Xch make_xch(gmapp_ctx *ctx, int S, int G)
     xc.status = ctx->sync + kCounterWords + 16;
     xc.S = S;
     xc.G = G;
-    xc.limit = ctx->watchdog_ticks;
-    xc.abort = ctx->abort_word;
+    xc.fine = ctx->watchdog_ticks < 100000ull ? 1 : 0;
     return xc;
 }
 

@@ -102,27 +102,38 @@ __device__ __forceinline__ unsigned ld_system(const unsigned *p)
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
-// Every kAbortPeriod-th exchange a wait also reads the host's abort word: the load
-// is issued before the poll and consumed after it, so its latency mostly hides
-// under the exchange's own.
-constexpr unsigned kAbortPeriod = 64;
-
-// Check inside a bounded exchange wait that started at t_wait (real-time clock,
-// 100 MHz), made after every poll that found the words incomplete: true when the
-// wait must end -- it has gone on for longer than the limit without its words
-// arriving (status 1), or, every 64th poll, another wave already ended one
-// (status != 0) or the host raised the abort word (status 2).  The clock restarts
-// with every wait, so only a stall, not the length of a launch, trips it.
-__device__ __forceinline__ bool wait_expired(const Xch &xc, unsigned long long t_wait, unsigned spins)
+// The wait settings, read from device memory when a wait needs them (they sit after the
+// status word), so that they hold no registers across the step loop.
+__device__ __forceinline__ unsigned long long wait_limit(const Xch &xc)
 {
-    if (__builtin_amdgcn_s_memrealtime() - t_wait > xc.limit) {
-        st_agent(xc.status, 1u);
+    return *reinterpret_cast<const unsigned long long *>(xc.status + kWaitLimitWord);
+}
+__device__ __forceinline__ const unsigned *abort_addr(const Xch &xc)
+{
+    return *reinterpret_cast<const unsigned *const *>(xc.status + kAbortAddrWord);
+}
+
+// The slow path of an exchange wait, taken every 64th poll that finds the words
+// incomplete (every poll when xc.fine, i.e. limits below 1 ms): true when the wait
+// must end -- another wave already ended one (status != 0), the host raised the abort
+// word (status 2), or the wait has made no progress for longer than the limit (status
+// 1).  The clock restarts with every wait: in the usual mode the wait's clock starts at
+// its first slow check (t_wait = 0 until then), with xc.fine at the wait's start.  So
+// only a stall, never the length of a launch, trips it; a wait that completes within
+// 64 polls reads neither clock nor settings.
+__device__ __forceinline__ bool slow_check(const Xch &xc, unsigned long long &t_wait, unsigned spins)
+{
+    if (ld_agent(xc.status) != 0u) return true;
+    const unsigned *a = abort_addr(xc);
+    if (a && ld_system(a) != 0u) {
+        st_agent(xc.status, 2u);
         return true;
     }
-    if ((spins & 63u) != 0) return false;
-    if (ld_agent(xc.status) != 0u) return true;
-    if (xc.abort && ld_system(xc.abort) != 0u) {
-        st_agent(xc.status, 2u);
+    const unsigned long long now = __builtin_amdgcn_s_memrealtime();
+    if (!xc.fine && spins == 64) {
+        t_wait = now;
+    } else if (now - t_wait > wait_limit(xc)) {
+        st_agent(xc.status, 1u);
         return true;
     }
     return false;

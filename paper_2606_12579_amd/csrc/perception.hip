@@ -216,10 +216,18 @@ __device__ __forceinline__ unsigned wave_sum(unsigned x)
 //   counts: the lanes holding the lowest pending lane's cell add their points across the
 //     wave and that lane issues one atomic add; repeat until no cell is left (neighbouring
 //     points mostly share a cell, so the atomics, serialised per address, stay few).
-template <bool COUNT>
-__device__ __forceinline__ void wave_mark(int cell, unsigned cnt, unsigned *__restrict__ grid)
+template <bool COUNT, bool FLAG = true>
+__device__ __forceinline__ void wave_mark(int cell, unsigned cnt, unsigned *__restrict__ grid,
+                                          unsigned char *__restrict__ dirty)
 {
     if constexpr (!COUNT) {
+        // the block's dirty byte is stored by the first lane of each run of lanes in one
+        // block (FLAG = false: the caller flags the blocks itself)
+        if constexpr (FLAG) {
+            const int blk = cell >= 0 ? (int)((unsigned)cell / kCellBlock) : -1;
+            const int prev = __builtin_amdgcn_update_dpp(-2, blk, 0x111, 0xF, 0xF, false);   // row_shr:1
+            if (cell >= 0 && prev != blk) dirty[blk] = 1;
+        }
         if (cell >= 0) reinterpret_cast<unsigned char *>(grid)[(unsigned)cell] = 1;
     } else {
         const int lane = threadIdx.x & 63;
@@ -229,7 +237,10 @@ __device__ __forceinline__ void wave_mark(int cell, unsigned cnt, unsigned *__re
             const int c0 = __builtin_amdgcn_readlane(cell, leader);
             const bool mine = cell == c0;
             const unsigned v = wave_sum(mine ? cnt : 0u);
-            if (lane == leader) atomicAdd(&grid[(unsigned)c0], v);
+            if (lane == leader) {
+                atomicAdd(&grid[(unsigned)c0], v);
+                dirty[(unsigned)c0 / kCellBlock] = 1;
+            }
             pending &= ~__ballot(mine);
             if (mine) cell = -1;
         }
@@ -241,7 +252,7 @@ __device__ __forceinline__ void wave_mark(int cell, unsigned cnt, unsigned *__re
 // entry (uniform control flow, static indexing).
 template <bool COUNT>
 __device__ __forceinline__ void mark4(const float (&X)[4], const float (&Y)[4], const float (&Z)[4], bool live,
-                                      const VoxGrid &g, unsigned *__restrict__ grid)
+                                      const VoxGrid &g, unsigned *__restrict__ grid, unsigned char *__restrict__ dirty)
 {
     int c[4];
     unsigned n[4];
@@ -256,21 +267,40 @@ __device__ __forceinline__ void mark4(const float (&X)[4], const float (&Y)[4], 
             n[r - 1] += n[r];
             c[r] = -1;
         }
+    if constexpr (!COUNT) {
+        // dirty bytes of the thread's blocks (its four points nearly always share one): each
+        // block the thread marks after a different one is flagged, the first one only when the
+        // previous lane's last block differs
+        int first = -1, lastb = -1;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) wave_mark<COUNT>(c[r], n[r], grid);
+        for (int r = 0; r < 4; ++r) {
+            if (c[r] < 0) continue;
+            const int b = (int)((unsigned)c[r] / kCellBlock);
+            if (first < 0) first = b;
+            else if (b != lastb) dirty[b] = 1;
+            lastb = b;
+        }
+        const int prev = __builtin_amdgcn_update_dpp(-2, lastb, 0x111, 0xF, 0xF, false);   // row_shr:1
+        if (first >= 0 && first != prev) dirty[first] = 1;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) wave_mark<COUNT, false>(c[r], n[r], grid, dirty);
+    } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) wave_mark<COUNT>(c[r], n[r], grid, dirty);
+    }
 }
 
 // points, one per thread (the loop trip count is uniform across the wave)
 template <bool COUNT>
 __global__ __launch_bounds__(256) void k_mark(const float *__restrict__ x, const float *__restrict__ y,
                                               const float *__restrict__ z, long long n, VoxGrid g,
-                                              unsigned *__restrict__ grid)
+                                              unsigned *__restrict__ grid, unsigned char *__restrict__ dirty)
 {
     const long long stride = (long long)gridDim.x * blockDim.x;
     const long long wbase = blockIdx.x * (long long)blockDim.x + (threadIdx.x & ~63);
     for (long long w0 = wbase; w0 < n; w0 += stride) {
         const long long i = w0 + (threadIdx.x & 63);
-        wave_mark<COUNT>(i < n ? mark_cell(x[i], y[i], z[i], g) : -1, 1u, grid);
+        wave_mark<COUNT>(i < n ? mark_cell(x[i], y[i], z[i], g) : -1, 1u, grid, dirty);
     }
 }
 
@@ -282,7 +312,7 @@ __global__ __launch_bounds__(256) void k_mark_v4(const float4 *__restrict__ x4, 
                                                  const float4 *__restrict__ z4, long long n4,
                                                  const float *__restrict__ x, const float *__restrict__ y,
                                                  const float *__restrict__ z, long long n, VoxGrid g,
-                                                 unsigned *__restrict__ grid)
+                                                 unsigned *__restrict__ grid, unsigned char *__restrict__ dirty)
 {
     const long long stride = (long long)gridDim.x * blockDim.x;
     const long long tid = blockIdx.x * (long long)blockDim.x + threadIdx.x;
@@ -297,11 +327,11 @@ __global__ __launch_bounds__(256) void k_mark_v4(const float4 *__restrict__ x4, 
             Y[0] = b.x; Y[1] = b.y; Y[2] = b.z; Y[3] = b.w;
             Z[0] = c.x; Z[1] = c.y; Z[2] = c.z; Z[3] = c.w;
         }
-        mark4<COUNT>(X, Y, Z, live, g, grid);
+        mark4<COUNT>(X, Y, Z, live, g, grid, dirty);
     }
     if (wbase == 0) {
         const long long t = 4 * n4 + tid;
-        wave_mark<COUNT>(t < n ? mark_cell(x[t], y[t], z[t], g) : -1, 1u, grid);
+        wave_mark<COUNT>(t < n ? mark_cell(x[t], y[t], z[t], g) : -1, 1u, grid, dirty);
     }
 }
 
@@ -325,7 +355,8 @@ __device__ __forceinline__ void pixel_of(long long p, int w, int wh, int &f, int
 // 16-byte depth load (w h divisible by 4, depth 16-byte aligned)
 template <bool COUNT>
 __global__ __launch_bounds__(256) void k_mark_depth_v4(const float4 *__restrict__ depth, long long n4, Cam cam,
-                                                       VoxGrid g, unsigned *__restrict__ grid)
+                                                       VoxGrid g, unsigned *__restrict__ grid,
+                                                       unsigned char *__restrict__ dirty)
 {
     const int wh = cam.w * cam.h;
     const long long stride = (long long)gridDim.x * blockDim.x;
@@ -346,14 +377,14 @@ __global__ __launch_bounds__(256) void k_mark_depth_v4(const float4 *__restrict_
                 if (++u == cam.w) { u = 0; ++v; }
             }
         }
-        mark4<COUNT>(X, Y, Z, live, g, grid);
+        mark4<COUNT>(X, Y, Z, live, g, grid, dirty);
     }
 }
 
 // fused, any shape: one pixel per thread
 template <bool COUNT>
 __global__ __launch_bounds__(256) void k_mark_depth(const float *__restrict__ depth, long long n, Cam cam, VoxGrid g,
-                                                    unsigned *__restrict__ grid)
+                                                    unsigned *__restrict__ grid, unsigned char *__restrict__ dirty)
 {
     const int wh = cam.w * cam.h;
     const long long stride = (long long)gridDim.x * blockDim.x;
@@ -368,7 +399,7 @@ __global__ __launch_bounds__(256) void k_mark_depth(const float *__restrict__ de
             back_project(u, v, depth[p], cam.fx, cam.fy, cam.cx, cam.cy, cam.T + 12 * (size_t)f, X, Y, Z);
             c = mark_cell(X, Y, Z, g);
         }
-        wave_mark<COUNT>(c, 1u, grid);
+        wave_mark<COUNT>(c, 1u, grid, dirty);
     }
 }
 
@@ -433,19 +464,6 @@ __device__ __forceinline__ unsigned block_excl_scan(unsigned c, unsigned *wsum, 
     return before + incl - c;
 }
 
-// Block b's first output position.  local: the block adds the counts of the blocks
-// before it itself (few blocks: no separate scan launch), and the last block writes
-// the total; otherwise bsum already holds the exclusive scan.
-__device__ __forceinline__ long long block_offset(const unsigned *__restrict__ bsum, bool local, unsigned blk_total,
-                                                  long long *__restrict__ n_out, unsigned *wsum)
-{
-    if (!local) return (long long)bsum[blockIdx.x];
-    unsigned acc = 0;
-    for (unsigned i = threadIdx.x; i < blockIdx.x; i += 256) acc += bsum[i];
-    const unsigned before = block_sum<256>(acc, wsum);
-    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *n_out = (long long)before + blk_total;
-    return (long long)before;
-}
 
 // The four cells [base, base + 4) of a thread in the finish: their occupancy (bit q)
 // and whether any of them was marked.  Occupancy grid: one 32-bit load of 4 bytes;
@@ -478,12 +496,18 @@ __device__ __forceinline__ void clear4(unsigned *__restrict__ grid, long long ba
 
 // finish, pass 1: occupied cells per block of kCellBlock cells (4 per thread)
 template <bool COUNT>
-__global__ __launch_bounds__(256) void k_block_cells(const unsigned *__restrict__ grid, unsigned min_count,
+__global__ __launch_bounds__(256) void k_block_cells(const unsigned *__restrict__ grid,
+                                                     const unsigned char *__restrict__ dirty, unsigned min_count,
                                                      unsigned *__restrict__ bsum)
 {
     __shared__ unsigned wsum[4];
+    if (!dirty[blockIdx.x]) {                     // no point marked a cell of this block
+        if (threadIdx.x == 0) bsum[blockIdx.x] = 0u;
+        return;
+    }
     bool marked;
-    const unsigned occ = cells4<COUNT>(grid, (long long)blockIdx.x * kCellBlock + threadIdx.x * 4, min_count, marked);
+    const unsigned occ = cells4<COUNT>(grid, (long long)blockIdx.x * kCellBlock + threadIdx.x * 4, min_count,
+                                       marked);
     const unsigned t = block_sum<256>(__popc(occ), wsum);
     if (threadIdx.x == 0) bsum[blockIdx.x] = t;
 }
@@ -508,29 +532,51 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(unsigned *__restrict__ bsu
 
 // finish, pass 2: the block's occupied cells are compacted in LDS in cell order (local
 // scan), then written out as centres by consecutive threads (coalesced stores); every
-// marked cell read is cleared.
+// marked cell read, and the block's dirty flag, are cleared.  Clean blocks write
+// nothing (the last one still reports the total in local mode).
 template <bool COUNT>
-__global__ __launch_bounds__(256) void k_write_cells(unsigned *__restrict__ grid, unsigned min_count,
-                                                     const unsigned *__restrict__ bsum, int local,
+__global__ __launch_bounds__(256) void k_write_cells(unsigned *__restrict__ grid, unsigned char *__restrict__ dirty,
+                                                     unsigned min_count, const unsigned *__restrict__ bsum, int local,
                                                      long long *__restrict__ n_out, VoxGrid g, float *__restrict__ ox,
                                                      float *__restrict__ oy, float *__restrict__ oz, long long capacity)
 {
     __shared__ unsigned wsum[16];
     __shared__ unsigned short cellbuf[kCellBlock];
-    const long long base = (long long)blockIdx.x * kCellBlock + threadIdx.x * 4;
-    bool marked;
-    unsigned occ = cells4<COUNT>(grid, base, min_count, marked);
+    const unsigned b = blockIdx.x, tid = threadIdx.x;
+    const bool d = dirty[b] != 0;
+    const bool last = b == gridDim.x - 1;
+    if (!d && !(local && last)) return;
+    // the block's first position: the counts of the blocks before it (local: up to
+    // kLocalBlocks of them, 4 per thread, loaded together with the grid) or the scanned table
+    unsigned before = 0;
+    if (local) {
+#pragma unroll
+        for (unsigned q = 0; q < kLocalBlocks / 256; ++q) {
+            const unsigned i = tid + 256 * q;
+            before += i < b ? bsum[i] : 0u;
+        }
+    }
+    const long long base = (long long)b * kCellBlock + tid * 4;
+    bool marked = false;
+    unsigned occ = d ? cells4<COUNT>(grid, base, min_count, marked) : 0u;
     unsigned total;
     unsigned at = block_excl_scan<256>(__popc(occ), wsum, total);
-    const long long pos0 = block_offset(bsum, local != 0, total, n_out, wsum + 4);
+    long long pos0;
+    if (local) {
+        pos0 = (long long)block_sum<256>(before, wsum + 4);
+        if (last && tid == 0) *n_out = pos0 + total;
+    } else {
+        pos0 = (long long)bsum[b];
+    }
     if (marked) clear4(grid, base, COUNT);
+    if (d && tid == 0) dirty[b] = 0;              // every thread read it before the scan's barriers
     while (occ) {
-        cellbuf[at++] = (unsigned short)(4 * threadIdx.x + (unsigned)(__ffs(occ) - 1));
+        cellbuf[at++] = (unsigned short)(4 * tid + (unsigned)(__ffs(occ) - 1));
         occ &= occ - 1u;
     }
     __syncthreads();
-    const unsigned cbase = (unsigned)((long long)blockIdx.x * kCellBlock);
-    for (unsigned j = threadIdx.x; j < total; j += 256) {
+    const unsigned cbase = b * (unsigned)kCellBlock;
+    for (unsigned j = tid; j < total; j += 256) {
         const long long pos = pos0 + j;
         if (pos < capacity) write_centre(cell_coords(cbase + cellbuf[j], g), g, pos, ox, oy, oz);
     }
@@ -579,7 +625,7 @@ namespace {
 
 template <bool COUNT>
 void launch_mark(gmapp_ctx *ctx, const float *x, const float *y, const float *z, long long n, const Cam *cam,
-                 const VoxGrid &g, unsigned *grid, hipStream_t stream)
+                 const VoxGrid &g, unsigned *grid, unsigned char *dirty, hipStream_t stream)
 {
     if (n == 0) return;
     // four points (pixels) per thread only when the quads still give every SIMD two waves;
@@ -591,10 +637,10 @@ void launch_mark(gmapp_ctx *ctx, const float *x, const float *y, const float *z,
             const long long n4 = n / 4;
             const int pb = (int)std::min<long long>((n4 + 255) / 256, 16384);
             hipLaunchKernelGGL(k_mark_depth_v4<COUNT>, dim3(pb), dim3(256), 0, stream,
-                               reinterpret_cast<const float4 *>(x), n4, *cam, g, grid);
+                               reinterpret_cast<const float4 *>(x), n4, *cam, g, grid, dirty);
         } else {
             const int pb = (int)std::min<long long>((n + 255) / 256, 16384);
-            hipLaunchKernelGGL(k_mark_depth<COUNT>, dim3(pb), dim3(256), 0, stream, x, n, *cam, g, grid);
+            hipLaunchKernelGGL(k_mark_depth<COUNT>, dim3(pb), dim3(256), 0, stream, x, n, *cam, g, grid, dirty);
         }
         return;
     }
@@ -603,31 +649,77 @@ void launch_mark(gmapp_ctx *ctx, const float *x, const float *y, const float *z,
         const int pb = (int)std::min<long long>((n4 + 255) / 256, 16384);
         hipLaunchKernelGGL(k_mark_v4<COUNT>, dim3(pb), dim3(256), 0, stream, reinterpret_cast<const float4 *>(x),
                            reinterpret_cast<const float4 *>(y), reinterpret_cast<const float4 *>(z), n4, x, y, z, n,
-                           g, grid);
+                           g, grid, dirty);
     } else {
         const int pb = (int)std::min<long long>((n + 255) / 256, 8192);
-        hipLaunchKernelGGL(k_mark<COUNT>, dim3(pb), dim3(256), 0, stream, x, y, z, n, g, grid);
+        hipLaunchKernelGGL(k_mark<COUNT>, dim3(pb), dim3(256), 0, stream, x, y, z, n, g, grid, dirty);
     }
 }
 
 }  // namespace
 
-// The grid stays all-zero between calls: it is zero-filled when (re)allocated, and
-// every finish kernel clears what the marking set.
-gmapp_status launch_voxel_downsample(gmapp_ctx *ctx, const float *x, const float *y, const float *z, long long n,
-                                     const Cam *cam, const VoxGrid &g_in, unsigned min_count, float *ox, float *oy,
-                                     float *oz, long long capacity, long long *n_out_dev, hipStream_t stream)
+namespace {
+
+VoxGrid with_derived(const VoxGrid &g_in)
 {
     VoxGrid g = g_in;
     for (int a = 0; a < 3; ++a) g.lod[a] = (double)g.lo[a];
     g.sd = (double)g.voxel;
     g.inv_s = 1.0 / g.sd;
     g.inv_s32 = 1.0f / g.voxel;
-    const long long cells = (long long)g.dims[0] * g.dims[1] * g.dims[2];
-    const bool counts = min_count > 1;
-    const long long nb = (cells + kCellBlock - 1) / kCellBlock;
-    // whole blocks of u32 words: 1 per cell (counts) or 1 per 4 cells (occupancy bytes)
-    const size_t need = (size_t)nb * (counts ? kCellBlock : kCellBlock / 4);
+    return g;
+}
+
+long long cells_of(const VoxGrid &g) { return (long long)g.dims[0] * g.dims[1] * g.dims[2]; }
+long long blocks_of(const VoxGrid &g) { return (cells_of(g) + kCellBlock - 1) / kCellBlock; }
+// u32 words of grid for a pass: whole blocks, 1 word per cell (counts) or per 4 cells (occupancy bytes)
+size_t grid_words(const VoxGrid &g, unsigned min_count)
+{
+    return (size_t)blocks_of(g) * (min_count > 1 ? kCellBlock : kCellBlock / 4);
+}
+
+// words of a block table for up to nb blocks: nb block counts, then one dirty byte per
+// block (the dirty bytes are all zero between passes)
+size_t table_words(long long nb) { return (size_t)nb + ((size_t)nb + 3) / 4; }
+
+// marking and finish on an all-zero grid and all-zero dirty bytes (both left so)
+gmapp_status run_voxel(gmapp_ctx *ctx, const float *x, const float *y, const float *z, long long n, const Cam *cam,
+                       const VoxGrid &g, unsigned min_count, unsigned *grid, unsigned *bsum, unsigned char *dirty,
+                       float *ox, float *oy, float *oz, long long capacity, long long *n_out_dev, hipStream_t stream)
+{
+    const long long nb = blocks_of(g);
+    const int local = nb <= kLocalBlocks ? 1 : 0;
+    if (min_count > 1) {
+        launch_mark<true>(ctx, x, y, z, n, cam, g, grid, dirty, stream);
+        hipLaunchKernelGGL(k_block_cells<true>, dim3((unsigned)nb), dim3(256), 0, stream, grid, dirty, min_count,
+                           bsum);
+    } else {
+        launch_mark<false>(ctx, x, y, z, n, cam, g, grid, dirty, stream);
+        hipLaunchKernelGGL(k_block_cells<false>, dim3((unsigned)nb), dim3(256), 0, stream, grid, dirty, min_count,
+                           bsum);
+    }
+    if (!local) hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, stream, bsum, nb, n_out_dev);
+    if (min_count > 1)
+        hipLaunchKernelGGL(k_write_cells<true>, dim3((unsigned)nb), dim3(256), 0, stream, grid, dirty, min_count, bsum,
+                           local, n_out_dev, g, ox, oy, oz, capacity);
+    else
+        hipLaunchKernelGGL(k_write_cells<false>, dim3((unsigned)nb), dim3(256), 0, stream, grid, dirty, min_count,
+                           bsum, local, n_out_dev, g, ox, oy, oz, capacity);
+    GM_HIP(ctx, hipGetLastError());
+    return GMAPP_OK;
+}
+
+}  // namespace
+
+// The context's grid stays all-zero between calls: it is zero-filled when (re)allocated,
+// and every finish kernel clears what the marking set.
+gmapp_status launch_voxel_downsample(gmapp_ctx *ctx, const float *x, const float *y, const float *z, long long n,
+                                     const Cam *cam, const VoxGrid &g_in, unsigned min_count, float *ox, float *oy,
+                                     float *oz, long long capacity, long long *n_out_dev, hipStream_t stream)
+{
+    const VoxGrid g = with_derived(g_in);
+    const long long nb = blocks_of(g);
+    const size_t need = grid_words(g, min_count);
     if (need > ctx->vgrid_words) {
         if (ctx->vgrid) {
             GM_HIP(ctx, hipStreamSynchronize(stream));
@@ -637,44 +729,32 @@ gmapp_status launch_voxel_downsample(gmapp_ctx *ctx, const float *x, const float
         }
         void *p = nullptr;
         if (hipMalloc(&p, need * sizeof(unsigned)) != hipSuccess)
-            return fail(ctx, GMAPP_ENOMEM, "voxel grid of %lld cells: cannot allocate %zu bytes", cells,
+            return fail(ctx, GMAPP_ENOMEM, "voxel grid of %lld cells: cannot allocate %zu bytes", cells_of(g),
                         need * sizeof(unsigned));
         ctx->vgrid = static_cast<unsigned *>(p);
         ctx->vgrid_words = need;
         const int zb = (int)std::min<long long>(((long long)need + 255) / 256, 8192);
         hipLaunchKernelGGL(k_zero_u32, dim3(zb), dim3(256), 0, stream, ctx->vgrid, (long long)need);
     }
-    if ((size_t)nb > ctx->vbsum_words) {
+    const size_t tw = table_words(nb);
+    if (tw > table_words((long long)ctx->vbsum_blocks)) {
         if (ctx->vbsum) {
             GM_HIP(ctx, hipStreamSynchronize(stream));
             (void)hipFree(ctx->vbsum);
             ctx->vbsum = nullptr;
-            ctx->vbsum_words = 0;
+            ctx->vbsum_blocks = 0;
         }
         void *p = nullptr;
-        if (hipMalloc(&p, (size_t)nb * sizeof(unsigned)) != hipSuccess)
+        if (hipMalloc(&p, tw * sizeof(unsigned)) != hipSuccess)
             return fail(ctx, GMAPP_ENOMEM, "voxel block table of %lld entries: cannot allocate", nb);
         ctx->vbsum = static_cast<unsigned *>(p);
-        ctx->vbsum_words = (size_t)nb;
+        ctx->vbsum_blocks = (size_t)nb;
+        hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)std::min<size_t>((tw + 255) / 256, 8192)), dim3(256), 0, stream,
+                           ctx->vbsum, (long long)tw);
     }
-    unsigned *grid = ctx->vgrid, *bsum = ctx->vbsum;
-    const int local = nb <= kLocalBlocks ? 1 : 0;
-    if (counts) {
-        launch_mark<true>(ctx, x, y, z, n, cam, g, grid, stream);
-        hipLaunchKernelGGL(k_block_cells<true>, dim3((unsigned)nb), dim3(256), 0, stream, grid, min_count, bsum);
-    } else {
-        launch_mark<false>(ctx, x, y, z, n, cam, g, grid, stream);
-        hipLaunchKernelGGL(k_block_cells<false>, dim3((unsigned)nb), dim3(256), 0, stream, grid, min_count, bsum);
-    }
-    if (!local) hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, stream, bsum, nb, n_out_dev);
-    if (counts)
-        hipLaunchKernelGGL(k_write_cells<true>, dim3((unsigned)nb), dim3(256), 0, stream, grid, min_count, bsum, local,
-                           n_out_dev, g, ox, oy, oz, capacity);
-    else
-        hipLaunchKernelGGL(k_write_cells<false>, dim3((unsigned)nb), dim3(256), 0, stream, grid, min_count, bsum,
-                           local, n_out_dev, g, ox, oy, oz, capacity);
-    GM_HIP(ctx, hipGetLastError());
-    return GMAPP_OK;
+    return run_voxel(ctx, x, y, z, n, cam, g, min_count, ctx->vgrid, ctx->vbsum,
+                     reinterpret_cast<unsigned char *>(ctx->vbsum + ctx->vbsum_blocks), ox, oy, oz, capacity,
+                     n_out_dev, stream);
 }
 
 }  // namespace gm

@@ -20,6 +20,9 @@
 //   (sc1) stores and loads are single-copy atomic.  Every shard adds the S
 //   partials in shard order, so all shards hold bit-identical agent states.
 //   Shards of a group are placed on one XCD (dispatch is round-robin over 8 XCDs).
+//   Every wait is bounded (slow_check): a wait that stalls past the context's limit,
+//   or sees the host's abort word, ends, and so do the launch's later waits; the
+//   rollout then runs its remaining steps without waiting and reports the status.
 //   Waves wait for their own exchange only, so the waves of a CU overlap one
 //   another's exchange latency.
 //
@@ -113,7 +116,7 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
     float *lpt = reinterpret_cast<float *>(lds + lp.cx);          // points interleaved: x, y, z per point
     int4 *runs = reinterpret_cast<int4 *>(lds + lp.runs);      // [runs_cap]: begin, end, first slice, slices
     float4 *rvel = reinterpret_cast<float4 *>(lds + lp.rvel);  // [runs_cap]
-    __shared__ int s_last, s_nruns, s_split, s_halt;
+    __shared__ int s_last, s_nruns, s_split;
 
     constexpr bool POSE = KIND >= 1;
     constexpr bool ARM = KIND == 2;
@@ -260,10 +263,6 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
     if constexpr (ARM) {
         if (jwriter && out.joints) out.joints[(size_t)agent * (pr.n_steps + 1) * pr.arm_n + my_j] = pr.arm_q0[my_j];
     }
-    // an exchange wait that ran out of time or saw the host's abort ends the rollout (a
-    // wave-uniform decision, shared through LDS when the workgroup is one group)
-    bool halt = false;
-    if (tid == 0) s_halt = 0;
 
     for (int k = 1; k <= n_steps; ++k) {
         const float t = PROBE ? t_fixed : fmaf((float)(k - 1), pr.dt, pr.t0);
@@ -422,13 +421,8 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
                 st64_agent(slot + 3, xword(m2_, tag));
             }
         };
-        // returns false when the wait was cut short (the rollout then halts)
-        auto collect = [&](float &Fx_, float &Fy_, float &Fz_, float &m2_) -> bool {
-            if (halt) return false;
-            bool ok = true;
-            const bool probe_abort = xc.abort && (tag % kAbortPeriod) == 0;
-            const unsigned ab = probe_abort ? ld_system(xc.abort) : 0u;
-            const unsigned long long t_wait = __builtin_amdgcn_s_memrealtime();
+        auto collect = [&](float &Fx_, float &Fy_, float &Fz_, float &m2_) {
+            unsigned long long t_wait = xc.fine ? __builtin_amdgcn_s_memrealtime() : 0ull;
             if (kVecX && 4 * S * AW <= 64) {
                 const bool poller = lane < 4 * S * AW;
                 unsigned long long q = 0;
@@ -436,9 +430,8 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
                 while (true) {
                     if (poller) q = ld64_agent(garea + lane);
                     if (__all(!poller || xtag(q) == tag)) break;
-                    if (wait_expired(xc, t_wait, ++spins)) {
-                        ok = false;
-                        break;
+                    if ((++spins & 63u) == 0 || xc.fine) {
+                        if (slow_check(xc, t_wait, spins)) break;
                     }
                 }
                 if (poller) reinterpret_cast<float *>(xtw)[lane] = xval(q);
@@ -453,18 +446,12 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
                         q3 = ld64_agent(slot + 3);
                         if (xtag(q0) == tag && xtag(q1) == tag && xtag(q2) == tag && xtag(q3) == tag) break;
                         __builtin_amdgcn_s_sleep(2);
-                        if (wait_expired(xc, t_wait, ++spins)) {
-                            ok = false;
-                            break;
+                        if ((++spins & 63u) == 0 || xc.fine) {
+                            if (slow_check(xc, t_wait, spins)) break;
                         }
                     }
                     xtw[l] = make_float4(xval(q0), xval(q1), xval(q2), xval(q3));
                 }
-                ok = !__any(!ok);
-            }
-            if (ab != 0u) {
-                st_agent(xc.status, 2u);
-                ok = false;
             }
             __builtin_amdgcn_wave_barrier();
             float4 a4 = xtw[a_w];
@@ -474,7 +461,6 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
             }
             __builtin_amdgcn_wave_barrier();        // xtw is rewritten next step
             Fx_ = a4.x; Fy_ = a4.y; Fz_ = a4.z; m2_ = a4.w;
-            return ok;
         };
         // net force (Eqs. 6, 7), obstacle cost (Eq. 18), integration (Eqs. 9-11), outputs
         auto finish = [&](float Fx_, float Fy_, float Fz_, float m2_) {
@@ -587,17 +573,15 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
                 Fx = acc.x; Fy = acc.y; Fz = acc.z; m2 = acc.w;
                 if (S > 1) publish(Fx, Fy, Fz, m2);
                 if constexpr (!PROBE) costs_early();       // overlaps the exchange
-                if (S > 1 && !collect(Fx, Fy, Fz, m2)) halt = true;
+                if (S > 1) collect(Fx, Fy, Fz, m2);
                 finish(Fx, Fy, Fz, m2);
                 if (lane < AW) {
                     tot[2 * lane] = make_float4(px, py, pz, vx);
                     tot[2 * lane + 1] = make_float4(vy, vz, 0.f, 0.f);
                 }
-                if (halt && lane == 0) s_halt = 1;
             }
             __syncthreads();
             if constexpr (PROBE) break;
-            if (s_halt) break;
             if (!lead) {
                 const float4 a = tot[2 * a_w], b = tot[2 * a_w + 1];
                 px = a.x; py = a.y; pz = a.z; vx = a.w; vy = b.x; vz = b.y;
@@ -605,12 +589,9 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
         } else {
             if (S > 1) publish(Fx, Fy, Fz, m2);
             if constexpr (!PROBE) costs_early();
-            if (S > 1 && !collect(Fx, Fy, Fz, m2)) halt = true;
+            if (S > 1) collect(Fx, Fy, Fz, m2);
             finish(Fx, Fy, Fz, m2);
             if constexpr (PROBE) break;
-            // without barriers in the step loop (resident shard) the wave stops on its own; with
-            // streamed tiles it keeps the workgroup's barriers and runs on without waiting
-            if (halt && resident) break;
         }
     }
 

@@ -529,6 +529,20 @@ gmapp_status gmapp_voxel_downsample_filtered(gmapp_ctx *ctx, const float *x, con
                                              float *ox, float *oy, float *oz, int64_t capacity, int64_t *n_out_dev,
                                              void *stream);
 
+/* For callers that cannot allocate device memory during the call (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the voxel
+ * pass of gmapp_voxel_downsample (no robot self-filter) on a statically sized grid
+ * that the library holds per device for the life of the process (8 MiB, set up by
+ * gmapp_create), so this call allocates nothing.  Grids of more than 2^21 cells give
+ * ECAPACITY; otherwise arguments, outputs and errors are those of
+ * gmapp_voxel_downsample.  Every call on one device shares that device's grid: calls
+ * whose work overlaps on one device (other streams, other contexts or threads) race
+ * and must be ordered by the caller. */
+gmapp_status gmapp_voxel_downsample_noalloc(gmapp_ctx *ctx, const float *x, const float *y, const float *z,
+                                            int64_t n, float voxel, const float lo[3], const int32_t dims[3],
+                                            int32_t min_count, float *ox, float *oy, float *oz, int64_t capacity,
+                                            int64_t *n_out_dev, void *stream);
+
 /* Depth frames straight to the voxel-centre cloud (Sec. IV-B / V-A: coordinate
  * transform, robot self-filter and voxel lattice in one pass): every pixel is
  * back-projected exactly as gmapp_depth_to_points_batch does it (the same FP32

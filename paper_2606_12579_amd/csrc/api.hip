@@ -235,7 +235,8 @@ gmapp_status gmapp_create(int32_t device, size_t workspace_bytes, gmapp_ctx **ou
     }
     ctx->abort_word = static_cast<unsigned *>(dw);
     hipLaunchKernelGGL(k_fill_u32, dim3(256), dim3(256), 0, nullptr, ctx->sync, fixed / sizeof(unsigned), 0u);
-    if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess || write_wait_settings(ctx)) {
+    if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess || write_wait_settings(ctx) ||
+        gm::static_scratch_init(ctx) != GMAPP_OK) {
         (void)hipHostFree(hw);
         (void)hipFree(p);
         delete ctx;
@@ -554,6 +555,24 @@ gmapp_status gmapp_voxel_downsample_filtered(gmapp_ctx *ctx, const float *x, con
     if ((st = voxel_grid(ctx, voxel, lo, dims, min_count, robot_spheres, n_spheres, g))) return st;
     return gm::launch_voxel_downsample(ctx, x, y, z, n, nullptr, g, (unsigned)min_count, ox, oy, oz, capacity,
                                        reinterpret_cast<long long *>(n_out_dev), static_cast<hipStream_t>(stream));
+}
+
+gmapp_status gmapp_voxel_downsample_noalloc(gmapp_ctx *ctx, const float *x, const float *y, const float *z,
+                                            int64_t n, float voxel, const float lo[3], const int32_t dims[3],
+                                            int32_t min_count, float *ox, float *oy, float *oz, int64_t capacity,
+                                            int64_t *n_out_dev, void *stream)
+{
+    gmapp_status st = check_ctx(ctx);
+    if (st) return st;
+    if (n < 0 || capacity < 0) return fail(ctx, GMAPP_EINVAL, "n and capacity must be >= 0");
+    if (n > 0 && (!x || !y || !z)) return fail(ctx, GMAPP_EINVAL, "input points must be non-NULL");
+    if (capacity > 0 && (!ox || !oy || !oz)) return fail(ctx, GMAPP_EINVAL, "output arrays must be non-NULL");
+    if (!n_out_dev) return fail(ctx, GMAPP_EINVAL, "n_out_dev must be non-NULL");
+    gm::VoxGrid g;
+    if ((st = voxel_grid(ctx, voxel, lo, dims, min_count, nullptr, 0, g))) return st;
+    return gm::launch_voxel_downsample_static(ctx, x, y, z, n, g, (unsigned)min_count, ox, oy, oz, capacity,
+                                              reinterpret_cast<long long *>(n_out_dev),
+                                              static_cast<hipStream_t>(stream));
 }
 
 gmapp_status gmapp_depth_to_voxels(gmapp_ctx *ctx, const float *depth, int32_t n_frames, int32_t w, int32_t h,

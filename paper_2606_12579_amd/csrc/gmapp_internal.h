@@ -190,6 +190,7 @@ struct gmapp_ctx {
     size_t vgrid_words = 0;
     unsigned *vbsum = nullptr;    // voxel pass: per-block occupied-cell counts, then per-block dirty bytes
     size_t vbsum_blocks = 0;      // blocks the table holds (the dirty bytes start after that many counts)
+    unsigned *static_grid = nullptr;  // device address of the static voxel grid on this device
     unsigned long long watchdog_ticks = 400000000ull;   // per-wait limit of the exchanges (4 s)
     unsigned *abort_host = nullptr;   // pinned, coherent host word: nonzero ends every exchange wait
     unsigned *abort_word = nullptr;   // its device address
@@ -268,6 +269,13 @@ gmapp_status launch_depth_to_points_batch(gmapp_ctx *ctx, const float *depth, in
 gmapp_status launch_voxel_downsample(gmapp_ctx *ctx, const float *x, const float *y, const float *z, long long n,
                                      const Cam *cam, const VoxGrid &g, unsigned min_count, float *ox, float *oy,
                                      float *oz, long long capacity, long long *n_out_dev, hipStream_t stream);
+// the same pass on the statically sized grid (no allocation): grids of at most kStaticCells cells
+constexpr long long kStaticCells = 1ll << 21;
+gmapp_status static_scratch_init(gmapp_ctx *ctx);
+gmapp_status launch_voxel_downsample_static(gmapp_ctx *ctx, const float *x, const float *y, const float *z,
+                                            long long n, const VoxGrid &g, unsigned min_count, float *ox,
+                                            float *oy, float *oz, long long capacity, long long *n_out_dev,
+                                            hipStream_t stream);
 gmapp_status check_tiling(gmapp_ctx *ctx, const Tiling &t, long long n_points, int n_seg, int cutoff);
 size_t rollout_lds_bytes(const Tiling &t, long long n_points, int n_seg);
 

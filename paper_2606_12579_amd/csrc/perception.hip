@@ -34,6 +34,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 
 namespace gm {
 namespace {
@@ -755,6 +756,60 @@ gmapp_status launch_voxel_downsample(gmapp_ctx *ctx, const float *x, const float
     return run_voxel(ctx, x, y, z, n, cam, g, min_count, ctx->vgrid, ctx->vbsum,
                      reinterpret_cast<unsigned char *>(ctx->vbsum + ctx->vbsum_blocks), ox, oy, oz, capacity,
                      n_out_dev, stream);
+}
+
+// ---------------------------------------------------------------- the pass without allocation
+// A statically sized grid and block table for callers that cannot allocate: one copy per
+// device, for the life of the process (the count grid of kStaticCells cells, its block
+// table after it).  In host code `scratch` names a host-side stand-in, not device memory:
+// its device address per device comes from hipGetSymbolAddress at set-up and is the only
+// way the host ever refers to it.
+namespace {
+constexpr size_t kStaticBlocks = (size_t)kStaticCells / kCellBlock;
+constexpr size_t kStaticWords = (size_t)kStaticCells + kStaticBlocks + kStaticBlocks / 4;   // grid, counts, dirty
+static __device__ __align__(256) unsigned scratch[kStaticWords];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned *g_scratch_dev[kMaxDevices] = {};
+}  // namespace
+
+gmapp_status static_scratch_init(gmapp_ctx *ctx)
+{
+    if (ctx->device < 0 || ctx->device >= kMaxDevices)
+        return fail(ctx, GMAPP_EDEVICE, "device %d is beyond the %d devices the static grid covers", ctx->device,
+                    kMaxDevices);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[ctx->device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return hip_fail(ctx, e != hipSuccess ? e : hipErrorInvalidSymbol,
+                                                   "hipGetSymbolAddress(scratch)");
+        unsigned *d = static_cast<unsigned *>(p);
+        // all-zero before the first pass (every pass leaves the grid as it found it)
+        hipLaunchKernelGGL(k_zero_u32, dim3(2048), dim3(256), 0, nullptr, d, (long long)kStaticWords);
+        GM_HIP(ctx, hipGetLastError());
+        GM_HIP(ctx, hipDeviceSynchronize());
+        g_scratch_dev[ctx->device] = d;
+    }
+    ctx->static_grid = g_scratch_dev[ctx->device];
+    return GMAPP_OK;
+}
+
+gmapp_status launch_voxel_downsample_static(gmapp_ctx *ctx, const float *x, const float *y, const float *z,
+                                            long long n, const VoxGrid &g_in, unsigned min_count, float *ox,
+                                            float *oy, float *oz, long long capacity, long long *n_out_dev,
+                                            hipStream_t stream)
+{
+    const VoxGrid g = with_derived(g_in);
+    if (cells_of(g) > kStaticCells)
+        return fail(ctx, GMAPP_ECAPACITY, "voxel grid of %lld cells exceeds the static grid's %lld cells",
+                    cells_of(g), kStaticCells);
+    if (!ctx->static_grid) return fail(ctx, GMAPP_EDEVICE, "the static voxel grid was not set up");
+    unsigned *grid = ctx->static_grid;
+    unsigned *bsum = ctx->static_grid + kStaticCells;
+    unsigned char *dirty = reinterpret_cast<unsigned char *>(bsum + kStaticBlocks);
+    return run_voxel(ctx, x, y, z, n, nullptr, g, min_count, grid, bsum, dirty, ox, oy, oz, capacity, n_out_dev,
+                     stream);
 }
 
 }  // namespace gm

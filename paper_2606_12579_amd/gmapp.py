@@ -185,6 +185,9 @@ def load_library(path: str = LIB_PATH):
                                                              vp]),
         "gmapp_depth_to_points_batch": (ctypes.c_int32, [vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                                          P(ctypes.c_float), vp, vp, vp, vp, vp]),
+        "gmapp_voxel_downsample_noalloc": (ctypes.c_int32, [vp, vp, vp, vp, ctypes.c_int64, ctypes.c_float,
+                                                            P(ctypes.c_float), P(ctypes.c_int32), ctypes.c_int32,
+                                                            vp, vp, vp, ctypes.c_int64, vp, vp]),
         "gmapp_depth_to_voxels": (ctypes.c_int32, [vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                                    P(ctypes.c_float), vp, ctypes.c_float, P(ctypes.c_float),
                                                    P(ctypes.c_int32), ctypes.c_int32, vp, ctypes.c_int32, vp, vp, vp,
@@ -786,6 +789,27 @@ class Context:
         Kc = (ctypes.c_float * 4)(*[float(v) for v in np.asarray(K, np.float32).reshape(4)])
         st = self.lib.gmapp_depth_to_points_batch(self.handle, _ptr(depth), int(b), int(w), int(h), Kc, _ptr(T_wc),
                                                   _ptr(out[0]), _ptr(out[1]), _ptr(out[2]), self._stream(stream))
+        self._raise(st)
+        return out
+
+    def voxel_downsample_noalloc(self, x, y, z, voxel, lo, dims, min_count=1, out=None, stream=None):
+        """gmapp_voxel_downsample_noalloc: the voxel pass on the library's static per-device grid (the call
+        allocates nothing; `out` = (ox, oy, oz, n_out) must be given, the capacity is ox's length)."""
+        import torch
+        n = int(x.numel())
+        for nm, t in (("x", x), ("y", y), ("z", z)):
+            _check_tensor(t, nm, n, torch.float32, self.device)
+        if out is None or len(out) != 4:
+            raise ValueError("out = (ox, oy, oz, n_out) is required: this call allocates nothing")
+        capacity = int(out[0].numel())
+        for i in range(3):
+            _check_tensor(out[i], f"out[{i}]", capacity, torch.float32, self.device)
+        _check_tensor(out[3], "n_out", 1, torch.int64, self.device)
+        loc = (ctypes.c_float * 3)(*[float(v) for v in np.asarray(lo, np.float32).reshape(3)])
+        dc = (ctypes.c_int32 * 3)(*[int(v) for v in np.asarray(dims).reshape(3)])
+        st = self.lib.gmapp_voxel_downsample_noalloc(self.handle, _ptr(x), _ptr(y), _ptr(z), n, float(voxel), loc,
+                                                     dc, int(min_count), _ptr(out[0]), _ptr(out[1]), _ptr(out[2]),
+                                                     capacity, _ptr(out[3]), self._stream(stream))
         self._raise(st)
         return out
 

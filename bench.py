@@ -35,22 +35,35 @@ def measured_traffic(path=os.path.join(ROOT, "profiles", "rollout_config2_hbm_co
     """HBM bytes per k_rollout launch from the committed rocprofv3 --pmc summary
     (FETCH_SIZE and WRITE_SIZE, each scaled by the same counter on a copy of known
     size); None when the summary is missing or the kernel changed since."""
+    v = profile_values(path, ("fetch_bytes_per_launch", "write_bytes_per_launch"))
+    return None if v is None else v["fetch_bytes_per_launch"] + v["write_bytes_per_launch"]
+
+
+def profile_values(path, keys):
+    """Values of `key: value` lines of a committed rocprofv3 summary, or None when the
+    summary is missing or was taken on other rollout kernel sources."""
     try:
         text = open(path).read()
     except OSError:
         return None
     vals = {}
     for line in text.splitlines():
-        if ":" in line and line.strip().startswith(("fetch_bytes_per_launch", "write_bytes_per_launch",
-                                                    "kernel_source_sha1")):
+        if ":" in line and line.strip().startswith(tuple(keys) + ("kernel_source_sha1",)):
             k, v = line.strip().split(":", 1)
             vals[k.strip()] = v.strip().strip("`")
     if vals.get("kernel_source_sha1") != kernel_sources_sha1():
         return None
     try:
-        return float(vals["fetch_bytes_per_launch"]) + float(vals["write_bytes_per_launch"])
+        return {k: float(vals[k]) for k in keys}
     except (KeyError, ValueError):
         return None
+
+
+def counter_fp32_flop(path=os.path.join(ROOT, "profiles", "rollout_config2_fp32_counters.md")):
+    """FP32 lane FLOP per k_rollout launch, 64 x (ADD + MUL + 2 FMA) of the SQ instruction
+    counters in the committed rocprofv3 --pmc summary; None when missing or stale."""
+    v = profile_values(path, ("fp32_lane_flop_per_launch",))
+    return None if v is None else v["fp32_lane_flop_per_launch"]
 
 
 def _percentile(xs, q):
@@ -487,14 +500,33 @@ def batched_vs_per_scene(ctx, dev, reqs, proxy_steps=16):
     e1.record(stream)
     torch.cuda.synchronize()
     single_s = e0.elapsed_time(e1) * 1e-3
-    # the two paths agree (FP32 summation order only)
+    # the two paths differ in FP32 summation order only: their costs, and the positions of
+    # every agent of 16 evenly spaced requests, rerun untimed with trajectories (a job's
+    # batched result does not depend on the other jobs of the launch)
     d = max(float((a - j.out["cost"]).abs().max()) for a, j in zip(batched_cost, jobs) if j.agents.n)
+    sample = [jobs[i] for i in np.linspace(0, len(jobs) - 1, min(16, len(jobs))).astype(int)]
+    tj = [gmapp.BatchJob(j.scene, j.agents, j.query, j.params,
+                         ctx.outputs(j.agents.n, j.params.n_steps, traj=True, min_clear=False)) for j in sample]
+    ctx.rollout_batch(tj, stream=stream)
+    pos = []
+    for j in tj:
+        o = ctx.rollout(j.scene, j.agents, j.query, j.params, traj=True, min_clear=False, stream=stream)
+        torch.cuda.synchronize()
+        pos.append((j.out["traj"] - o["traj"]).abs().amax(dim=(1, 2)).cpu().numpy())
+    pos = np.concatenate(pos) if pos else np.zeros(0)
     return {"requests": len(reqs), "interactions": work,
             "batched_interactions_per_s": work / batched_s, "batched_s": batched_s,
             "per_scene_interactions_per_s": work / single_s, "per_scene_s": single_s,
             "speedup": single_s / batched_s, "batched_frac_fp32_peak": work * FLOP_PER_INTERACTION / batched_s / PEAK_FP32,
             "tuning": {"tile_points": tuning[0], "wg_per_cu": tuning[1], "balance": tuning[2]},
-            "autotune_s": t_tune, "autotune_best_proxy_ms": proxy_ms, "max_cost_diff_batched_vs_per_scene": d}
+            "autotune_s": t_tune, "autotune_best_proxy_ms": proxy_ms, "max_cost_diff_batched_vs_per_scene": d,
+            "position_check": {"requests": len(sample), "agents": int(pos.size),
+                               "max_pos_diff_m": float(pos.max()) if pos.size else 0.0,
+                               "median_pos_diff_m": float(np.median(pos)) if pos.size else 0.0,
+                               "agents_over_1e-4_m": int((pos > 1e-4).sum()),
+                               "note": "batched vs per-scene launch, both FP32; agents over 1e-4 m are the "
+                                       "ill-conditioned ones, which the parity tests classify against the FP64 "
+                                       "oracle (one-ulp rotation-vector envelope) and hold to their envelope"}}
 
 
 def serving(ctx, reqs, quantum=50, budget=8 << 30):
@@ -586,6 +618,7 @@ def run():
     value = inter / (wall / args.steps)
     avg_kernel_s = float(np.mean(kern_ms)) * 1e-3
     achieved = inter * FLOP_PER_INTERACTION / avg_kernel_s
+    cflop = counter_fp32_flop()
 
     # ---- replan loop: the scene stays resident, obstacles advance 1 ms per cycle,
     # the start follows the selected agent; latency = launch to result on the host
@@ -632,7 +665,14 @@ def run():
         "kernel_ms_mean": avg_kernel_s * 1e3,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32, "traffic": measured_traffic(),
+                     "counter_tflops": None if cflop is None else cflop / avg_kernel_s / 1e12,
+                     "counter_frac": None if cflop is None else cflop / avg_kernel_s / PEAK_FP32,
+                     "counter_flop_per_interaction": None if cflop is None else cflop / inter,
                      "kernel_source_sha1": kernel_sources_sha1()},
+    }
+    res["targets"] = {
+        "frac_fp32_peak": {"target": ">= 0.5", "measured": achieved / PEAK_FP32, "pass": achieved / PEAK_FP32 >= 0.5},
+        "p99_replan_ms": {"target": "< 1.0", "measured": p99, "pass": None if p99 is None else p99 < 1.0},
     }
     if not args.no_heterogeneous:
         res["heterogeneous"] = heterogeneous_pass(ctx, dev, avg_kernel_s * 1e3)

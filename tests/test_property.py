@@ -1,0 +1,87 @@
+"""Property sweep on the GPU: random tiny planning problems (N_O <= 64, N_a <= 8,
+N_k <= 20) under random tilings of the rollout kernel, each checked against the FP64
+oracle on positions (1e-4 m), costs, the selection rule, and the teacher-forced
+force of Alg. 1 at the oracle's own states (1e-5 relative).  The draws cover what
+fixed cases miss in combination: empty and one-point worlds, point counts that are
+not a multiple of the slices or tiles, shards with no points, coincident spheres, an
+agent starting on a sphere centre, moving and static obstacles, the hard cut-off and
+the taper, every grouping of agents over lanes and waves."""
+import numpy as np
+import pytest
+from hypothesis import HealthCheck, given, settings
+from hypothesis import strategies as st
+
+import oracle
+from paper_2606_12579_amd import scenes
+from tests import gpu_util as gu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_2606_12579_amd import gmapp
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = gmapp.Context(0)
+    yield c
+    c.clear_tiling()
+    c.close()
+
+
+def _tilings():
+    """(agents per group, waves, shards, tile points, layout, group) that the kernel takes."""
+    out = []
+    for group in (1, 2):
+        for A in ((1, 2, 4, 8, 16, 32, 64) if group == 1 else (1, 2, 4, 8)):
+            for W in ((1, 2, 4, 8, 16) if group == 1 else (4, 8, 16)):
+                for S in (1, 2, 3, 4, 8):
+                    if S * A > 256:
+                        continue
+                    for layout, tile in ((0, 0), (1, 0), (2, 64), (2, 96)):
+                        out.append((A, W, S, tile, layout, group))
+    return out
+
+
+TILINGS = _tilings()
+
+
+def _problem(seed, n_o, n_a, n_k, moving, cutoff, coincide, on_centre):
+    pb = scenes.tiny(seed, n_points=n_o, n_agents=n_a, n_steps=n_k, moving=moving and n_o > 0, cutoff=cutoff)
+    if coincide and n_o >= 2:                       # two spheres at one centre
+        for a in ("x", "y", "z"):
+            arr = getattr(pb.scene, a)
+            arr[1] = arr[0]
+    if on_centre and n_o >= 1:                      # the agents start on a sphere centre (|d| = 0 at step 1)
+        pb.query.p0 = np.array([pb.scene.x[0], pb.scene.y[0], pb.scene.z[0]], np.float32)
+    return pb
+
+
+@settings(max_examples=200, deadline=None, derandomize=True,
+          suppress_health_check=[HealthCheck.function_scoped_fixture, HealthCheck.too_slow])
+@given(seed=st.integers(0, 2 ** 31 - 1), n_o=st.integers(0, 64), n_a=st.integers(1, 8), n_k=st.integers(1, 20),
+       moving=st.booleans(), cutoff=st.integers(0, 1), coincide=st.booleans(), on_centre=st.booleans(),
+       tiling=st.sampled_from(TILINGS))
+def test_random_tiny_problems(ctx, seed, n_o, n_a, n_k, moving, cutoff, coincide, on_centre, tiling):
+    import torch
+    from paper_2606_12579_amd import gmapp
+    pb = _problem(seed, n_o, n_a, n_k, moving, cutoff, coincide, on_centre)
+    print(f"seed {seed} N_O {n_o} N_a {n_a} N_k {n_k} moving {moving} cutoff {cutoff} coincide {coincide} "
+          f"on_centre {on_centre} tiling {tiling}", flush=True)
+    gpu = gu.gpu_rollout(ctx, pb, tiling=tiling)
+    ref = oracle.rollout(pb)
+    gu.compare_rollout(pb, gpu, ref)
+    gu.check_selection(gpu["best"], ref.cost, gpu["cost"])
+    # teacher-forced Alg. 1 response at the oracle's states of the first and the last step
+    sc, ag = gmapp.scene_to_device(pb.scene), gmapp.agents_to_device(pb.agents)
+    for k in sorted({1, n_k}):
+        p32 = ref.traj[:, k - 1].astype(np.float32)
+        v32 = ref.vel[:, k - 1].astype(np.float32)
+        t32 = np.float32((k - 1) * np.float32(pb.params.dt))
+        r = oracle.repulsion(pb, p32.astype(np.float64), v32.astype(np.float64), float(t32))
+        f, rho = ctx.force_probe(sc, ag, torch.as_tensor(p32, device="cuda"), torch.as_tensor(v32, device="cuda"),
+                                 float(t32), pb.params)
+        torch.cuda.synchronize()
+        d = np.linalg.norm(f.cpu().numpy().astype(np.float64) - r.force, axis=1)
+        assert (d <= gu.force_bound(r) + 1e-30).all(), (k, d, gu.force_bound(r))

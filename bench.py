@@ -204,6 +204,34 @@ def perception_pass(ctx, dev, reps=20):
         torch.cuda.synchronize()
         t_fu.append(e[0].elapsed_time(e[1]))
     assert int(vox[3].item()) == nv
+    # frames back to back on one stream: the device time per frame once launches queue ahead
+    torch.cuda.synchronize()
+    e[0].record()
+    for _ in range(5 * reps):
+        ctx.depth_to_voxels(d1, fr.K, T1, fr.voxel, fr.box_lo, fr.dims, capacity=cap, out=vox)
+    e[1].record()
+    torch.cuda.synchronize()
+    t_stream = e[0].elapsed_time(e[1]) / (5 * reps)
+    assert int(vox[3].item()) == nv
+    # the same passes captured in a HIP graph and replayed: device time per frame without the
+    # host's launch work (the grid is already allocated, so a pass launches kernels only)
+    gs = torch.cuda.Stream(dev)
+    gs.wait_stream(torch.cuda.current_stream(dev))
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=gs):
+        for _ in range(reps):
+            ctx.depth_to_voxels(d1, fr.K, T1, fr.voxel, fr.box_lo, fr.dims, capacity=cap, out=vox)
+    torch.cuda.synchronize()
+    graph.replay()
+    torch.cuda.synchronize()
+    e[0].record()
+    for _ in range(5):
+        graph.replay()
+    e[1].record()
+    torch.cuda.synchronize()
+    t_graph = e[0].elapsed_time(e[1]) / (5 * reps)
+    assert int(vox[3].item()) == nv
+    del graph
     bp_bytes = 4 * n + 12 * n
     vx_bytes = 12 * n + 12 * nv
     fu_bytes = 4 * n + 12 * nv
@@ -213,6 +241,13 @@ def perception_pass(ctx, dev, reps=20):
            "depth_to_points_GBps": bp_bytes / (t_bp / reps * 1e-3) / 1e9,
            "voxel_downsample_GBps": vx_bytes / (t_vx / reps * 1e-3) / 1e9,
            "fused_depth_to_voxels_ms": t_f, "fused_depth_to_voxels_GBps": fu_bytes / (t_f * 1e-3) / 1e9,
+           "fused_back_to_back_ms_per_frame": t_stream,
+           "fused_back_to_back_GBps": fu_bytes / (t_stream * 1e-3) / 1e9,
+           "fused_graph_ms_per_frame": t_graph, "fused_graph_GBps": fu_bytes / (t_graph * 1e-3) / 1e9,
+           "timing_note": "fused_depth_to_voxels_ms: one call between two events (host launch work included); "
+                          "back_to_back: calls queued on one stream (host-bound: the Python binding and three "
+                          "launches per frame); graph: the calls captured in one HIP graph and replayed (device "
+                          "time per frame, kernels and the gaps between them)",
            "bytes_note": "algorithmic: depth 4 B + points 12 B per pixel; points 12 B per point + centres 12 B; "
                          "fused: depth 4 B per pixel + centres 12 B"}
     # multi-view: B frames from B poses in one launch, then one fused voxel pass; the sweep

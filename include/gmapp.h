@@ -506,9 +506,10 @@ gmapp_status gmapp_depth_to_points_batch(gmapp_ctx *ctx, const float *depth, int
  * (device [capacity]) in increasing linear cell index (x fastest, then y, then z);
  * the number of occupied cells goes to n_out_dev (device int64 [1]), even when it
  * exceeds capacity (then only the first `capacity` centres are written).
- * The context keeps a grid over the box (1 bit per cell for min_count = 1,
- * 4 bytes per cell otherwise), allocated by the first call that needs a larger
- * one (a device allocation, ENOMEM if it fails) and freed by gmapp_destroy.
+ * The context keeps a grid over the box (1 byte per cell for min_count = 1,
+ * 4 bytes per cell otherwise) and a table of about 133 bytes per 1024 cells, both
+ * allocated by the first call that needs larger ones (a device allocation, ENOMEM if
+ * it fails) and freed by gmapp_destroy.
  * x, y, z: device [n]. */
 gmapp_status gmapp_voxel_downsample(gmapp_ctx *ctx, const float *x, const float *y, const float *z, int64_t n,
                                     float voxel, const float lo[3], const int32_t dims[3], int32_t min_count,
@@ -532,7 +533,7 @@ gmapp_status gmapp_voxel_downsample_filtered(gmapp_ctx *ctx, const float *x, con
 /* For callers that cannot allocate device memory during the call (code under HIP
  * graph capture, tight serving loops, harnesses that forbid hipMalloc): the voxel
  * pass of gmapp_voxel_downsample (no robot self-filter) on a statically sized grid
- * that the library holds per device for the life of the process (8 MiB, set up by
+ * that the library holds per device for the life of the process (8.3 MiB, set up by
  * gmapp_create), so this call allocates nothing.  Grids of more than 2^21 cells give
  * ECAPACITY; otherwise arguments, outputs and errors are those of
  * gmapp_voxel_downsample.  Every call on one device shares that device's grid: calls

@@ -18,12 +18,14 @@
 //   min_count > 1: a count grid (4 bytes per cell), marked with atomic adds that the
 //     wave first combines per cell.
 // A thread takes up to four consecutive points (or pixels) and merges equal cells
-// first: neighbouring pixels mostly share a voxel.  The occupied cells' centres are then written in increasing linear cell
-// index (x fastest, then y, then z) without a sort: per-block counts, then a
-// per-block local scan that writes the centres and clears what it read, each
-// block adding the counts of the blocks before it itself (up to kLocalBlocks
-// blocks; past that one exclusive scan of the block counts runs in between).
-// The count of occupied cells stays on the device.
+// first: neighbouring pixels mostly share a voxel.  The occupied cells' centres are then
+// written in increasing linear cell index (x fastest, then y, then z) without a sort: per
+// block of the grid, a counting pass (the grid's last reader: it leaves a 128-byte
+// occupancy mask and clears what was marked), then a local scan of the mask that writes
+// the centres, each block adding the counts of the blocks before it itself (up to
+// kLocalBlocks blocks; past that one exclusive scan of the block counts runs in between).
+// Only blocks holding a marked cell are read.  The count of occupied cells stays on the
+// device.
 //
 // The fused pass (cam != nullptr) back-projects each pixel with the same FP32
 // operations as the back-projection kernels and marks its cell directly, so the
@@ -41,6 +43,9 @@ namespace {
 
 constexpr int kCellBlock = 1024;        // cells per block of the finish (4 per thread)
 constexpr int kLocalBlocks = 1024;      // up to this many blocks each block adds its predecessors' counts itself
+constexpr int kMaskWords = kCellBlock / 32;   // occupancy mask words per block
+// inputs of up to this many points (pixels) -- one frame -- are marked in XCD bands
+constexpr long long kBandMax = 1ll << 19;
 
 // pixel (u, v) with z-depth d -> world point; NaN when d is not a positive finite depth
 __device__ __forceinline__ void back_project(int u, int v, float d, float fx, float fy, float cx, float cy,
@@ -211,6 +216,22 @@ __device__ __forceinline__ unsigned wave_sum(unsigned x)
     return (unsigned)sw[0] + (unsigned)sw[1];
 }
 
+// Logical block of this workgroup for the marking kernels.  Workgroups are dispatched to
+// the 8 XCDs round-robin (workgroup i to XCD i mod 8); with `band` set they are renumbered
+// so that the workgroups of one XCD take one contiguous range of the points (pixels).
+// Within one frame neighbouring pixels mark neighbouring cells, which share grid lines: a
+// line marked from one XCD is merged in that XCD's L2 and written back once, instead of
+// once per XCD that touched it (a single frame writes 4x fewer grid bytes).  Many frames
+// of one scene mark the same lines from every band anyway, and there the bands measured
+// slower, so the host sets `band` for single-frame inputs only.
+__device__ __forceinline__ unsigned xcd_block(int band)
+{
+    const unsigned nb = gridDim.x, b = blockIdx.x;
+    if (!band) return b;
+    const unsigned x = b & 7u, per = nb >> 3, rem = nb & 7u;
+    return x * per + min(x, rem) + (b >> 3);
+}
+
 // Marks one cell per lane (-1: none).
 //   occupancy (min_count = 1): a plain store of byte 1 -- racing writers store the same
 //     value, and the caches merge byte writes, so no atomic is needed;
@@ -295,10 +316,10 @@ __device__ __forceinline__ void mark4(const float (&X)[4], const float (&Y)[4], 
 template <bool COUNT>
 __global__ __launch_bounds__(256) void k_mark(const float *__restrict__ x, const float *__restrict__ y,
                                               const float *__restrict__ z, long long n, VoxGrid g,
-                                              unsigned *__restrict__ grid, unsigned char *__restrict__ dirty)
+                                              unsigned *__restrict__ grid, unsigned char *__restrict__ dirty, int band)
 {
     const long long stride = (long long)gridDim.x * blockDim.x;
-    const long long wbase = blockIdx.x * (long long)blockDim.x + (threadIdx.x & ~63);
+    const long long wbase = xcd_block(band) * (long long)blockDim.x + (threadIdx.x & ~63);
     for (long long w0 = wbase; w0 < n; w0 += stride) {
         const long long i = w0 + (threadIdx.x & 63);
         wave_mark<COUNT>(i < n ? mark_cell(x[i], y[i], z[i], g) : -1, 1u, grid, dirty);
@@ -313,10 +334,11 @@ __global__ __launch_bounds__(256) void k_mark_v4(const float4 *__restrict__ x4, 
                                                  const float4 *__restrict__ z4, long long n4,
                                                  const float *__restrict__ x, const float *__restrict__ y,
                                                  const float *__restrict__ z, long long n, VoxGrid g,
-                                                 unsigned *__restrict__ grid, unsigned char *__restrict__ dirty)
+                                                 unsigned *__restrict__ grid, unsigned char *__restrict__ dirty,
+                                                 int band)
 {
     const long long stride = (long long)gridDim.x * blockDim.x;
-    const long long tid = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    const long long tid = xcd_block(band) * (long long)blockDim.x + threadIdx.x;
     const long long wbase = tid - (threadIdx.x & 63);        // the wave's first thread (wave-uniform)
     for (long long w0 = wbase; w0 < n4; w0 += stride) {
         const long long i = w0 + (threadIdx.x & 63);
@@ -357,11 +379,11 @@ __device__ __forceinline__ void pixel_of(long long p, int w, int wh, int &f, int
 template <bool COUNT>
 __global__ __launch_bounds__(256) void k_mark_depth_v4(const float4 *__restrict__ depth, long long n4, Cam cam,
                                                        VoxGrid g, unsigned *__restrict__ grid,
-                                                       unsigned char *__restrict__ dirty)
+                                                       unsigned char *__restrict__ dirty, int band)
 {
     const int wh = cam.w * cam.h;
     const long long stride = (long long)gridDim.x * blockDim.x;
-    const long long wbase = blockIdx.x * (long long)blockDim.x + (threadIdx.x & ~63);
+    const long long wbase = xcd_block(band) * (long long)blockDim.x + (threadIdx.x & ~63);
     for (long long w0 = wbase; w0 < n4; w0 += stride) {
         const long long i = w0 + (threadIdx.x & 63);
         float X[4] = {0, 0, 0, 0}, Y[4] = {0, 0, 0, 0}, Z[4] = {0, 0, 0, 0};
@@ -385,11 +407,12 @@ __global__ __launch_bounds__(256) void k_mark_depth_v4(const float4 *__restrict_
 // fused, any shape: one pixel per thread
 template <bool COUNT>
 __global__ __launch_bounds__(256) void k_mark_depth(const float *__restrict__ depth, long long n, Cam cam, VoxGrid g,
-                                                    unsigned *__restrict__ grid, unsigned char *__restrict__ dirty)
+                                                    unsigned *__restrict__ grid, unsigned char *__restrict__ dirty,
+                                                    int band)
 {
     const int wh = cam.w * cam.h;
     const long long stride = (long long)gridDim.x * blockDim.x;
-    const long long wbase = blockIdx.x * (long long)blockDim.x + (threadIdx.x & ~63);
+    const long long wbase = xcd_block(band) * (long long)blockDim.x + (threadIdx.x & ~63);
     for (long long w0 = wbase; w0 < n; w0 += stride) {
         const long long p = w0 + (threadIdx.x & 63);
         int c = -1;
@@ -495,22 +518,33 @@ __device__ __forceinline__ void clear4(unsigned *__restrict__ grid, long long ba
     else grid[base >> 2] = 0u;
 }
 
-// finish, pass 1: occupied cells per block of kCellBlock cells (4 per thread)
+// finish, pass 1: occupied cells per block of kCellBlock cells (4 per thread).  The grid's
+// last reader: the block's occupancy goes to its mask (kMaskWords words, bit c for cell
+// c of the block) and every marked grid word is cleared, so the writing pass reads
+// 128 bytes per block instead of the block's grid.
 template <bool COUNT>
-__global__ __launch_bounds__(256) void k_block_cells(const unsigned *__restrict__ grid,
+__global__ __launch_bounds__(256) void k_block_cells(unsigned *__restrict__ grid,
                                                      const unsigned char *__restrict__ dirty, unsigned min_count,
-                                                     unsigned *__restrict__ bsum)
+                                                     unsigned *__restrict__ bsum, unsigned *__restrict__ mask)
 {
     __shared__ unsigned wsum[4];
-    if (!dirty[blockIdx.x]) {                     // no point marked a cell of this block
-        if (threadIdx.x == 0) bsum[blockIdx.x] = 0u;
+    const unsigned b = blockIdx.x, tid = threadIdx.x;
+    if (!dirty[b]) {                              // no point marked a cell of this block
+        if (tid == 0) bsum[b] = 0u;
         return;
     }
+    const long long base = (long long)b * kCellBlock + tid * 4;
     bool marked;
-    const unsigned occ = cells4<COUNT>(grid, (long long)blockIdx.x * kCellBlock + threadIdx.x * 4, min_count,
-                                       marked);
+    const unsigned occ = cells4<COUNT>(grid, base, min_count, marked);
+    if (marked) clear4(grid, base, COUNT);
+    // eight neighbouring threads' 4 bits form one mask word
+    unsigned m = occ << (4 * (tid & 7));
+    m |= __shfl_xor(m, 1, 64);
+    m |= __shfl_xor(m, 2, 64);
+    m |= __shfl_xor(m, 4, 64);
+    if ((tid & 7) == 0) mask[(size_t)b * kMaskWords + (tid >> 3)] = m;
     const unsigned t = block_sum<256>(__popc(occ), wsum);
-    if (threadIdx.x == 0) bsum[blockIdx.x] = t;
+    if (tid == 0) bsum[b] = t;
 }
 
 // exclusive scan of nb block counts in place (one workgroup of 1024 threads);
@@ -531,13 +565,13 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(unsigned *__restrict__ bsu
     if (threadIdx.x == 0) *n_out = (long long)carry;
 }
 
-// finish, pass 2: the block's occupied cells are compacted in LDS in cell order (local
-// scan), then written out as centres by consecutive threads (coalesced stores); every
-// marked cell read, and the block's dirty flag, are cleared.  Clean blocks write
-// nothing (the last one still reports the total in local mode).
-template <bool COUNT>
-__global__ __launch_bounds__(256) void k_write_cells(unsigned *__restrict__ grid, unsigned char *__restrict__ dirty,
-                                                     unsigned min_count, const unsigned *__restrict__ bsum, int local,
+// finish, pass 2: the block's occupied cells (its mask) are compacted in LDS in cell order
+// (local scan), then written out as centres by consecutive threads (coalesced stores); the
+// block's dirty flag is cleared.  Clean blocks write nothing (the last one still reports
+// the total in local mode).
+__global__ __launch_bounds__(256) void k_write_cells(const unsigned *__restrict__ mask,
+                                                     unsigned char *__restrict__ dirty,
+                                                     const unsigned *__restrict__ bsum, int local,
                                                      long long *__restrict__ n_out, VoxGrid g, float *__restrict__ ox,
                                                      float *__restrict__ oy, float *__restrict__ oz, long long capacity)
 {
@@ -548,7 +582,7 @@ __global__ __launch_bounds__(256) void k_write_cells(unsigned *__restrict__ grid
     const bool last = b == gridDim.x - 1;
     if (!d && !(local && last)) return;
     // the block's first position: the counts of the blocks before it (local: up to
-    // kLocalBlocks of them, 4 per thread, loaded together with the grid) or the scanned table
+    // kLocalBlocks of them, 4 per thread, loaded together with the mask) or the scanned table
     unsigned before = 0;
     if (local) {
 #pragma unroll
@@ -557,9 +591,7 @@ __global__ __launch_bounds__(256) void k_write_cells(unsigned *__restrict__ grid
             before += i < b ? bsum[i] : 0u;
         }
     }
-    const long long base = (long long)b * kCellBlock + tid * 4;
-    bool marked = false;
-    unsigned occ = d ? cells4<COUNT>(grid, base, min_count, marked) : 0u;
+    unsigned occ = d ? (mask[(size_t)b * kMaskWords + (tid >> 3)] >> (4 * (tid & 7))) & 0xFu : 0u;
     unsigned total;
     unsigned at = block_excl_scan<256>(__popc(occ), wsum, total);
     long long pos0;
@@ -569,7 +601,6 @@ __global__ __launch_bounds__(256) void k_write_cells(unsigned *__restrict__ grid
     } else {
         pos0 = (long long)bsum[b];
     }
-    if (marked) clear4(grid, base, COUNT);
     if (d && tid == 0) dirty[b] = 0;              // every thread read it before the scan's barriers
     while (occ) {
         cellbuf[at++] = (unsigned short)(4 * tid + (unsigned)(__ffs(occ) - 1));
@@ -629,6 +660,7 @@ void launch_mark(gmapp_ctx *ctx, const float *x, const float *y, const float *z,
                  const VoxGrid &g, unsigned *grid, unsigned char *dirty, hipStream_t stream)
 {
     if (n == 0) return;
+    const int band = n <= kBandMax ? 1 : 0;
     // four points (pixels) per thread only when the quads still give every SIMD two waves;
     // below that one per thread hides more latency
     const long long fill = 2ll * 64 * 4 * std::max(ctx->n_cu, 1);
@@ -638,10 +670,10 @@ void launch_mark(gmapp_ctx *ctx, const float *x, const float *y, const float *z,
             const long long n4 = n / 4;
             const int pb = (int)std::min<long long>((n4 + 255) / 256, 16384);
             hipLaunchKernelGGL(k_mark_depth_v4<COUNT>, dim3(pb), dim3(256), 0, stream,
-                               reinterpret_cast<const float4 *>(x), n4, *cam, g, grid, dirty);
+                               reinterpret_cast<const float4 *>(x), n4, *cam, g, grid, dirty, band);
         } else {
             const int pb = (int)std::min<long long>((n + 255) / 256, 16384);
-            hipLaunchKernelGGL(k_mark_depth<COUNT>, dim3(pb), dim3(256), 0, stream, x, n, *cam, g, grid, dirty);
+            hipLaunchKernelGGL(k_mark_depth<COUNT>, dim3(pb), dim3(256), 0, stream, x, n, *cam, g, grid, dirty, band);
         }
         return;
     }
@@ -650,10 +682,10 @@ void launch_mark(gmapp_ctx *ctx, const float *x, const float *y, const float *z,
         const int pb = (int)std::min<long long>((n4 + 255) / 256, 16384);
         hipLaunchKernelGGL(k_mark_v4<COUNT>, dim3(pb), dim3(256), 0, stream, reinterpret_cast<const float4 *>(x),
                            reinterpret_cast<const float4 *>(y), reinterpret_cast<const float4 *>(z), n4, x, y, z, n,
-                           g, grid, dirty);
+                           g, grid, dirty, band);
     } else {
-        const int pb = (int)std::min<long long>((n + 255) / 256, 8192);
-        hipLaunchKernelGGL(k_mark<COUNT>, dim3(pb), dim3(256), 0, stream, x, y, z, n, g, grid, dirty);
+        const int pb = (int)std::min<long long>((n + 255) / 256, 16384);
+        hipLaunchKernelGGL(k_mark<COUNT>, dim3(pb), dim3(256), 0, stream, x, y, z, n, g, grid, dirty, band);
     }
 }
 
@@ -679,33 +711,32 @@ size_t grid_words(const VoxGrid &g, unsigned min_count)
     return (size_t)blocks_of(g) * (min_count > 1 ? kCellBlock : kCellBlock / 4);
 }
 
-// words of a block table for up to nb blocks: nb block counts, then one dirty byte per
-// block (the dirty bytes are all zero between passes)
-size_t table_words(long long nb) { return (size_t)nb + ((size_t)nb + 3) / 4; }
+// Words of a block table for up to nb blocks: nb block counts (padded to 4 words), one
+// dirty byte per block (all zero between passes), then kMaskWords mask words per block.
+size_t count_words(long long nb) { return ((size_t)nb + 3) & ~(size_t)3; }
+size_t dirty_words(long long nb) { return ((size_t)nb + 3) / 4; }
+size_t table_words(long long nb) { return count_words(nb) + dirty_words(nb) + (size_t)nb * kMaskWords; }
 
 // marking and finish on an all-zero grid and all-zero dirty bytes (both left so)
 gmapp_status run_voxel(gmapp_ctx *ctx, const float *x, const float *y, const float *z, long long n, const Cam *cam,
                        const VoxGrid &g, unsigned min_count, unsigned *grid, unsigned *bsum, unsigned char *dirty,
-                       float *ox, float *oy, float *oz, long long capacity, long long *n_out_dev, hipStream_t stream)
+                       unsigned *mask, float *ox, float *oy, float *oz, long long capacity, long long *n_out_dev,
+                       hipStream_t stream)
 {
     const long long nb = blocks_of(g);
     const int local = nb <= kLocalBlocks ? 1 : 0;
     if (min_count > 1) {
         launch_mark<true>(ctx, x, y, z, n, cam, g, grid, dirty, stream);
         hipLaunchKernelGGL(k_block_cells<true>, dim3((unsigned)nb), dim3(256), 0, stream, grid, dirty, min_count,
-                           bsum);
+                           bsum, mask);
     } else {
         launch_mark<false>(ctx, x, y, z, n, cam, g, grid, dirty, stream);
         hipLaunchKernelGGL(k_block_cells<false>, dim3((unsigned)nb), dim3(256), 0, stream, grid, dirty, min_count,
-                           bsum);
+                           bsum, mask);
     }
     if (!local) hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, stream, bsum, nb, n_out_dev);
-    if (min_count > 1)
-        hipLaunchKernelGGL(k_write_cells<true>, dim3((unsigned)nb), dim3(256), 0, stream, grid, dirty, min_count, bsum,
-                           local, n_out_dev, g, ox, oy, oz, capacity);
-    else
-        hipLaunchKernelGGL(k_write_cells<false>, dim3((unsigned)nb), dim3(256), 0, stream, grid, dirty, min_count,
-                           bsum, local, n_out_dev, g, ox, oy, oz, capacity);
+    hipLaunchKernelGGL(k_write_cells, dim3((unsigned)nb), dim3(256), 0, stream, mask, dirty, bsum, local, n_out_dev,
+                       g, ox, oy, oz, capacity);
     GM_HIP(ctx, hipGetLastError());
     return GMAPP_OK;
 }
@@ -753,9 +784,10 @@ gmapp_status launch_voxel_downsample(gmapp_ctx *ctx, const float *x, const float
         hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)std::min<size_t>((tw + 255) / 256, 8192)), dim3(256), 0, stream,
                            ctx->vbsum, (long long)tw);
     }
+    unsigned *dirty = ctx->vbsum + count_words((long long)ctx->vbsum_blocks);
     return run_voxel(ctx, x, y, z, n, cam, g, min_count, ctx->vgrid, ctx->vbsum,
-                     reinterpret_cast<unsigned char *>(ctx->vbsum + ctx->vbsum_blocks), ox, oy, oz, capacity,
-                     n_out_dev, stream);
+                     reinterpret_cast<unsigned char *>(dirty), dirty + dirty_words((long long)ctx->vbsum_blocks), ox,
+                     oy, oz, capacity, n_out_dev, stream);
 }
 
 // ---------------------------------------------------------------- the pass without allocation
@@ -766,7 +798,8 @@ gmapp_status launch_voxel_downsample(gmapp_ctx *ctx, const float *x, const float
 // way the host ever refers to it.
 namespace {
 constexpr size_t kStaticBlocks = (size_t)kStaticCells / kCellBlock;
-constexpr size_t kStaticWords = (size_t)kStaticCells + kStaticBlocks + kStaticBlocks / 4;   // grid, counts, dirty
+constexpr size_t kStaticWords = (size_t)kStaticCells + kStaticBlocks + kStaticBlocks / 4 +
+                                kStaticBlocks * kMaskWords;     // grid, counts, dirty bytes, masks
 static __device__ __align__(256) unsigned scratch[kStaticWords];
 constexpr int kMaxDevices = 64;
 std::mutex g_scratch_mu;
@@ -807,9 +840,9 @@ gmapp_status launch_voxel_downsample_static(gmapp_ctx *ctx, const float *x, cons
     if (!ctx->static_grid) return fail(ctx, GMAPP_EDEVICE, "the static voxel grid was not set up");
     unsigned *grid = ctx->static_grid;
     unsigned *bsum = ctx->static_grid + kStaticCells;
-    unsigned char *dirty = reinterpret_cast<unsigned char *>(bsum + kStaticBlocks);
-    return run_voxel(ctx, x, y, z, n, nullptr, g, min_count, grid, bsum, dirty, ox, oy, oz, capacity, n_out_dev,
-                     stream);
+    unsigned *dirty = bsum + kStaticBlocks;
+    return run_voxel(ctx, x, y, z, n, nullptr, g, min_count, grid, bsum, reinterpret_cast<unsigned char *>(dirty),
+                     dirty + dirty_words((long long)kStaticBlocks), ox, oy, oz, capacity, n_out_dev, stream);
 }
 
 }  // namespace gm

@@ -83,6 +83,50 @@ def test_fused_voxels_multiview(ctx):
     assert np.array_equal(G, C)
 
 
+def test_voxel_pass_in_a_captured_graph(ctx):
+    """Fused depth-to-voxel passes captured in a HIP graph: every replay (with eager passes on
+    other frames and host synchronisations in between) gives the eager result bit for bit,
+    for min_count 1 and 2 (the grid each pass leaves zeroed is what the next one needs)."""
+    import torch
+    fr = scenes.config3_frame()
+    T = torch.as_tensor(scenes.config3_poses(3), device="cuda")
+    d = torch.as_tensor(fr.depth, device="cuda")
+    frames = [d.unsqueeze(0).contiguous(), torch.flip(d, [1]).unsqueeze(0).contiguous()]
+    cap = 65536
+    for min_count in (1, 2):
+        want = []
+        for f in frames:
+            o = ctx.depth_to_voxels(f, fr.K, T[:1], fr.voxel, fr.box_lo, fr.dims, min_count=min_count, capacity=cap)
+            torch.cuda.synchronize()
+            want.append([x.clone() for x in o])
+        outs = [tuple(torch.empty(cap, dtype=torch.float32, device="cuda") for _ in range(3)) +
+                (torch.zeros(1, dtype=torch.int64, device="cuda"),) for _ in frames]
+        gs = torch.cuda.Stream()
+        gs.wait_stream(torch.cuda.current_stream())
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=gs):
+            for f, o in zip(frames, outs):
+                ctx.depth_to_voxels(f, fr.K, T[:1], fr.voxel, fr.box_lo, fr.dims, min_count=min_count,
+                                    capacity=cap, out=o)
+        torch.cuda.synchronize()
+        for rep in range(4):
+            for o in outs:
+                for x in o:
+                    x.fill_(-1)
+            g.replay()
+            torch.cuda.synchronize()
+            for o, w in zip(outs, want):
+                n = int(w[3].item())
+                assert int(o[3].item()) == n, (min_count, rep)
+                for a in range(3):
+                    assert torch.equal(o[a][:n], w[a][:n]), (min_count, rep, a)
+            # eager passes between replays, on other frames and the other min_count
+            ctx.depth_to_voxels(frames[rep % 2], fr.K, T[1:2], fr.voxel, fr.box_lo, fr.dims,
+                                min_count=3 - min_count, capacity=cap)
+            torch.cuda.synchronize()
+        del g
+
+
 def test_voxel_exact_on_oracle_points(ctx):
     """Same FP32 points on both sides: identical occupied cells, centres = FP32 rounding of the exact centres."""
     import torch
@@ -145,9 +189,9 @@ def test_voxel_exact_at_faces(ctx):
 
 
 def test_voxel_large_grid_paths(ctx):
-    """Grids past the one-workgroup bitmap (2^19 cells) take the multi-block bitmap and
-    count-grid finishes: a 1024 x 1024 x 2 lattice with points in a band across it,
-    ragged point counts, min_count 1 and 3, and a capacity below the count."""
+    """Grids of more than 1024 blocks of 1024 cells take the multi-kernel finish (per-block
+    counts, their scan, then the centres): a 1024 x 1024 x 2 lattice with points in a band
+    across it, ragged point counts, min_count 1 and 3, and a capacity below the count."""
     import torch
     rng = np.random.default_rng(29)
     lo, s, dims = np.array([0.0, 0.0, 0.0], np.float32), np.float32(0.001), np.array([1024, 1024, 2], np.int32)
@@ -166,6 +210,32 @@ def test_voxel_large_grid_paths(ctx):
                 C = op.voxel_centres(cells[:k], s, lo, dims).astype(np.float32)
                 G = np.stack([ox[:k].cpu().numpy(), oy[:k].cpu().numpy(), oz[:k].cpu().numpy()], 1)
                 assert np.array_equal(G, C), (n, min_count, cap)
+
+
+def test_voxel_finish_across_block_counts(ctx):
+    """Consecutive passes over grids of 1, 2, 3, 517, 1024 and 1025 blocks of 1024 cells,
+    in an order that alternates the finish whose blocks add their predecessors' counts
+    themselves (up to 1024 blocks) with the one that scans the counts first, min_count 1
+    and 2: every pass gives the oracle's cells, on the grid and dirty bytes the passes
+    before it left cleared."""
+    import torch
+    rng = np.random.default_rng(41)
+    lo, s = np.array([0.0, 0.0, 0.0], np.float32), np.float32(0.001)
+    seq = [1, 3, 1024, 1025, 517, 1, 1024, 2, 1025, 1024, 3, 517, 1]
+    for i, nb in enumerate(seq):
+        dims = np.array([1024, nb, 1], np.int32)
+        n = int(rng.integers(1, 40000))
+        P = np.stack([rng.uniform(-0.01, 1.03, n), rng.uniform(0.0, nb * 0.001, n) * rng.uniform(0.0, 1.0, n) ** 2,
+                      rng.uniform(-0.0002, 0.0011, n)], 1).astype(np.float32)
+        t = [torch.as_tensor(np.ascontiguousarray(P[:, a]), device="cuda") for a in range(3)]
+        min_count = 1 + (i % 2)
+        cells = op.voxel_cells(P[:, 0], P[:, 1], P[:, 2], s, lo, dims, min_count)
+        ox, oy, oz, m = ctx.voxel_downsample(*t, s, lo, dims, min_count=min_count, capacity=len(cells) + 1)
+        torch.cuda.synchronize()
+        assert int(m.item()) == len(cells), (i, nb, n, min_count, int(m.item()), len(cells))
+        C = op.voxel_centres(cells, s, lo, dims).astype(np.float32)
+        G = np.stack([ox[:len(cells)].cpu().numpy(), oy[:len(cells)].cpu().numpy(), oz[:len(cells)].cpu().numpy()], 1)
+        assert np.array_equal(G, C), (i, nb, n, min_count)
 
 
 def _fused_vs_two_kernel(ctx, depth, K, T, fr, min_count=1, spheres=None, capacity=65536):

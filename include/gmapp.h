@@ -328,6 +328,11 @@ typedef struct {
     float *state;    /* device [N_a][GMAPP_STATE_FLOATS]; required unless k_begin = 1 and k_end = N_k + 1 */
     int32_t k_begin; /* first step of this launch, 1 <= k_begin <= N_k */
     int32_t k_end;   /* one past the last step, k_begin < k_end <= N_k + 1 */
+    const uint32_t *cancel; /* NULL, or a word the device can read while the launch runs (the device
+                               address of mapped, coherent host memory): nonzero cancels the job --
+                               its work items not yet started are skipped, running ones stop within
+                               64 steps, and best[0] reads GMAPP_ECANCELLED; its other outputs (and
+                               state) are then undefined.  Keep the word raised until the launch ends. */
 } gmapp_job;
 
 /* Tuning of the batched kernel.  Zero fields mean "choose" (the autotuned values
@@ -346,7 +351,10 @@ typedef struct {
 /* One persistent launch over n_jobs jobs (1..GMAPP_BATCH_MAX_JOBS, at most
  * GMAPP_BATCH_MAX_SEGMENTS segments per scene).  Workgroups pull (job, agent
  * block) items from a device queue, longest items first.  The job table is staged
- * through pinned host memory owned by the context. */
+ * through pinned host memory owned by the context.  A job's cancel word (see
+ * gmapp_job) and the context's abort word (gmapp_abort, gmapp_wait) are read at the
+ * start of every item and every 64 steps within one: a raised word ends that job's
+ * (or, for the abort word, every job's) work early, with best[0] = GMAPP_ECANCELLED. */
 gmapp_status gmapp_rollout_batch(gmapp_ctx *ctx, const gmapp_job *jobs, int32_t n_jobs, void *stream);
 /* Force a batch tuning on this context (NULL restores the automatic choice). */
 gmapp_status gmapp_set_batch_tuning(gmapp_ctx *ctx, const gmapp_batch_tuning *t);
@@ -449,7 +457,9 @@ gmapp_status gmapp_server_create(gmapp_ctx *ctx, const gmapp_server_config *cfg,
 gmapp_status gmapp_server_submit(gmapp_server *s, const gmapp_request *req, int64_t *id);
 /* Up to max completions, waiting up to wait_ms for the first; returns the count (>= 0). */
 int32_t gmapp_server_poll(gmapp_server *s, gmapp_completion *out, int32_t max, int32_t wait_ms);
-/* Cancel a waiting or active request (it completes with ECANCELLED); EINVAL if unknown or finished. */
+/* Cancel a waiting or active request (it completes with ECANCELLED); EINVAL if unknown or finished.
+ * An active request's work in the running cycle is skipped or stopped on the device (its job's
+ * cancel word, see gmapp_job), so it completes without waiting for its quantum to finish. */
 gmapp_status gmapp_server_cancel(gmapp_server *s, int64_t id);
 /* Wait until no request is waiting or active (ETIMEOUT after timeout_ms; < 0 = no limit). */
 gmapp_status gmapp_server_drain(gmapp_server *s, int32_t timeout_ms);

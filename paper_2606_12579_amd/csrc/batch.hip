@@ -62,9 +62,17 @@ struct Lds {
 };
 
 // One item: agents [a0, a0 + W * AW) (WS = 1) or [a0, a0 + AW) (WS = W) of job `jb`.
+// Whether the job was cancelled (its word) or the launch aborted (the context's word):
+// system-scope loads of mapped host memory, by one thread.
+__device__ __forceinline__ int job_stopped(const BatchJob &jb, const unsigned *abort)
+{
+    return (abort && ld_system(abort) != 0u) || (jb.cancel && ld_system(jb.cancel) != 0u);
+}
+
 template <int AW, int WS, int CUT>
 __device__ __forceinline__ void run_item(const BatchJob &jb, int a0, const Lds &m, const BatchLay &lay,
-                                                   int &n_runs_sh, int &split_sh)
+                                                   int &n_runs_sh, int &split_sh, int &stop_sh,
+                                                   const unsigned *abort)
 {
     constexpr int NT = 64 * kW;
     constexpr int L = 64 * WS / AW;            // slices per agent
@@ -137,6 +145,13 @@ __device__ __forceinline__ void run_item(const BatchJob &jb, int a0, const Lds &
     }
 
     for (int k = k_begin; k < k_end; ++k) {
+        // every 64 steps the workgroup looks at the cancel and abort words (one decision for
+        // all its waves, which share barriers); a stopped item leaves partial results
+        if (((k - k_begin) & 63) == 63) {
+            if (tid == 0) stop_sh = job_stopped(jb, abort);
+            __syncthreads();
+            if (stop_sh) break;
+        }
         const float t = fmaf((float)(k - 1), pr.dt, pr.t0);
         float Fx = 0, Fy = 0, Fz = 0, m2 = INFINITY;
         if (split) {
@@ -286,7 +301,8 @@ __device__ void select_best(const BatchJob &jb, char *sel)
 }
 
 __global__ __launch_bounds__(64 * kW) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_batch(const BatchTable *__restrict__ tab, unsigned *__restrict__ queue,
-                                                   unsigned *__restrict__ done, BatchLay lay)
+                                                   unsigned *__restrict__ done, BatchLay lay,
+                                                   const unsigned *__restrict__ abort)
 {
     extern __shared__ float4 lds4[];
     const BPlan lp = b_plan(lay);
@@ -297,7 +313,7 @@ __global__ __launch_bounds__(64 * kW) __attribute__((amdgpu_waves_per_eu(4, 8)))
     m.runs = reinterpret_cast<int4 *>(lds + lp.runs);
     m.rvel = reinterpret_cast<float4 *>(lds + lp.rvel);
     m.sel = lds + lp.sel;
-    __shared__ int s_item, s_nruns, s_split, s_last;
+    __shared__ int s_item, s_nruns, s_split, s_last, s_stop;
     const int tid = threadIdx.x;
     const int n_jobs = tab->n_jobs, n_items = tab->n_items;
     const BatchJob *jobs = tab->jobs;
@@ -315,27 +331,29 @@ __global__ __launch_bounds__(64 * kW) __attribute__((amdgpu_waves_per_eu(4, 8)))
         const BatchJob &jb = jobs[lo];
         const int blk = item - jb.item_base;
         const int a0 = blk * (jb.wg_items ? jb.aw : kW * jb.aw);
-        const int code = jb.ag.n <= 0 ? -1 :       // no agents: nothing to roll out, only the selection (-1)
+        if (tid == 0) s_stop = job_stopped(jb, abort);   // a cancelled job's items are skipped
+        __syncthreads();
+        const int code = (jb.ag.n <= 0 || s_stop) ? -1 :  // nothing to roll out, only the selection (-1)
                          (jb.wg_items ? 8 : 0) + (jb.pr.cutoff ? 4 : 0) +
                          (jb.aw == 1 ? 0 : jb.aw == 2 ? 1 : jb.aw == 4 ? 2 : 3);
         switch (code) {
         case -1: break;
-        case 0: run_item<1, 1, 0>(jb, a0, m, lay, s_nruns, s_split); break;
-        case 1: run_item<2, 1, 0>(jb, a0, m, lay, s_nruns, s_split); break;
-        case 2: run_item<4, 1, 0>(jb, a0, m, lay, s_nruns, s_split); break;
-        case 3: run_item<8, 1, 0>(jb, a0, m, lay, s_nruns, s_split); break;
-        case 4: run_item<1, 1, 1>(jb, a0, m, lay, s_nruns, s_split); break;
-        case 5: run_item<2, 1, 1>(jb, a0, m, lay, s_nruns, s_split); break;
-        case 6: run_item<4, 1, 1>(jb, a0, m, lay, s_nruns, s_split); break;
-        case 7: run_item<8, 1, 1>(jb, a0, m, lay, s_nruns, s_split); break;
-        case 8: run_item<1, kW, 0>(jb, a0, m, lay, s_nruns, s_split); break;
-        case 9: run_item<2, kW, 0>(jb, a0, m, lay, s_nruns, s_split); break;
-        case 10: run_item<4, kW, 0>(jb, a0, m, lay, s_nruns, s_split); break;
-        case 11: run_item<8, kW, 0>(jb, a0, m, lay, s_nruns, s_split); break;
-        case 12: run_item<1, kW, 1>(jb, a0, m, lay, s_nruns, s_split); break;
-        case 13: run_item<2, kW, 1>(jb, a0, m, lay, s_nruns, s_split); break;
-        case 14: run_item<4, kW, 1>(jb, a0, m, lay, s_nruns, s_split); break;
-        default: run_item<8, kW, 1>(jb, a0, m, lay, s_nruns, s_split); break;
+        case 0: run_item<1, 1, 0>(jb, a0, m, lay, s_nruns, s_split, s_stop, abort); break;
+        case 1: run_item<2, 1, 0>(jb, a0, m, lay, s_nruns, s_split, s_stop, abort); break;
+        case 2: run_item<4, 1, 0>(jb, a0, m, lay, s_nruns, s_split, s_stop, abort); break;
+        case 3: run_item<8, 1, 0>(jb, a0, m, lay, s_nruns, s_split, s_stop, abort); break;
+        case 4: run_item<1, 1, 1>(jb, a0, m, lay, s_nruns, s_split, s_stop, abort); break;
+        case 5: run_item<2, 1, 1>(jb, a0, m, lay, s_nruns, s_split, s_stop, abort); break;
+        case 6: run_item<4, 1, 1>(jb, a0, m, lay, s_nruns, s_split, s_stop, abort); break;
+        case 7: run_item<8, 1, 1>(jb, a0, m, lay, s_nruns, s_split, s_stop, abort); break;
+        case 8: run_item<1, kW, 0>(jb, a0, m, lay, s_nruns, s_split, s_stop, abort); break;
+        case 9: run_item<2, kW, 0>(jb, a0, m, lay, s_nruns, s_split, s_stop, abort); break;
+        case 10: run_item<4, kW, 0>(jb, a0, m, lay, s_nruns, s_split, s_stop, abort); break;
+        case 11: run_item<8, kW, 0>(jb, a0, m, lay, s_nruns, s_split, s_stop, abort); break;
+        case 12: run_item<1, kW, 1>(jb, a0, m, lay, s_nruns, s_split, s_stop, abort); break;
+        case 13: run_item<2, kW, 1>(jb, a0, m, lay, s_nruns, s_split, s_stop, abort); break;
+        case 14: run_item<4, kW, 1>(jb, a0, m, lay, s_nruns, s_split, s_stop, abort); break;
+        default: run_item<8, kW, 1>(jb, a0, m, lay, s_nruns, s_split, s_stop, abort); break;
         }
         if (jb.k_end > jb.pr.n_steps) {            // the job's last item applies the selection rule
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -348,7 +366,15 @@ __global__ __launch_bounds__(64 * kW) __attribute__((amdgpu_waves_per_eu(4, 8)))
             __syncthreads();
             if (s_last) {
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-                select_best(jb, m.sel);
+                // the words stay raised until the launch ends, so a job any of whose items was
+                // skipped or stopped is seen as cancelled here
+                if (tid == 0) s_stop = job_stopped(jb, abort);
+                __syncthreads();
+                if (s_stop) {
+                    if (tid == 0) jb.out.best[0] = GMAPP_ECANCELLED;
+                } else {
+                    select_best(jb, m.sel);
+                }
                 if (tid == 0) __hip_atomic_store(&done[lo], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
         }
@@ -387,12 +413,14 @@ gmapp_status batch_launch_shape(gmapp_ctx *ctx, const BatchLay &lay, int wg_per_
     out.lay = lay;
     out.queue = ctx->sync + kBatchQueueWord;
     out.done = ctx->sync;
+    out.abort = ctx->abort_word;
     return GMAPP_OK;
 }
 
 gmapp_status launch_batch(gmapp_ctx *ctx, const BatchTable *tab_dev, const BatchLaunch &l, hipStream_t stream)
 {
-    hipLaunchKernelGGL(k_batch, dim3(l.grid), dim3(l.block), l.shm, stream, tab_dev, l.queue, l.done, l.lay);
+    hipLaunchKernelGGL(k_batch, dim3(l.grid), dim3(l.block), l.shm, stream, tab_dev, l.queue, l.done, l.lay,
+                       l.abort);
     GM_HIP(ctx, hipGetLastError());
     return GMAPP_OK;
 }

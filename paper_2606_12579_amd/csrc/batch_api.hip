@@ -136,6 +136,7 @@ gmapp_status plan(gmapp_ctx *ctx, const gmapp_job *jobs, int n, const Tune &tu, 
         b.state = j.state;
         b.k_begin = j.k_begin;
         b.k_end = j.k_end;
+        b.cancel = reinterpret_cast<const unsigned *>(j.cancel);
         b.wg_items = shp[order[q]].wg;
         b.aw = shp[order[q]].aw;
         const int per = agents_per_item(shp[order[q]]);
@@ -207,7 +208,7 @@ struct gmapp_batch {
     hipGraphNode_t copy = nullptr, kernel = nullptr;
     hipEvent_t replayed = nullptr;
     bool ready = false;           // jobs set
-    void *kargs[4]{};
+    void *kargs[5]{};
     const BatchTable *arg_tab = nullptr;
 };
 
@@ -279,6 +280,7 @@ gmapp_status gmapp_batch_create(gmapp_ctx *ctx, int32_t max_jobs, gmapp_batch **
         b->kargs[1] = &b->launch.queue;
         b->kargs[2] = &b->launch.done;
         b->kargs[3] = &b->launch.lay;
+        b->kargs[4] = &b->launch.abort;
         hipKernelNodeParams kp{};
         kp.func = const_cast<void *>(b->launch.fn);
         kp.gridDim = dim3(b->launch.grid);

@@ -141,6 +141,7 @@ struct BatchJob {
     int n_items;
     int wg_items;       // 0: every wave is an agent group of aw agents; 1: the workgroup holds aw agents
     int aw;             // agents per group: 1, 2, 4, 8
+    const unsigned *cancel;   // device-readable word (mapped host memory) or null: nonzero cancels the job
 };
 
 struct BatchTable {
@@ -164,6 +165,7 @@ struct BatchLaunch {
     size_t shm;
     BatchLay lay;
     unsigned *queue, *done;
+    const unsigned *abort;   // the context's abort word (device address of pinned host memory)
 };
 
 }  // namespace gm

@@ -181,7 +181,9 @@ public:
     }
 
     // After a cycle ran [t0, t1]: advance the ranges; finished or cancelled
-    // requests release their memory and are returned.
+    // requests release their memory and are returned.  A request cancelled while
+    // its cycle ran is cancelled even if that cycle reached the end of its horizon:
+    // the device may have skipped or stopped its work.
     void complete(const std::vector<Slice> &ran, double t0, double t1, std::vector<Req *> &finished)
     {
         if (!ran.empty()) {
@@ -194,7 +196,7 @@ public:
             const bool done = r->k_next > r->n_steps;
             const bool late = !done && r->deadline > 0 && t1 > r->deadline;
             if (done || r->cancel || late) {
-                if (!done && r->status == 0) {
+                if (r->status == 0 && (r->cancel || !done)) {
                     r->status = r->cancel ? -6 : -5;
                     (r->cancel ? st_.cancelled : st_.expired)++;
                 }

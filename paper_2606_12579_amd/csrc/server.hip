@@ -8,6 +8,12 @@
 // requests that reached the end of their horizon download their costs, choice
 // and trajectory, release their memory and are reported.  The scheduling logic
 // (allocator, FIFO, slots, quanta, deadlines, statistics) is in sched.h.
+//
+// Every admitted request holds one cancel word in mapped, coherent host memory
+// (one per slot), which its job of each cycle carries: cancelling a request that
+// is on the device raises the word, and the running cycle skips or stops that
+// request's work (the batched kernel reads the word at every work item and every
+// 64 steps), so the completion comes without waiting for the request's quantum.
 #include "gmapp_internal.h"
 #include "sched.h"
 
@@ -61,6 +67,7 @@ struct Item {
     gmapp_request in;
     Layout lay;
     int best = -1;
+    int word = -1;      // cancel word while admitted
 };
 
 }  // namespace
@@ -81,6 +88,9 @@ struct gmapp_server {
     int64_t next_id = 1;
     bool stop = false;
     gmapp_status fault = GMAPP_OK;
+    unsigned *cancel_host = nullptr;   // [max_active] cancel words, mapped and coherent
+    unsigned *cancel_dev = nullptr;    // their device address
+    std::vector<int> free_words;
     std::thread worker;
     std::chrono::steady_clock::time_point t0;
 
@@ -141,6 +151,7 @@ void gmapp_server::report(std::vector<sched::Req *> &fin)
         c.queue_s = q->t_admit >= 0 ? q->t_admit - q->t_submit : -1.0;
         c.latency_s = q->t_finish - q->t_submit;
         done.push_back(c);
+        if (it.word >= 0) free_words.push_back(it.word);
         items.erase(q->id);
     }
     fin.clear();
@@ -184,6 +195,7 @@ void gmapp_server::run()
                 j.state = f(it.lay.state);
                 j.k_begin = s.k_begin;
                 j.k_end = s.k_end;
+                j.cancel = it.word >= 0 ? cancel_dev + it.word : nullptr;
                 jobs.push_back(j);
             }
             gmapp_status st;
@@ -209,6 +221,14 @@ void gmapp_server::run()
             std::lock_guard<std::mutex> lk(m);
             in = core->admit(now(), fin);
             report(fin);
+            for (sched::Req *q : in) {          // a lowered cancel word for each (slots bound them)
+                Item &it = *static_cast<Item *>(q->user);
+                if (!free_words.empty()) {
+                    it.word = free_words.back();
+                    free_words.pop_back();
+                    __atomic_store_n(cancel_host + it.word, 0u, __ATOMIC_SEQ_CST);
+                }
+            }
         }
         if (!in.empty()) {
             std::lock_guard<std::mutex> g(m_ctx);
@@ -305,6 +325,16 @@ gmapp_status gmapp_server_create(gmapp_ctx *ctx, const gmapp_server_config *cfg,
         hipEventCreateWithFlags(&s->uploaded, hipEventDisableTiming) != hipSuccess)
         return bail(fail(ctx, GMAPP_EDEVICE, "stream or event creation"));
     if ((st = gmapp_batch_create(ctx, c.max_active, &s->batch))) return bail(st);
+    void *hw = nullptr, *dw = nullptr;
+    if (hipHostMalloc(&hw, sizeof(unsigned) * (size_t)c.max_active, hipHostMallocMapped | hipHostMallocCoherent) !=
+        hipSuccess)
+        return bail(fail(ctx, GMAPP_ENOMEM, "pinned cancel words"));
+    s->cancel_host = static_cast<unsigned *>(hw);
+    std::memset(hw, 0, sizeof(unsigned) * (size_t)c.max_active);
+    if (hipHostGetDevicePointer(&dw, hw, 0) != hipSuccess)
+        return bail(fail(ctx, GMAPP_EDEVICE, "device address of the cancel words"));
+    s->cancel_dev = static_cast<unsigned *>(dw);
+    for (int w = c.max_active - 1; w >= 0; --w) s->free_words.push_back(w);
     s->core.reset(new sched::Core(c.memory_budget, c.max_active, c.quantum_steps, c.max_queue));
     s->t0 = std::chrono::steady_clock::now();
     s->worker = std::thread([s] { s->run(); });
@@ -367,6 +397,9 @@ gmapp_status gmapp_server_cancel(gmapp_server *s, int64_t id)
     if (!s) return GMAPP_EINVAL;
     std::lock_guard<std::mutex> lk(s->m);
     if (!s->core->cancel(id)) return GMAPP_EINVAL;
+    auto f = s->items.find(id);
+    if (f != s->items.end() && f->second->word >= 0)   // on the device: stop its work in the running cycle
+        __atomic_store_n(s->cancel_host + f->second->word, 1u, __ATOMIC_SEQ_CST);
     s->cv_work.notify_one();
     return GMAPP_OK;
 }
@@ -423,6 +456,7 @@ void gmapp_server_destroy(gmapp_server *s)
     if (s->comp) (void)hipStreamDestroy(s->comp);
     if (s->copy) (void)hipStreamDestroy(s->copy);
     if (s->arena) (void)hipFree(s->arena);
+    if (s->cancel_host) (void)hipHostFree(s->cancel_host);
     delete s;
 }
 

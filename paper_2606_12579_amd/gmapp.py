@@ -97,7 +97,8 @@ class Tiling(ctypes.Structure):
 
 class Job(ctypes.Structure):
     _fields_ = [("scene", Scene), ("agents", Agents), ("query", Query), ("params", Params), ("out", Outputs),
-                ("state", ctypes.c_void_p), ("k_begin", ctypes.c_int32), ("k_end", ctypes.c_int32)]
+                ("state", ctypes.c_void_p), ("k_begin", ctypes.c_int32), ("k_end", ctypes.c_int32),
+                ("cancel", ctypes.c_void_p)]
 
 
 class BatchTuning(ctypes.Structure):

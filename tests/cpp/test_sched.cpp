@@ -183,6 +183,26 @@ static void test_deadlines_and_cancel()
     CHECK(c.memory().used() == 0);
 }
 
+// a request cancelled while the cycle that covers its whole horizon runs is
+// reported cancelled, not completed (its work on the device may have stopped)
+static void test_cancel_during_last_cycle()
+{
+    Core c(100 * kGranule, 4, 10, 100);
+    Req a;
+    a.id = 1; a.bytes = kGranule; a.n_steps = 10;
+    std::vector<Req *> fin;
+    c.submit(&a, 0);
+    c.admit(0, fin);
+    const std::vector<Slice> run = c.plan();
+    CHECK(run.size() == 1 && run[0].k_begin == 1 && run[0].k_end == 11);
+    CHECK(c.cancel(1));                        // raised while the cycle runs
+    c.complete(run, 0, 1, fin);
+    CHECK(fin.size() == 1 && a.status == -6);
+    const Stats s = c.stats();
+    CHECK(s.cancelled == 1 && s.completed == 0);
+    CHECK(c.memory().used() == 0);
+}
+
 static void test_queue_limit_and_percentiles()
 {
     Core c(1000 * kGranule, 1000, 1000, 3);
@@ -210,6 +230,7 @@ int main()
     test_admission_and_slicing();
     test_head_of_line_and_joining();
     test_deadlines_and_cancel();
+    test_cancel_during_last_cycle();
     test_queue_limit_and_percentiles();
     if (failures) {
         std::printf("%d failures\n", failures);

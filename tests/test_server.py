@@ -134,3 +134,37 @@ def test_server_deadline_cancel_refuse(ctx):
             srv.cancel(c)                                     # already finished
     finally:
         srv.close()
+
+
+def test_server_cancel_stops_the_running_cycle(ctx):
+    """Cancelling a request whose work is on the GPU stops it there: a one-cycle request
+    (quantum = its horizon) completes with ECANCELLED well before its uncancelled time
+    once cancelled mid-cycle, and the loop goes on unaffected (oracle parity on a small
+    request afterwards)."""
+    from paper_2606_12579_amd import gmapp
+    long_pb = scenes.config2(seed=7, n_points=200_000, n_agents=128, n_steps=1000)
+    srv = ctx.server(memory_budget=1 << 30, max_active=4, quantum_steps=1000)
+    try:
+        (w,) = _collect(srv, [srv.submit(long_pb)])        # first launch of the loop's kernels
+        assert w["status"] == 0, w
+        t0 = time.time()
+        (ra,) = _collect(srv, [srv.submit(long_pb)])
+        full = time.time() - t0
+        assert ra["status"] == 0, ra
+        _log(f"uncancelled one-cycle request: {full * 1e3:.1f} ms")
+        assert full > 0.04, full                      # long enough to cancel mid-cycle
+        b = srv.submit(long_pb)
+        time.sleep(0.3 * full)                        # admitted, uploaded and running by now
+        t1 = time.time()
+        srv.cancel(b)
+        (rb,) = _collect(srv, [b])
+        stop = time.time() - t1
+        _log(f"cancelled mid-cycle: completion {stop * 1e3:.1f} ms after the cancel, status {rb['status']}")
+        assert rb["status"] == gmapp.ECANCELLED and rb["best"] == -1
+        assert stop < 0.5 * full, (stop, full)
+        small = scenes.tiny(28, n_points=80, n_agents=5, n_steps=60)
+        c = srv.submit(small, traj=True)
+        (rc,) = _collect(srv, [c])
+        _check_oracle(small, rc, oracle.rollout(small))
+    finally:
+        srv.close()

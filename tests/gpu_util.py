@@ -89,12 +89,13 @@ def conditioning(pb, idx):
     each agent five times: nominal; its rotation vector moved by one FP32 ulp up and down in
     every component; its circular-field gain k_f scaled by 1 +- 1e-5 (a repulsive force off
     by the stated 1e-5 relative force tolerance at every step).
-      env_ulp[i]:   largest position change over the horizon under the one-ulp moves; above
-                    1e-4 m the agent is ill-conditioned (the exact problem does not fix its
-                    FP32 trajectory to the tolerance);
+      env[i]:       largest position change over the horizon under any of the four
+                    perturbations; above 1e-4 m the agent is ill-conditioned (the exact problem
+                    does not fix its FP32 trajectory to the tolerance: one ulp of its inputs, or a
+                    force within the per-step tolerance, moves it further);
       env_step[i, k]: largest change of p^(k) under all four perturbations: the spread of the
                     trajectories whose every step meets the force tolerance.
-    Returns (nominal oracle rollout of idx, env_ulp [m], env_step [m, N_k + 1])."""
+    Returns (nominal oracle rollout of idx, env [m], env_step [m, N_k + 1])."""
     import copy
 
     import oracle
@@ -116,28 +117,28 @@ def conditioning(pb, idx):
     for f in ("traj", "cost", "min_clear", "force", "vel", "ftot"):
         setattr(nom, f, getattr(r, f)[:m])
     dev = [np.abs(r.traj[q * m:(q + 1) * m] - r.traj[:m]).max(2) for q in range(1, 5)]
-    env_ulp = np.maximum(dev[0], dev[1]).max(1)
     env_step = np.maximum.reduce(dev)
-    return nom, env_ulp, env_step
+    env = env_step.max(1)
+    return nom, env, env_step
 
 
 def compare_conditioned(pb, gpu, idx, label=""):
     """Sampled agents idx of a GPU rollout against the oracle, each to its own bar: the
-    well-conditioned ones (one-ulp envelope <= 1e-4 m) element-wise as compare_rollout
+    well-conditioned ones (envelope <= 1e-4 m) element-wise as compare_rollout
     (positions 1e-4 m, costs); the ill-conditioned ones step by step within
     max(1e-4 m, twice the largest spread of the perturbed trajectories so far).  Returns
     (worst error of the well-conditioned agents, number of ill-conditioned agents)."""
-    nom, env_ulp, env_step = conditioning(pb, idx)
+    nom, env, env_step = conditioning(pb, idx)
     idx = np.asarray(idx)
     err = np.abs(gpu["traj"][idx].astype(np.float64) - nom.traj).max(2)
-    ill = env_ulp > POS_TOL
+    ill = env > POS_TOL
     # the GPU trajectory is one more member of the family the perturbations sample; past the
     # onset of divergence the members' spread saturates at the size of the region the agent
     # wanders in, so the bar is twice the running maximum of the sampled spread
     bar = np.maximum(POS_TOL, 2.0 * np.maximum.accumulate(env_step, axis=1))
     for i in np.nonzero(ill)[0]:
         k = int(np.argmax(err[i] - bar[i]))
-        assert err[i, k] <= bar[i, k], (label, int(idx[i]), k, err[i, k], bar[i, k], env_ulp[i])
+        assert err[i, k] <= bar[i, k], (label, int(idx[i]), k, err[i, k], bar[i, k], env[i])
     worst = 0.0
     if (~ill).any():
         import copy

@@ -70,11 +70,12 @@ def test_adjoint_small(ctx, case):
 
 def test_adjoint_config4_sampled(ctx):
     """128 agents, 400 steps, 20,000 noisy sphere points, C1 taper, checkpoints
-    every 50 steps; the oracle's dual-number gradient on a spread subset."""
+    every 50 steps; the oracle's dual-number gradient on 33 agents spread over the
+    ensemble (every fourth, and the last)."""
     pb = scenes.config4()
     w = np.ones(pb.agents.n, np.float32)
     gpu = _gpu_grads(ctx, pb, w, 50)
-    idx = np.array([0, 37, 85, 127])
+    idx = np.append(np.arange(0, pb.agents.n, 4), pb.agents.n - 1)
     sub = copy.deepcopy(pb)
     sub.agents = pb.agents.subset(idx)
     ref = oracle.rollout_grad(sub)

@@ -268,8 +268,9 @@ def test_batch_validation(ctx, mix_refs):
 
 def test_config5_ill_conditioned_agent(ctx):
     """An agent that runs into an obstacle (clamped distance rho = eps) is
-    ill-conditioned: moving its rotation vector by one FP32 ulp moves the exact
-    (FP64) trajectory by more than the 1e-4 m tolerance.  Such an agent is held, step
+    ill-conditioned: moving its rotation vector by one FP32 ulp, or its force by the
+    1e-5 relative tolerance, moves the exact (FP64) trajectory by more than the 1e-4 m
+    tolerance.  Such an agent is held, step
     by step, to twice the spread of the exact trajectories perturbed by one ulp of its
     rotation vector or by the 1e-5 relative force tolerance (reading R24), and its
     divergence from the oracle starts only after the agent has reached the clamp."""

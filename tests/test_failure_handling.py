@@ -181,3 +181,42 @@ def test_wait_times_out_and_aborts_a_running_launch(ctx):
     b1, c1 = _rollout(ctx, p)
     b2, c2 = _rollout(ctx, ref)
     assert b1 == b2 and np.array_equal(c1, c2)
+
+
+def test_abort_word_stops_a_batched_launch(ctx):
+    """The batched kernel reads the abort word at every work item and every 64 steps:
+    raised before the launch, every job reports GMAPP_ECANCELLED in a fraction of the
+    launch's normal time; lowered again, the same jobs give their normal results."""
+    import torch
+    from paper_2606_12579_amd import gmapp
+    pbs = [scenes.config2(seed=8 + i, n_points=50_000, n_agents=64, n_steps=1000) for i in range(4)]
+
+    def jobs():
+        return [gmapp.BatchJob(gmapp.scene_to_device(pb.scene), gmapp.agents_to_device(pb.agents), pb.query,
+                               pb.params, ctx.outputs(pb.agents.n, pb.params.n_steps)) for pb in pbs]
+
+    ref = jobs()
+    ctx.rollout_batch(ref)                        # warm-up and reference
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.rollout_batch(ref)
+    torch.cuda.synchronize()
+    full = time.perf_counter() - t0
+    ab = jobs()
+    ctx.abort(True)
+    try:
+        t0 = time.perf_counter()
+        ctx.rollout_batch(ab)
+        torch.cuda.synchronize()
+        stopped = time.perf_counter() - t0
+    finally:
+        ctx.abort(False)
+    _log(f"batched launch: {full * 1e3:.1f} ms, aborted before it started: {stopped * 1e3:.1f} ms")
+    assert all(int(j.out["best"].item()) == ECANCELLED for j in ab)
+    assert stopped < 0.5 * full, (stopped, full)
+    again = jobs()
+    ctx.rollout_batch(again)
+    torch.cuda.synchronize()
+    for a, r in zip(again, ref):
+        assert int(a.out["best"].item()) == int(r.out["best"].item())
+        assert torch.equal(a.out["cost"], r.out["cost"])

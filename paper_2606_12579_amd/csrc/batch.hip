@@ -61,7 +61,6 @@ struct Lds {
     char *sel;
 };
 
-// One item: agents [a0, a0 + W * AW) (WS = 1) or [a0, a0 + AW) (WS = W) of job `jb`.
 // Whether the job was cancelled (its word) or the launch aborted (the context's word):
 // system-scope loads of mapped host memory, by one thread.
 __device__ __forceinline__ int job_stopped(const BatchJob &jb, const unsigned *abort)
@@ -69,10 +68,12 @@ __device__ __forceinline__ int job_stopped(const BatchJob &jb, const unsigned *a
     return (abort && ld_system(abort) != 0u) || (jb.cancel && ld_system(jb.cancel) != 0u);
 }
 
+// One item: agents [a0, a0 + W * AW) (WS = 1) or [a0, a0 + AW) (WS = W) of job `jb`.
+// chk: two LDS flags for the stop checks inside the step loop, used alternately, so that
+// between two writes of one flag every wave has passed the barrier after its last read.
 template <int AW, int WS, int CUT>
 __device__ __forceinline__ void run_item(const BatchJob &jb, int a0, const Lds &m, const BatchLay &lay,
-                                                   int &n_runs_sh, int &split_sh, int &stop_sh,
-                                                   const unsigned *abort)
+                                                   int &n_runs_sh, int &split_sh, int *chk, const unsigned *abort)
 {
     constexpr int NT = 64 * kW;
     constexpr int L = 64 * WS / AW;            // slices per agent
@@ -148,9 +149,10 @@ __device__ __forceinline__ void run_item(const BatchJob &jb, int a0, const Lds &
         // every 64 steps the workgroup looks at the cancel and abort words (one decision for
         // all its waves, which share barriers); a stopped item leaves partial results
         if (((k - k_begin) & 63) == 63) {
-            if (tid == 0) stop_sh = job_stopped(jb, abort);
+            int &f = chk[((k - k_begin) >> 6) & 1];
+            if (tid == 0) f = job_stopped(jb, abort);
             __syncthreads();
-            if (stop_sh) break;
+            if (f) break;
         }
         const float t = fmaf((float)(k - 1), pr.dt, pr.t0);
         float Fx = 0, Fy = 0, Fz = 0, m2 = INFINITY;
@@ -313,7 +315,7 @@ __global__ __launch_bounds__(64 * kW) __attribute__((amdgpu_waves_per_eu(4, 8)))
     m.runs = reinterpret_cast<int4 *>(lds + lp.runs);
     m.rvel = reinterpret_cast<float4 *>(lds + lp.rvel);
     m.sel = lds + lp.sel;
-    __shared__ int s_item, s_nruns, s_split, s_last, s_stop;
+    __shared__ int s_item, s_nruns, s_split, s_last, s_stop, s_chk[2];
     const int tid = threadIdx.x;
     const int n_jobs = tab->n_jobs, n_items = tab->n_items;
     const BatchJob *jobs = tab->jobs;
@@ -338,22 +340,22 @@ __global__ __launch_bounds__(64 * kW) __attribute__((amdgpu_waves_per_eu(4, 8)))
                          (jb.aw == 1 ? 0 : jb.aw == 2 ? 1 : jb.aw == 4 ? 2 : 3);
         switch (code) {
         case -1: break;
-        case 0: run_item<1, 1, 0>(jb, a0, m, lay, s_nruns, s_split, s_stop, abort); break;
-        case 1: run_item<2, 1, 0>(jb, a0, m, lay, s_nruns, s_split, s_stop, abort); break;
-        case 2: run_item<4, 1, 0>(jb, a0, m, lay, s_nruns, s_split, s_stop, abort); break;
-        case 3: run_item<8, 1, 0>(jb, a0, m, lay, s_nruns, s_split, s_stop, abort); break;
-        case 4: run_item<1, 1, 1>(jb, a0, m, lay, s_nruns, s_split, s_stop, abort); break;
-        case 5: run_item<2, 1, 1>(jb, a0, m, lay, s_nruns, s_split, s_stop, abort); break;
-        case 6: run_item<4, 1, 1>(jb, a0, m, lay, s_nruns, s_split, s_stop, abort); break;
-        case 7: run_item<8, 1, 1>(jb, a0, m, lay, s_nruns, s_split, s_stop, abort); break;
-        case 8: run_item<1, kW, 0>(jb, a0, m, lay, s_nruns, s_split, s_stop, abort); break;
-        case 9: run_item<2, kW, 0>(jb, a0, m, lay, s_nruns, s_split, s_stop, abort); break;
-        case 10: run_item<4, kW, 0>(jb, a0, m, lay, s_nruns, s_split, s_stop, abort); break;
-        case 11: run_item<8, kW, 0>(jb, a0, m, lay, s_nruns, s_split, s_stop, abort); break;
-        case 12: run_item<1, kW, 1>(jb, a0, m, lay, s_nruns, s_split, s_stop, abort); break;
-        case 13: run_item<2, kW, 1>(jb, a0, m, lay, s_nruns, s_split, s_stop, abort); break;
-        case 14: run_item<4, kW, 1>(jb, a0, m, lay, s_nruns, s_split, s_stop, abort); break;
-        default: run_item<8, kW, 1>(jb, a0, m, lay, s_nruns, s_split, s_stop, abort); break;
+        case 0: run_item<1, 1, 0>(jb, a0, m, lay, s_nruns, s_split, s_chk, abort); break;
+        case 1: run_item<2, 1, 0>(jb, a0, m, lay, s_nruns, s_split, s_chk, abort); break;
+        case 2: run_item<4, 1, 0>(jb, a0, m, lay, s_nruns, s_split, s_chk, abort); break;
+        case 3: run_item<8, 1, 0>(jb, a0, m, lay, s_nruns, s_split, s_chk, abort); break;
+        case 4: run_item<1, 1, 1>(jb, a0, m, lay, s_nruns, s_split, s_chk, abort); break;
+        case 5: run_item<2, 1, 1>(jb, a0, m, lay, s_nruns, s_split, s_chk, abort); break;
+        case 6: run_item<4, 1, 1>(jb, a0, m, lay, s_nruns, s_split, s_chk, abort); break;
+        case 7: run_item<8, 1, 1>(jb, a0, m, lay, s_nruns, s_split, s_chk, abort); break;
+        case 8: run_item<1, kW, 0>(jb, a0, m, lay, s_nruns, s_split, s_chk, abort); break;
+        case 9: run_item<2, kW, 0>(jb, a0, m, lay, s_nruns, s_split, s_chk, abort); break;
+        case 10: run_item<4, kW, 0>(jb, a0, m, lay, s_nruns, s_split, s_chk, abort); break;
+        case 11: run_item<8, kW, 0>(jb, a0, m, lay, s_nruns, s_split, s_chk, abort); break;
+        case 12: run_item<1, kW, 1>(jb, a0, m, lay, s_nruns, s_split, s_chk, abort); break;
+        case 13: run_item<2, kW, 1>(jb, a0, m, lay, s_nruns, s_split, s_chk, abort); break;
+        case 14: run_item<4, kW, 1>(jb, a0, m, lay, s_nruns, s_split, s_chk, abort); break;
+        default: run_item<8, kW, 1>(jb, a0, m, lay, s_nruns, s_split, s_chk, abort); break;
         }
         if (jb.k_end > jb.pr.n_steps) {            // the job's last item applies the selection rule
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");

@@ -162,7 +162,7 @@ def test_voxel_exact_at_faces(ctx):
     """Points on and one or two FP32 steps either side of the faces of the config-3
     lattice (1 cm cells from a corner that is not a multiple of the voxel) and of a
     dyadic lattice (faces representable): the kernel's cells are the exact lattice
-    cells of the oracle, bit for bit, for min_count 1 (bitmap) and 2 (counts).  An
+    cells of the oracle, bit for bit, for min_count 1 (occupancy bytes) and 2 (counts).  An
     FP32 quotient misplaces some of these points, so agreement is not a shared rounding."""
     import torch
     fr = scenes.config3_frame()

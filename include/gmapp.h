@@ -512,7 +512,8 @@ gmapp_status gmapp_depth_to_points_batch(gmapp_ctx *ctx, const float *depth, int
  * the box lo + [0, dims * voxel) or non-finite are dropped (the workspace
  * bounding-box filter).  Every cell holding at least min_count points (>= 1;
  * larger values filter sensing artifacts) contributes its centre
- * lo + (k + 1/2) voxel, rounded to FP32.  Centres are written to ox, oy, oz
+ * lo + (k + 1/2) voxel, rounded once to FP32 (dims: 1 .. 2^23 per axis, at most 2^31
+ * cells, else ECAPACITY).  Centres are written to ox, oy, oz
  * (device [capacity]) in increasing linear cell index (x fastest, then y, then z);
  * the number of occupied cells goes to n_out_dev (device int64 [1]), even when it
  * exceeds capacity (then only the first `capacity` centres are written).

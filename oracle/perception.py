@@ -8,7 +8,9 @@
                                  coordinate, corner and voxel size (exact rationals where
                                  an FP64 quotient cannot decide the floor)
   voxel_cells(x, y, z, ...)      the occupied cells of that lattice
-  voxel_centres(cells, ...)      the voxel-centre cloud lo + (k + 1/2) voxel (FP64)
+  voxel_centres(cells, ...)      the voxel-centre cloud: lo + (k + 1/2) voxel of the exact
+                                 values, rounded once to FP32 (exact rationals where FP64
+                                 cannot decide the rounding)
   on_robot(x, y, z, spheres)     the robot self-filter of Sec. V-A: points within any
                                  of the robot's bounding spheres (an integer decision,
                                  taken in FP64 as the library takes it)
@@ -95,11 +97,34 @@ def voxel_cells(x, y, z, voxel, lo, dims, min_count=1, spheres=None):
     return cells[counts >= min_count]
 
 
+def _nearest_f32(x):
+    """The FP32 value nearest to the rational x (ties to the even significand): the
+    answer is the FP32 rounding of float(x) or one of its two neighbours, compared
+    exactly."""
+    c0 = np.float32(float(x))
+    cands = [np.nextafter(c0, np.float32(-np.inf)), c0, np.nextafter(c0, np.float32(np.inf))]
+    return min(cands, key=lambda c: (abs(Fraction(float(c)) - x), int(np.float32(c).view(np.uint32)) & 1))
+
+
 def voxel_centres(cells, voxel, lo, dims):
+    """Centres [n, 3] (FP32) of the cells: lo + (k + 1/2) voxel of the exact values that
+    the FP32 corner and voxel size denote, rounded once to FP32.  FP64 evaluates it
+    with at most two roundings, which decide the FP32 value unless the FP64 result lies
+    within a few FP64 ulps of a point halfway between two FP32 neighbours; those are
+    redone with exact rationals (a round-to-FP64-then-FP32 there can break a tie the
+    wrong way, e.g. when lo is far smaller than the offset)."""
     dims = np.asarray(dims, np.int64)
-    kx = cells % dims[0]
-    ky = (cells // dims[0]) % dims[1]
-    kz = cells // (dims[0] * dims[1])
-    lo = np.asarray(lo, np.float32).astype(np.float64)
-    s = float(np.float32(voxel))
-    return np.stack([lo[0] + (kx + 0.5) * s, lo[1] + (ky + 0.5) * s, lo[2] + (kz + 0.5) * s], 1)
+    k = np.stack([cells % dims[0], (cells // dims[0]) % dims[1], cells // (dims[0] * dims[1])], 1)
+    lo32 = np.asarray(lo, np.float32)
+    s32 = np.float32(voxel)
+    v = lo32.astype(np.float64) + (k + 0.5) * np.float64(s32)
+    c = v.astype(np.float32)
+    c64 = c.astype(np.float64)
+    with np.errstate(invalid="ignore", over="ignore"):
+        up = np.nextafter(c, np.float32(np.inf)).astype(np.float64)
+        dn = np.nextafter(c, np.float32(-np.inf)).astype(np.float64)
+        tol = 4.0 * np.spacing(np.abs(v))
+        amb = (np.abs(v - (c64 + up) / 2) <= tol) | (np.abs(v - (c64 + dn) / 2) <= tol)
+    for i, a in zip(*np.nonzero(amb)):
+        c[i, a] = _nearest_f32(Fraction(float(lo32[a])) + (int(k[i, a]) + Fraction(1, 2)) * Fraction(float(s32)))
+    return c

@@ -175,6 +175,8 @@ gmapp_status voxel_grid(gmapp_ctx *ctx, float voxel, const float lo[3], const in
     for (int a = 0; a < 3; ++a) {
         if (!finite(lo[a])) return fail(ctx, GMAPP_EINVAL, "lo must be finite");
         if (dims[a] < 1) return fail(ctx, GMAPP_EINVAL, "dims must be >= 1");
+        // k + 1/2 exact in FP32, so that each centre lo + (k + 1/2) voxel is one rounding (a fused multiply-add)
+        if (dims[a] > (1 << 23)) return fail(ctx, GMAPP_ECAPACITY, "dims must be <= 2^23 per axis");
         g.lo[a] = lo[a];
         g.dims[a] = dims[a];
         cells *= dims[a];

@@ -438,7 +438,8 @@ __device__ __forceinline__ CellIdx cell_coords(unsigned c, const VoxGrid &g)
     const unsigned r = c / d0;
     return CellIdx{c - r * d0, r % d1, r / d1};
 }
-// voxel centre lo + (k + 1/2) s, rounded to FP32
+// voxel centre lo + (k + 1/2) s, rounded once to FP32: k + 1/2 is exact (k < 2^23 per axis) and
+// the fused multiply-add rounds the exact product-plus-corner once
 __device__ __forceinline__ void write_centre(const CellIdx &k, const VoxGrid &g, long long pos, float *__restrict__ ox,
                                              float *__restrict__ oy, float *__restrict__ oz)
 {

@@ -1,6 +1,7 @@
 """Pins of the perception oracle: projection round trip, brute-force voxel sets,
 geometric properties of voxel centres, idempotence."""
 import math
+from fractions import Fraction
 
 import numpy as np
 
@@ -135,6 +136,51 @@ def test_voxel_bruteforce_small():
         c2 = op.voxel_cells(P[:, 0], P[:, 1], P[:, 2], s, lo, dims, min_count=m)
         assert all((lin == c).sum() >= m for c in c2)
         assert all((lin == c).sum() < m for c in set(lin) - set(c2))
+
+
+def _round_f32_by_integers(x):
+    """Round the positive rational x to FP32 by integer arithmetic: scale it to a 24-bit
+    significand, round half to even with an integer division (normal range only)."""
+    e = x.numerator.bit_length() - x.denominator.bit_length()
+    while Fraction(2) ** e > x:
+        e -= 1
+    while Fraction(2) ** (e + 1) <= x:
+        e += 1
+    q = x / Fraction(2) ** (e - 23)                 # in [2^23, 2^24)
+    m, r = divmod(q.numerator, q.denominator)
+    if 2 * r > q.denominator or (2 * r == q.denominator and m % 2 == 1):
+        m += 1
+    return np.float32(float(Fraction(m) * Fraction(2) ** (e - 23)))
+
+
+def test_voxel_centres_rounded_once():
+    """Centres are lo + (k + 1/2) s of the exact values rounded once to FP32.  With lo the
+    smallest normal FP32 number and s = 0.001f, 1.5 s is an exact tie between two FP32
+    neighbours, and the tiny lo breaks it upward; a sum rounded to FP64 first loses lo
+    and ties to even instead.  A brute force over random corners, voxel sizes and cells
+    (integer-arithmetic rounding of the exact rational) must agree everywhere."""
+    s = np.float32(0.001)
+    tiny = np.float32(np.finfo(np.float32).tiny)
+    P = Fraction(3, 2) * Fraction(float(s))
+    below = np.float32(float(P))                   # P lies exactly halfway between two FP32 values
+    lo_n, hi_n = (np.nextafter(below, np.float32(-np.inf)), below) if Fraction(float(below)) > P else \
+        (below, np.nextafter(below, np.float32(np.inf)))
+    assert Fraction(float(lo_n)) + Fraction(float(hi_n)) == 2 * P
+    c = op.voxel_centres(np.array([1 * 1]), s, [0.0, tiny, 0.0], [1, 2, 1])     # cell (0, 1, 0)
+    assert c[0, 1] == hi_n and c[0, 1] == _round_f32_by_integers(P + Fraction(float(tiny)))
+    rng = np.random.default_rng(5)
+    for _ in range(400):
+        s = np.float32(rng.choice([0.001, 0.003, 0.01, 0.25, 1e-5]) * rng.uniform(0.5, 2.0))
+        lo = np.array([rng.choice([0.0, float(tiny), 1e-30, rng.uniform(-2, 2)]) for _ in range(3)], np.float32)
+        lo = np.abs(lo)                              # positive centres for the integer rounding
+        dims = rng.integers(1, 5000, 3)
+        cells = rng.integers(0, int(np.prod(dims)), 4)
+        C = op.voxel_centres(cells, s, lo, dims)
+        k = np.stack([cells % dims[0], (cells // dims[0]) % dims[1], cells // (dims[0] * dims[1])], 1)
+        for i in range(len(cells)):
+            for a in range(3):
+                x = Fraction(float(lo[a])) + (int(k[i, a]) + Fraction(1, 2)) * Fraction(float(s))
+                assert C[i, a] == _round_f32_by_integers(x), (float(s), lo, k[i], a)
 
 
 def test_voxel_centre_properties_and_idempotence():

@@ -330,6 +330,14 @@ def test_voxel_edges(ctx):
     ox, oy, oz, n = ctx.voxel_downsample(*e, s, lo, dims, capacity=4)
     torch.cuda.synchronize()
     assert int(n.item()) == 0
+    # an axis longer than 2^23 cells is refused (k + 1/2 would not be exact in FP32)
+    from paper_2606_12579_amd import gmapp
+    with pytest.raises(gmapp.GmappError) as ei:
+        ctx.voxel_downsample(*t, s, lo, np.array([(1 << 23) + 1, 1, 1], np.int32), capacity=4)
+    assert ei.value.status == gmapp.ECAPACITY
+    ox, oy, oz, n = ctx.voxel_downsample(*e, s, lo, np.array([1 << 23, 1, 1], np.int32), capacity=4)
+    torch.cuda.synchronize()
+    assert int(n.item()) == 0
 
 
 def test_voxel_ragged_and_unaligned(ctx):

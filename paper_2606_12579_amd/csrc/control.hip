@@ -100,7 +100,7 @@ __device__ __forceinline__ void control_share(const Scn &sc, const Run *runs, in
                 interact<CUT>(qx, qy, qz, psx, psy, psz, cwx, cwy, cwz, P.R, eps, P.rd, P.tb_a, P.tb_b, G, Sx, Sy, Sz,
                               m2);
             }
-            project_add(ux, uy, uz, P.kf, cwx, cwy, cwz, G, Sx, Sy, Sz, Fx, Fy, Fz);
+            project_add(ux, uy, uz, P.kf, cwx, cwy, cwz, cur ? 0.0f : G, Sx, Sy, Sz, Fx, Fy, Fz);   // G w lies along w
         }
     }
 }

@@ -289,7 +289,9 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
                 for (int i = 0; i < my_n; ++i, q += step3)
                     interact<CUT>(q[0], q[1], q[2], psx, psy, psz, cwx, cwy, cwz, P.R, pr.eps, P.rd, P.tb_a, P.tb_b,
                                   Gs, Sx, Sy, Sz, m2);
-                project_add(ux, uy, uz, P.kf, cwx, cwy, cwz, Gs, Sx, Sy, Sz, Fx, Fy, Fz);
+                // velocity current: the G w part of the summed current lies along w, and the
+                // projection across w removes it exactly; dropping it leaves no FP32 residue
+                project_add(ux, uy, uz, P.kf, cwx, cwy, cwz, cur ? 0.0f : Gs, Sx, Sy, Sz, Fx, Fy, Fz);
             }
         }
         const int tile = resident ? (int)max(n_shard, 1ll) : lay.cap;
@@ -323,7 +325,7 @@ __global__ __launch_bounds__(64 * W) void k_rollout(Scn sc, Agt ag, Prm pr, Out 
                         float Gs = 0, Sx = 0, Sy = 0, Sz = 0;
                         interact_run_aos<L, CUT>(lpt, b - t0r, e - t0r, slice, psx, psy, psz, cwx, cwy, cwz, P.R,
                                                  pr.eps, P.rd, P.tb_a, P.tb_b, Gs, Sx, Sy, Sz, m2);
-                        project_add(ux, uy, uz, P.kf, cwx, cwy, cwz, Gs, Sx, Sy, Sz, Fx, Fy, Fz);
+                        project_add(ux, uy, uz, P.kf, cwx, cwy, cwz, cur ? 0.0f : Gs, Sx, Sy, Sz, Fx, Fy, Fz);
                     }
                 }
             }

@@ -144,6 +144,7 @@ class RepulsionResult:
     abs_sum: np.ndarray    # [N_a] sum_j |f_j|
     edge_sum: np.ndarray   # [N_a] force magnitude of pairs at the hard cut-off (within 1e-6 r_d)
     edge_cnt: np.ndarray   # [N_a]
+    term_sum: np.ndarray   # [N_a] sum over pairs of the magnitudes of the terms of each pair force
 
 
 def repulsion(problem, p, v, t) -> RepulsionResult:
@@ -155,11 +156,11 @@ def repulsion(problem, p, v, t) -> RepulsionResult:
     pp, ppp = _d(np.asarray(p, np.float64).reshape(-1, 3))
     vv, pvv = _d(np.asarray(v, np.float64).reshape(-1, 3))
     P, pP = _d(_params_row(prm))
-    out = np.zeros((ag.n, 7))
+    out = np.zeros((ag.n, 8))
     lib.oracle_repulsion(*sargs, ag.n, pA, ppp, pvv, float(t), pP, int(prm.cutoff), out.ctypes.data_as(_dp))
     del keep
     return RepulsionResult(out[:, :3].copy(), out[:, 3].copy(), out[:, 4].copy(), out[:, 5].copy(),
-                           out[:, 6].astype(np.int64))
+                           out[:, 6].astype(np.int64), out[:, 7].copy())
 
 
 def rollout_grad(problem) -> np.ndarray:

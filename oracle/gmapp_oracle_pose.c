@@ -191,7 +191,7 @@ static void rollout_pose_one(long n_pts, const double *px, const double *py, con
     double kr = gains[0], dr = gains[1], ir = gains[2];
     for (int k = 1; k <= N; ++k) {
         double t = query[9] + (k - 1) * dt;
-        double vw[3], out[7];
+        double vw[3], out[8];
         mat_vec(R, u, vw);                           /* world velocity of the body origin */
         oracle_repulsion(n_pts, px, py, pz, r_obs, n_seg, seg_begin, seg_vel, 1, ag, p, vw, t, prm, cutoff, out);
         memcpy(pos + 3 * (k - 1), p, sizeof(p));

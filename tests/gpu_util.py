@@ -77,11 +77,17 @@ def compare_rollout(pb, gpu, ref, agents=None, pos_tol=POS_TOL):
     return pos_err
 
 
+TERM_ROUNDINGS = 16     # FP32 roundings charged to the magnitude of each pair force's terms
+
+
 def force_bound(r):
-    """Per-agent force bound: |dF| <= 1e-5 max(|F|, 1e-2 sum_j |f_j|) plus the force of pairs
-    sitting at the hard cut-off (where FP32 and FP64 may decide rho <= r_d differently)."""
+    """Per-agent force bound: |dF| <= 1e-5 max(|F|, 1e-2 sum_j |f_j|), plus the force of pairs
+    sitting at the hard cut-off (where FP32 and FP64 may decide rho <= r_d differently), plus 16
+    FP32 roundings of the magnitudes of the terms each pair force is made of (where Eq. 2's terms
+    cancel -- the velocity current for motion along or across the line to a sphere centre --
+    rounding leaves an error of the order of the terms, not of the small result)."""
     F = np.linalg.norm(r.force, axis=1)
-    return FORCE_REL * np.maximum(F, 1e-2 * r.abs_sum) + r.edge_sum
+    return FORCE_REL * np.maximum(F, 1e-2 * r.abs_sum) + r.edge_sum + TERM_ROUNDINGS * 2.0 ** -24 * r.term_sum
 
 
 def conditioning(pb, idx):

@@ -132,6 +132,9 @@ def test_force_tolerance_terms_hand_placed():
         perpendicular to w (and 0 where the current vanishes);
       the edge terms count the pairs within 1e-6 r_d of the hard cut-off, on both sides
         of it, with the force each would give if classified the other way;
+      the term magnitudes give each kept pair s |w| (|omega| + |n . omega|), s = k_f / rho:
+        k_f / rho where n is perpendicular to omega, 2 k_f / rho for the pair whose current
+        vanishes (its two terms cancel), and never less than |f_j|;
     pairs farther from the cut-off, and the whole edge band under the taper, add nothing."""
     r_d = np.float32(0.1)
     up = lambda x, n: [x := np.nextafter(x, np.float32(1.0)) for _ in range(n)][-1]
@@ -158,9 +161,11 @@ def test_force_tolerance_terms_hand_placed():
             np.testing.assert_allclose(r.abs_sum[0], kept, rtol=1e-12)
             np.testing.assert_allclose(r.edge_sum[0], kf / rho(2) + kf / rho(4) + kf / rho(6), rtol=1e-12)
             assert r.edge_cnt[0] == 3
+            np.testing.assert_allclose(r.term_sum[0], kept + 2 * kf / rho(1), rtol=1e-12)
         else:
             assert r.edge_sum[0] == 0.0 and r.edge_cnt[0] == 0
             assert r.abs_sum[0] >= abs(r.force[0, 2]) > 0.0
+        assert r.term_sum[0] >= r.abs_sum[0]
 
 
 def test_min_distance_matches_kdtree():

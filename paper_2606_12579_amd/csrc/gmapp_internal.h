@@ -188,7 +188,7 @@ struct gmapp_ctx {
     gmapp_batch_tuning batch_forced_tuning{0, 0, 0, 0};
     bool batch_tuned = false;
     gmapp_batch_tuning batch_tuned_tuning{0, 0, 0, 0};
-    unsigned *vgrid = nullptr;    // voxel grid (bitmap or counts), all zero between calls
+    unsigned *vgrid = nullptr;    // voxel grid (occupancy bytes or counts), all zero between calls
     size_t vgrid_words = 0;
     unsigned *vbsum = nullptr;    // voxel pass: per-block occupied-cell counts, then per-block dirty bytes
     size_t vbsum_blocks = 0;      // blocks the table holds (the dirty bytes start after that many counts)

@@ -3,36 +3,38 @@
 // and Alg. 1), one persistent launch per planning cycle, for gfx950 (CDNA4).
 //
 // Work decomposition
-//   Every wavefront is an independent agent group: its 64 lanes are (agent,
-//   slice) pairs, lane = agent + AW * slice, so each of its AW agents spreads the
-//   shard's points over L = 64 / AW lanes.  A workgroup of W waves holds W such
-//   groups (W * AW agents) and one shard of the sphere world (a contiguous range of
-//   the N_O points) in LDS, read by all its waves; S workgroups (shards) cover the
-//   points.  Points of one segment (object) are dealt round-robin to the L lanes,
-//   so every point read is broadcast to the AW agents of its slice, segment runs
-//   change at the same loop index in all lanes, and a run wastes at most one
-//   interaction per lane.  No workgroup barrier sits in the step loop when the
-//   shard is LDS-resident; shards too large for LDS are streamed through tiles.
+//   An agent group is either one wavefront (WS = 1) or the whole workgroup of W
+//   waves (WS = W).  Its lanes are (agent, slice) pairs, lane = agent + AW * slice,
+//   so each of its AW agents spreads the shard's points over L = 64 WS / AW lanes.
+//   A workgroup holds W / WS groups and one shard of the sphere world (a contiguous
+//   range of the N_O points) in LDS, read by all its waves; S workgroups (shards)
+//   cover the points.  Points of one segment (object) are dealt round-robin to the
+//   lanes of the run, so every point read is broadcast to the AW agents of its slice
+//   and a run wastes at most one interaction per lane.  With wave groups no
+//   workgroup barrier sits in the step loop when the shard is LDS-resident; a
+//   workgroup-wide group reduces its waves' partials through LDS (two barriers per
+//   step).  Shards too large for LDS are streamed through tiles.
 //
-//   After each step the S shards of a wave group exchange partial sums through the
+//   After each step the S shards of a group exchange partial sums through the
 //   context arena.  Each 64-bit word carries one float and the step number, so a
 //   reader knows a word is current without any fence or counter: the device-scope
 //   (sc1) stores and loads are single-copy atomic.  Every shard adds the S
 //   partials in shard order, so all shards hold bit-identical agent states.
 //   Shards of a group are placed on one XCD (dispatch is round-robin over 8 XCDs).
+//   Each group's lead wave (the group's only wave for wave groups) publishes and
+//   polls; wave groups of one CU overlap one another's exchange latency.
 //   Every wait is bounded (slow_check): a wait that stalls past the context's limit,
 //   or sees the host's abort word, ends, and so do the launch's later waits; the
 //   rollout then runs its remaining steps without waiting and reports the status.
-//   Waves wait for their own exchange only, so the waves of a CU overlap one
-//   another's exchange latency.
 //
 // Per interaction (agent i, sphere j) the lane evaluates the factored form of
 // Eq. (2) with the current vector c = omega - n (n . omega):
 //   f_j = g_j k_f |w| P_w (omega - n_j (n_j . omega)),  g_j = [rho_j <= r_d] / rho_j,
 // where P_w projects out w (the relative velocity, uniform over a segment) so
 //   sum_j f_j = k_f |w| P_w (omega G - S),  G = sum g_j,  S = sum g_j (d_j . omega) d_j / |d_j|^2.
-// The lane accumulates G, S (4 floats) and min |d|^2 over its points with
-// 20 VALU ops and 2 transcendentals (rsq, rcp) per interaction.
+// The lane accumulates G, S (4 floats) and min |d|^2 over its points with about
+// 21.5 VALU ops and 2 transcendentals (rsq, rcp) per interaction, plus about 2 of
+// loop bookkeeping (LDS addresses, the per-lane trip count) in the 4-point unrolled loop.
 // rho_min^(k) = max(sqrt(min |d|^2) - (r_O + r_a), eps).
 //
 // Heterogeneous ensembles (HET) take each agent's field from its heuristic code:

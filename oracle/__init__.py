@@ -40,7 +40,8 @@ def _load():
                                        _dp, _dp, _dp, _dp, _dp, _dp, _ip]
         lib.oracle_repulsion.restype = ctypes.c_int
         lib.oracle_repulsion.argtypes = [ctypes.c_long, _dp, _dp, _dp, ctypes.c_double, ctypes.c_int, _ip, _dp,
-                                         ctypes.c_int, _dp, _dp, _dp, ctypes.c_double, _dp, ctypes.c_int, _dp]
+                                         ctypes.c_int, _dp, _dp, _dp, ctypes.c_double, _dp, ctypes.c_int, ctypes.c_int,
+                                         _dp]
         lib.oracle_rollout_grad.restype = ctypes.c_int
         lib.oracle_rollout_grad.argtypes = [ctypes.c_long, _dp, _dp, _dp, ctypes.c_double, ctypes.c_int, _ip, _dp,
                                             ctypes.c_int, _dp, _dp, _dp, ctypes.c_int, ctypes.c_int, _dp]
@@ -145,10 +146,12 @@ class RepulsionResult:
     edge_sum: np.ndarray   # [N_a] force magnitude of pairs at the hard cut-off (within 1e-6 r_d)
     edge_cnt: np.ndarray   # [N_a]
     term_sum: np.ndarray   # [N_a] sum over pairs of the magnitudes of the terms of each pair force
+    shift_sum: np.ndarray  # [N_a] sum over moving pairs of |f_j| changes when p - t v_seg is rounded to FP32
 
 
-def repulsion(problem, p, v, t) -> RepulsionResult:
-    """Alg. 1's response for each agent at positions p [N_a,3], velocities v [N_a,3], time t."""
+def repulsion(problem, p, v, t, diagnostics=True) -> RepulsionResult:
+    """Alg. 1's response for each agent at positions p [N_a,3], velocities v [N_a,3], time t; with
+    diagnostics, the terms of the force tolerance too (zeros without)."""
     lib = _load()
     sc, ag, prm = problem.scene, problem.agents, problem.params
     keep, sargs = _scene_args(sc)
@@ -156,11 +159,12 @@ def repulsion(problem, p, v, t) -> RepulsionResult:
     pp, ppp = _d(np.asarray(p, np.float64).reshape(-1, 3))
     vv, pvv = _d(np.asarray(v, np.float64).reshape(-1, 3))
     P, pP = _d(_params_row(prm))
-    out = np.zeros((ag.n, 8))
-    lib.oracle_repulsion(*sargs, ag.n, pA, ppp, pvv, float(t), pP, int(prm.cutoff), out.ctypes.data_as(_dp))
+    out = np.zeros((ag.n, 9))
+    lib.oracle_repulsion(*sargs, ag.n, pA, ppp, pvv, float(t), pP, int(prm.cutoff), int(bool(diagnostics)),
+                         out.ctypes.data_as(_dp))
     del keep
     return RepulsionResult(out[:, :3].copy(), out[:, 3].copy(), out[:, 4].copy(), out[:, 5].copy(),
-                           out[:, 6].astype(np.int64), out[:, 7].copy())
+                           out[:, 6].astype(np.int64), out[:, 7].copy(), out[:, 8].copy())
 
 
 def rollout_grad(problem) -> np.ndarray:
@@ -330,7 +334,7 @@ def plan_loop(problem, n_cycles, ctrl_steps, ctrl_dt) -> LoopResult:
                 clear.append(np.nan)
                 continue
             t = t0c + j * dt_c
-            rep = repulsion(one, p[None], v[None], t)
+            rep = repulsion(one, p[None], v[None], t, diagnostics=False)
             F = k_a * (goal - p) - d_a * v + rep.force[0]
             v = v + h * F
             p = p + dt_c * v

@@ -100,7 +100,7 @@ def rollout_arm(problem, pose_agents, pose_query, links, q0, damping):
         u = R.T @ np.asarray(q.v0, np.float32).astype(np.float64)
         traj[i, 0], rot[i, 0], jts[i, 0] = p, _mat_quat(R), qj
         for k in range(1, N + 1):
-            r = repulsion(one, p[None], (R @ u)[None], t0 + (k - 1) * dt)
+            r = repulsion(one, p[None], (R @ u)[None], t0 + (k - 1) * dt, diagnostics=False)
             mc[i, k - 1] = r.rho_min[0]
             phi, rho = se3_log(_mat_quat(R.T @ Rg), R.T @ (goal - p))           # e = log(M^-1 M_g)
             Fa = kr * phi - dr * om                                               # Eqs. (6), (7)

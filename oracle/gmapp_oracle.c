@@ -140,23 +140,29 @@ static int seg_of(long j, int n_seg, const int *seg_begin)
  * spheres (the distance of the obstacle cost, Eq. 18).  Sphere j sits at
  * q_j + t v_seg(j).  Diagnostics: sum of |f_j|; the pairs whose rho lies within
  * 1e-6 r_d of the hard cut-off (their classification may legitimately differ in
- * FP32); and the sum of the magnitudes of the terms each pair force is made of,
- * which bounds what rounding can leave where Eq. (2)'s terms cancel: with
- * s = sigma k_f / rho and the current c = omega - n (n . omega) (omega = w for the
- * velocity current), s |w| (|omega| + |n . omega|); |f_j| for the APF, whose force is
- * a single term. */
+ * FP32); the sum of the magnitudes of the terms each pair force is made of, which
+ * bounds what rounding can leave where terms cancel; and the sum of the force changes
+ * when the agent's position in a moving segment's frame, p - t v_seg, is rounded to
+ * FP32 (the position a single-precision evaluation works from).  Term magnitudes:
+ *   circular fields, c = omega - n (n . omega) with omega = w for the velocity current:
+ *     (k_f / rho) |w| (|omega| + |n . omega|) (Eqs. 2, 3: c x w and the projection cancel
+ *     for motion along or across n);
+ *   APF: k_f (1/rho + 1/r_d) / rho^2 (Eq. 1: 1/rho - 1/r_d cancels at the cut-off);
+ *   both times sigma + |d sigma / d s| (rho + r_d) / (band r_d) under the taper, whose
+ *   argument s = (r_d - rho) / (band r_d) cancels at its outer edge. */
 static void repulsion_one(long n_pts, const double *px, const double *py, const double *pz, double r_obs,
                           int n_seg, const int *seg_begin, const double *seg_vel,
                           const double *ag, const double p[3], const double v[3], double t,
                           const double *prm, int cutoff,
                           double F[3], double *rho_min, double *abs_sum, double *edge_sum, long *edge_cnt,
-                          double *term_sum)
+                          double *term_sum, double *shift_sum)
 {
     double omega[3] = {ag[A_WX], ag[A_WY], ag[A_WZ]};
     const int heur = (int)ag[A_HEUR];
     double R = r_obs + ag[A_RA];
     F[0] = F[1] = F[2] = 0.0;
-    double rmin = INFINITY, asum = 0.0, esum = 0.0, tsum = 0.0;
+    double rmin = INFINITY, asum = 0.0, esum = 0.0, tsum = 0.0, ssum = 0.0;
+    const double r_d = ag[A_RD], band = prm[P_BAND];
     long ecnt = 0;
     for (long j = 0; j < n_pts; ++j) {
         int s = seg_of(j, n_seg, seg_begin);
@@ -170,16 +176,30 @@ static void repulsion_one(long n_pts, const double *px, const double *py, const 
         if (rho < rmin) rmin = rho;
         double fa = norm3(f);
         asum += fa;
-        if (heur == H_APF) {
-            tsum += fa;
-        } else {
-            const double *om = heur == H_MFI_VEL ? w : omega;
-            double d[3] = {p[0] - q[0], p[1] - q[1], p[2] - q[2]};
-            double r = norm3(d), nw = r > 0.0 ? dot3(d, om) / r : 0.0;
-            double sigma = oracle_cutoff_weight(rho, ag[A_RD], cutoff, prm[P_BAND]);
-            tsum += sigma * ag[A_KF] / rho * norm3(w) * (norm3(om) + fabs(nw));
+        if (term_sum) {
+            double weight = oracle_cutoff_weight(rho, r_d, cutoff, band);
+            if (cutoff == 1) {
+                const double st = (r_d - rho) / (band * r_d);
+                if (st > 0.0 && st < 1.0) weight += 6.0 * st * (1.0 - st) * (rho + r_d) / (band * r_d);
+            }
+            if (heur == H_APF) {
+                tsum += weight * ag[A_KF] * (1.0 / rho + 1.0 / r_d) / (rho * rho);
+            } else {
+                const double *om = heur == H_MFI_VEL ? w : omega;
+                double d[3] = {p[0] - q[0], p[1] - q[1], p[2] - q[2]};
+                double r = norm3(d), nw = r > 0.0 ? dot3(d, om) / r : 0.0;
+                tsum += weight * ag[A_KF] / rho * norm3(w) * (norm3(om) + fabs(nw));
+            }
         }
-        if (cutoff == 0 && fabs(rho - ag[A_RD]) <= 1e-6 * ag[A_RD]) {
+        if (shift_sum && s >= 0) {
+            /* the agent in the segment's frame, rounded to FP32, against the static point */
+            double ps[3], q0[3] = {px[j], py[j], pz[j]}, fs[3], rs;
+            for (int a = 0; a < 3; ++a) ps[a] = (double)(float)(p[a] - t * vo[a]);
+            oracle_pair_force_h(heur, ps, w, q0, omega, ag[A_KF], r_d, R, prm[P_EPS], cutoff, band, fs, &rs);
+            double df[3] = {fs[0] - f[0], fs[1] - f[1], fs[2] - f[2]};
+            ssum += norm3(df);
+        }
+        if (edge_sum && cutoff == 0 && fabs(rho - ag[A_RD]) <= 1e-6 * ag[A_RD]) {
             ecnt += 1;
             /* the force such a pair would give if classified the other way */
             double fo[3], rr;
@@ -193,25 +213,29 @@ static void repulsion_one(long n_pts, const double *px, const double *py, const 
     if (edge_sum) *edge_sum = esum;
     if (edge_cnt) *edge_cnt = ecnt;
     if (term_sum) *term_sum = tsum;
+    if (shift_sum) *shift_sum = ssum;
 }
 
 /* Teacher-forced force query (the response of Alg. 1 to one agent query), for a
  * batch of agents at given positions p[i], velocities v[i] and time t.
- * out rows per agent: F_r (3), rho_min, sum |f_j|, edge_force_sum, edge_count, term magnitude sum. */
+ * out rows per agent: F_r (3), rho_min, then (diagnostics != 0, else zeros) sum |f_j|, edge_force_sum,
+ * edge_count, term magnitude sum, frame-rounding sum. */
 int oracle_repulsion(long n_pts, const double *px, const double *py, const double *pz, double r_obs,
                      int n_seg, const int *seg_begin, const double *seg_vel,
                      int n_agents, const double *agents, const double *p, const double *v, double t,
-                     const double *prm, int cutoff, double *out)
+                     const double *prm, int cutoff, int diagnostics, double *out)
 {
 #pragma omp parallel for schedule(dynamic, 1)
     for (int i = 0; i < n_agents; ++i) {
-        double F[3], rmin, asum, esum, tsum;
-        long ecnt;
+        double F[3], rmin, asum = 0.0, esum = 0.0, tsum = 0.0, ssum = 0.0;
+        long ecnt = 0;
+        const int dg = diagnostics != 0;
         repulsion_one(n_pts, px, py, pz, r_obs, n_seg, seg_begin, seg_vel, agents + A_N * i, p + 3 * i,
-                      v + 3 * i, t, prm, cutoff, F, &rmin, &asum, &esum, &ecnt, &tsum);
-        double *o = out + 8 * i;
+                      v + 3 * i, t, prm, cutoff, F, &rmin, dg ? &asum : NULL, dg ? &esum : NULL,
+                      dg ? &ecnt : NULL, dg ? &tsum : NULL, dg ? &ssum : NULL);
+        double *o = out + 9 * i;
         o[0] = F[0]; o[1] = F[1]; o[2] = F[2]; o[3] = rmin; o[4] = asum; o[5] = esum; o[6] = (double)ecnt;
-        o[7] = tsum;
+        o[7] = tsum; o[8] = ssum;
     }
     return 0;
 }
@@ -291,7 +315,7 @@ static void rollout_one(long n_pts, const double *px, const double *py, const do
         double t = query[9] + (k - 1) * dt;   /* cycle start time + step offset */
         double Fr[3], rho_min;
         repulsion_one(n_pts, px, py, pz, r_obs, n_seg, seg_begin, seg_vel, ag, p, v, t, prm, cutoff, Fr,
-                      &rho_min, NULL, NULL, NULL, NULL);
+                      &rho_min, NULL, NULL, NULL, NULL, NULL);
         double F[3];
         for (int a = 0; a < 3; ++a)  /* Eq. (6) with the attractor of Eq. (7), e = p_g - p */
             F[a] = ag[A_KA] * (g[a] - p[a]) - ag[A_DA] * v[a] + Fr[a];

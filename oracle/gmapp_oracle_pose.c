@@ -21,7 +21,8 @@
 /* from gmapp_oracle.c */
 int oracle_repulsion(long n_pts, const double *px, const double *py, const double *pz, double r_obs, int n_seg,
                      const int *seg_begin, const double *seg_vel, int n_agents, const double *agents,
-                     const double *p, const double *v, double t, const double *prm, int cutoff, double *out);
+                     const double *p, const double *v, double t, const double *prm, int cutoff, int diagnostics,
+                     double *out);
 void oracle_costs(int N, const double *pos, const double *rmin, const double goal[3], const double *prm,
                   double out[5]);
 int oracle_select(int n, const double *total, int incumbent, double alpha);
@@ -191,9 +192,9 @@ static void rollout_pose_one(long n_pts, const double *px, const double *py, con
     double kr = gains[0], dr = gains[1], ir = gains[2];
     for (int k = 1; k <= N; ++k) {
         double t = query[9] + (k - 1) * dt;
-        double vw[3], out[8];
+        double vw[3], out[9];
         mat_vec(R, u, vw);                           /* world velocity of the body origin */
-        oracle_repulsion(n_pts, px, py, pz, r_obs, n_seg, seg_begin, seg_vel, 1, ag, p, vw, t, prm, cutoff, out);
+        oracle_repulsion(n_pts, px, py, pz, r_obs, n_seg, seg_begin, seg_vel, 1, ag, p, vw, t, prm, cutoff, 0, out);
         memcpy(pos + 3 * (k - 1), p, sizeof(p));
         mat_to_quat(R, rot + 4 * (k - 1));
         rmin[k - 1] = out[3];

@@ -81,13 +81,18 @@ TERM_ROUNDINGS = 16     # FP32 roundings charged to the magnitude of each pair f
 
 
 def force_bound(r):
-    """Per-agent force bound: |dF| <= 1e-5 max(|F|, 1e-2 sum_j |f_j|), plus the force of pairs
-    sitting at the hard cut-off (where FP32 and FP64 may decide rho <= r_d differently), plus 16
-    FP32 roundings of the magnitudes of the terms each pair force is made of (where Eq. 2's terms
-    cancel -- the velocity current for motion along or across the line to a sphere centre --
-    rounding leaves an error of the order of the terms, not of the small result)."""
+    """Per-agent force bound: |dF| <= 1e-5 max(|F|, 1e-2 sum_j |f_j|), plus
+      - the force of pairs sitting at the hard cut-off (where FP32 and FP64 may decide
+        rho <= r_d differently);
+      - 16 FP32 roundings of the magnitudes of the terms each pair force is made of (where terms
+        cancel -- the velocity current for motion along or across the line to a sphere centre,
+        the APF's 1/rho - 1/r_d at its cut-off, the taper's argument at its outer edge -- rounding
+        leaves an error of the order of the terms, not of the small result);
+      - the force change when the agent's position in a moving segment's frame is rounded to
+        FP32 (near a sphere centre the direction n = d / |d| amplifies that rounding)."""
     F = np.linalg.norm(r.force, axis=1)
-    return FORCE_REL * np.maximum(F, 1e-2 * r.abs_sum) + r.edge_sum + TERM_ROUNDINGS * 2.0 ** -24 * r.term_sum
+    return (FORCE_REL * np.maximum(F, 1e-2 * r.abs_sum) + r.edge_sum + TERM_ROUNDINGS * 2.0 ** -24 * r.term_sum
+            + r.shift_sum)
 
 
 def conditioning(pb, idx):

@@ -168,6 +168,65 @@ def test_force_tolerance_terms_hand_placed():
         assert r.term_sum[0] >= r.abs_sum[0]
 
 
+def test_force_tolerance_terms_cancellation_and_frame():
+    """The term magnitudes and the frame-rounding diagnostic of the force tolerance, by their
+    properties rather than their formulas:
+      every pair's term magnitude is at least its |f_j| (so the sum is at least sum_j |f_j|), with
+      equality for none of the APF pairs (its two terms 1/rho and 1/r_d have the same sign);
+      an APF sphere just inside the cut-off gives a vanishing force but a term magnitude that
+      stays at its interior size, and one beyond the cut-off adds nothing;
+      under the taper the magnitude exceeds |f_j| most where the weight is smallest;
+      the frame diagnostic is zero for static spheres, at t = 0, and when p - t v_seg is an FP32
+      number, and otherwise positive and within the force's own change over one FP32 step."""
+    r_d = 0.1
+    P = np.array([[0.03, 0.0, 0.0], [0.0, 0.05, 0.0], [0.0, 0.0, 0.099999], [0.0, -0.2, 0.0]], np.float32)
+    for heur in (0, 1, 2):
+        for cutoff in (0, 1):
+            ag = _agents(1, k_f=KF if heur < 2 else scenes.K_F_APF, r_d=r_d, r_a=0.0, omega=[[0.0, 0.6, 0.8]])
+            ag.heuristic = np.array([heur], np.int32)
+            pb = _problem_from_points(P, ag, [0, 0, 0], [1, 0, 0], r_obs=0.0, cutoff=cutoff)
+            r = oracle.repulsion(pb, [[0.0, 0.0, 0.0]], [[0.3, -0.2, 0.1]], 0.0)
+            assert r.term_sum[0] >= r.abs_sum[0] > 0.0
+            if heur == 2:
+                assert r.term_sum[0] > 1.5 * r.abs_sum[0]
+            assert r.shift_sum[0] == 0.0                     # static spheres
+    # APF at the cut-off: the force of a sphere at rho -> r_d vanishes, its term magnitude does not
+    ag = _agents(1, k_f=scenes.K_F_APF, r_d=r_d, r_a=0.0)
+    ag.heuristic = np.array([2], np.int32)
+    near = lambda x: oracle.repulsion(_problem_from_points([[x, 0, 0]], ag, [0, 0, 0], [1, 0, 0], r_obs=0.0),
+                                      [[0.0, 0.0, 0.0]], [[0.3, 0.0, 0.0]], 0.0)
+    inner, edge, out = near(0.05), near(float(np.nextafter(np.float32(r_d), np.float32(0)))), near(0.2)
+    assert edge.abs_sum[0] < 1e-5 * inner.abs_sum[0]
+    assert edge.term_sum[0] > 0.1 * inner.term_sum[0]
+    assert out.term_sum[0] == 0.0 and out.abs_sum[0] == 0.0
+    # taper: the ratio term / |f| grows towards the outer edge of the band
+    ag = _agents(1, k_f=KF, r_d=r_d, r_a=0.0, omega=[[0.0, 0.0, 1.0]])
+    ratios = []
+    for x in (0.08, 0.092, 0.096, 0.099):
+        pb = _problem_from_points([[0.0, x, 0.0]], ag, [0, 0, 0], [1, 0, 0], r_obs=0.0, cutoff=1)
+        r = oracle.repulsion(pb, [[0.0, 0.0, 0.0]], [[1.0, 0.0, 0.0]], 0.0)
+        ratios.append(r.term_sum[0] / r.abs_sum[0])
+    assert ratios[0] == pytest.approx(1.0, rel=1e-12)           # on the plateau: the force is one term
+    assert all(b > a for a, b in zip(ratios[1:], ratios[2:]))
+    # frame rounding on a moving sphere
+    ag = _agents(1, k_f=KF, r_d=r_d, r_a=0.0, omega=[[0.0, 0.0, 1.0]])
+    seg = dict(seg_begin=np.array([0, 1], np.int32), seg_vel=np.array([[1.0, 0.0, 0.0]], np.float32))
+
+    def frame(p, t):
+        pb = _problem_from_points([[0.0, 0.004, 0.0]], ag, [0, 0, 0], [1, 0, 0], r_obs=0.0, **seg)
+        return oracle.repulsion(pb, [p], [[0.0, 0.5, 0.0]], t)
+    assert frame([0.5, 0.0, 0.0], 0.0).shift_sum[0] == 0.0        # t = 0
+    assert frame([0.5, 0.0, 0.0], 0.25).shift_sum[0] == 0.0       # 0.5 - 0.25 is an FP32 number
+    p = [float(np.float32(0.05)), float(np.float32(0.003)), 0.0]
+    t = float(np.float32(0.001))                                   # 0.05 - 0.001 is not an FP32 number
+    r = frame(p, t)
+    assert r.shift_sum[0] > 0.0
+    # within the change of f over one FP32 step of the relative position (2^-24 of |p|, per axis)
+    step = 2.0 ** -24 * 0.1
+    r_up = frame([p[0] + step, p[1], p[2]], t)
+    assert r.shift_sum[0] <= 4 * np.linalg.norm(r_up.force[0] - r.force[0]) + 1e-12 * np.linalg.norm(r.force[0])
+
+
 def test_min_distance_matches_kdtree():
     """rho_min^(k) = max(nearest-centre distance - (r_O + r_a), eps): checked with scipy's k-d tree."""
     pb = scenes.config1()

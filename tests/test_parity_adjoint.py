@@ -37,12 +37,18 @@ def _gpu_grads(ctx, pb, w, ckpt=50):
 
 
 def _check(pb, gpu, ref, w, rel=5e-3, label=""):
-    """Per parameter column: |g_gpu - g_or| <= rel * max(|g_or|, 1e-3 max_i |g_or_i|): FP32 reverse-mode
-    rounding grows with the horizon, the floor covers near-zero entries."""
+    """Per parameter column: |g_gpu - g_or| <= rel * max(|g_or|, 1e-3 max_i |g_or_i|) + 16 * 2^-24 |w_i C_i| / theta:
+    FP32 reverse-mode rounding grows with the horizon, the first floor covers near-zero entries, the second
+    entries whose response to a relative change of the parameter theta (k_a, d_a, k_f; 1 for the unit vector
+    omega) lies below 16 FP32 roundings of the weighted cost, which an FP32 evaluation of the cost cannot
+    resolve."""
     exp = ref[:, 1:] * w[:, None]
     scale = np.abs(exp).max(0)
     err = np.abs(gpu - exp)
-    bound = rel * np.maximum(np.abs(exp), 1e-3 * scale[None, :]) + 1e-9
+    theta = np.stack([pb.agents.k_a, pb.agents.d_a, pb.agents.k_f] + [np.ones(pb.agents.n)] * 3, 1)
+    theta = np.abs(theta.astype(np.float64))
+    resolve = 16 * 2.0 ** -24 * np.abs(w * ref[:, 0])[:, None] / np.maximum(theta, 1e-30)
+    bound = rel * np.maximum(np.abs(exp), 1e-3 * scale[None, :]) + resolve + 1e-9
     worst = (err / bound).max(0)
     print(f"{label} adjoint worst err/bound per column " + ", ".join(f"{n} {v:.2e}" for n, v in zip(NAMES, worst)),
           flush=True)

@@ -18,7 +18,9 @@ compound through the next cycles' chaotic dynamics:
     previous i*; with those costs within the bounds above, any i* the oracle's rule
     picks on a cost vector inside those bounds is correct, which covers near ties;
   - the robot's control steps under that i* against the oracle's loop run with that
-    agent alone, from the same state: positions, velocities and clearances;
+    agent alone, from the same state: positions, velocities and clearances (steps that
+    one FP32 ulp of the agent's rotation vector, or 1e-5 of its gain, moves by more than
+    1e-4 m are held to twice that spread);
   - N_sw counts the changes of i* from a valid previous i*."""
 import copy
 
@@ -106,6 +108,23 @@ def _select(total, incumbent, alpha):
     return incumbent if best < 0 and inc_ok else best
 
 
+def _control_spread(one, J, ctrl_dt, ref):
+    """Largest change of the robot's position and velocity at each control step when the one agent's rotation
+    vector moves by one FP32 ulp either way or its gain k_f by 1e-5 relative (the perturbations of reading R24)."""
+    ps, vs = np.zeros(J + 1), np.zeros(J + 1)
+    for dw, kf in ((1, 1.0), (-1, 1.0), (0, 1.0 + 1e-5), (0, 1.0 - 1e-5)):
+        q = copy.deepcopy(one)
+        w = q.agents.omega.astype(np.float32)
+        if dw:
+            w = np.nextafter(w, np.float32(np.inf * dw))
+        q.agents.omega = np.ascontiguousarray(w)
+        q.agents.k_f = (q.agents.k_f.astype(np.float64) * kf).astype(np.float32)
+        r = oracle.plan_loop(q, 1, J, ctrl_dt)
+        ps = np.maximum(ps, np.abs(r.robot[:, :3] - ref.robot[:, :3]).max(1))
+        vs = np.maximum(vs, np.abs(r.robot[:, 3:] - ref.robot[:, 3:]).max(1))
+    return ps, vs
+
+
 LOOP_TILINGS = [None, (1, 8, 4, 0, 0, 2), (2, 1, 2, 0, 1, 1), (4, 4, 1, 64, 2, 1), (8, 2, 2, 0, 0, 1),
                 (1, 4, 8, 0, 1, 2)]
 
@@ -171,10 +190,17 @@ def test_random_planning_loops(ctx, seed, n_o, n_a, n_k, moving, cutoff, mixed, 
         ref = oracle.plan_loop(one, 1, J, ctrl_dt)
         assert int(ref.best[0]) == 0
         seg = robot[c * J:(c + 1) * J + 1].astype(np.float64)
-        pos_err = float(np.abs(seg[:, :3] - ref.robot[:, :3]).max())
-        vel_err = float(np.abs(seg[:, 3:] - ref.robot[:, 3:]).max())
-        assert pos_err <= gu.POS_TOL, (c, pos_err)
-        assert vel_err <= 10 * gu.POS_TOL, (c, vel_err)
+        pe = np.abs(seg[:, :3] - ref.robot[:, :3]).max(1)
+        ve = np.abs(seg[:, 3:] - ref.robot[:, 3:]).max(1)
+        pos_err, vel_err = float(pe.max()), float(ve.max())
+        p_spread, v_spread = _control_spread(one, J, ctrl_dt, ref)
+        if p_spread.max() <= gu.POS_TOL:
+            assert pos_err <= gu.POS_TOL, (c, pos_err)
+            assert vel_err <= 10 * gu.POS_TOL, (c, vel_err)
+        else:                          # ill-conditioned control steps (reading R24): the perturbed family's bar
+            n_ill += 1
+            assert (pe <= np.maximum(gu.POS_TOL, 2 * np.maximum.accumulate(p_spread))).all(), (c, pe, p_spread)
+            assert (ve <= np.maximum(10 * gu.POS_TOL, 2 * np.maximum.accumulate(v_spread))).all(), (c, ve, v_spread)
         rc, rr = clear[c * J:(c + 1) * J].astype(np.float64), ref.robot_clear
         fin = np.isfinite(rr)
         assert np.array_equal(np.isfinite(rc), fin), (c, rc, rr)

@@ -198,14 +198,16 @@ typedef struct {
     int32_t n_joints;      /* 1..7 */
     const float *links;    /* device [n_joints + 1][7]: L_i as rotor (w, x, y, z) and offset (x, y, z) */
     const float *q0;       /* device [n_joints]: start joint angles [rad] */
-    float damping;         /* lambda >= 0 of the damped pseudo-inverse (0: J_b^T (J_b J_b^T)^-1) */
+    float damping;         /* lambda >= 0 of the damped pseudo-inverse (0: J_b^T (J_b J_b^T)^-1, which needs
+                              n_joints >= 6 and gives non-finite joint rates at a singular configuration) */
 } gmapp_arm;
 
 /* Forward rollout of arm agents: outputs as gmapp_rollout_pose, plus joints:
  * device [N_a][N_k + 1][n_joints] joint angles (q0 + the sum of dt qdot, not wrapped)
  * or NULL.  EINVAL for a NULL arm, n_joints outside 1..7, NULL links or q0, a damping
- * that is not finite and >= 0, or a forced tiling (gmapp_set_tiling) with more than
- * 8 agents per group (each agent holds one lane per joint in a wave). */
+ * that is not finite and >= 0, damping 0 with fewer than 6 joints (J_b J_b^T, 6 x 6, is
+ * then singular), or a forced tiling (gmapp_set_tiling) with more than 8 agents per
+ * group (each agent holds one lane per joint in a wave). */
 gmapp_status gmapp_rollout_arm(gmapp_ctx *ctx, const gmapp_scene *scene, const gmapp_agents *agents,
                                const gmapp_pose_agents *pose, const gmapp_arm *arm, const gmapp_query *query,
                                const gmapp_pose_query *pose_query, const gmapp_params *params,

@@ -416,6 +416,8 @@ gmapp_status rollout_6d(gmapp_ctx *ctx, const gmapp_scene *scene, const gmapp_ag
         if (!arm->links || !arm->q0) return fail(ctx, GMAPP_EINVAL, "arm links and q0 must be non-NULL");
         if (!finite(arm->damping) || arm->damping < 0.0f)
             return fail(ctx, GMAPP_EINVAL, "damping must be finite and >= 0");
+        if (arm->damping == 0.0f && arm->n_joints < 6)   // J_b J_b^T (6 x 6) has rank <= n_joints
+            return fail(ctx, GMAPP_EINVAL, "damping 0 needs at least 6 joints (J_b J_b^T is singular)");
     }
     if (!finite(pose_query->w0[0]) || !finite(pose_query->w0[1]) || !finite(pose_query->w0[2]))
         return fail(ctx, GMAPP_EINVAL, "w0 must be finite");

@@ -61,7 +61,9 @@ def _check(pb, gpu, ref, sampled=False):
     j_err = float(np.abs(gpu["joints"].astype(np.float64) - ref["joints"]).max())
     assert j_err <= JOINT_TOL, j_err
     fin = np.isfinite(ref["min_clear"])
-    assert np.abs(gpu["min_clear"][fin] - ref["min_clear"][fin]).max() <= pos_err + 1e-6
+    assert np.array_equal(np.isfinite(gpu["min_clear"]), fin)
+    if fin.any():
+        assert np.abs(gpu["min_clear"][fin] - ref["min_clear"][fin]).max() <= pos_err + 1e-6
     tol = gu.cost_tolerances(pb, pos_err)
     d = np.abs(gpu["cost"].astype(np.float64) - ref["cost"])
     for k in range(3):
@@ -116,6 +118,10 @@ def test_arm_validation(ctx):
     with pytest.raises(gmapp.GmappError) as ei:
         ctx.rollout_arm(sc, ag, dpa, L9, q8, 0.01, pb.query, pq, pb.params)
     assert ei.value.status == gmapp.EINVAL
+    # the undamped pseudo-inverse needs J_b J_b^T (6 x 6) of full rank: at least 6 joints
+    with pytest.raises(gmapp.GmappError) as ei:
+        ctx.rollout_arm(sc, ag, dpa, Ld[:6].contiguous(), qd[:5].contiguous(), 0.0, pb.query, pq, pb.params)
+    assert ei.value.status == gmapp.EINVAL and "6 joints" in str(ei.value)
     # each agent holds one lane per joint in a wave: at most 8 agents per group
     ctx.set_tiling(16, 1, 1, 0, 0, 1)
     try:

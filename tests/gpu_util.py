@@ -38,6 +38,21 @@ def cost_tolerances(pb, pos_err):
     return np.array([1.01 * e / rc + 1e-6, 1.01 * e / rc + 1e-6, 1e-4, 2e-3, 0.0])
 
 
+def path_tolerance(pb, traj, ref_traj, floor):
+    """Per-agent bound on |dC_path| (Eq. 19), from the two trajectories themselves: the path length L moves by at
+    most the total variation of the position error along the path, sum_k |e_k - e_(k-1)|, plus the FP32 rounding of
+    the steps it sums (the device sums dt |v|, which differs from the stored position increments by one rounding of
+    each position); C_path = 1 - d1/L or 1 - L/d1 then moves by at most that over min(L, d1).  Never below `floor`."""
+    n = pb.params.n_steps
+    g, o = traj[:, :n].astype(np.float64), ref_traj[:, :n]
+    tv = np.linalg.norm(np.diff(g - o, axis=1), axis=2).sum(axis=1)
+    L = np.linalg.norm(np.diff(o, axis=1), axis=2).sum(axis=1)
+    d1 = np.linalg.norm(pb.query.goal.astype(np.float64) - o[:, 0], axis=1)
+    scale = np.abs(o).max(axis=(1, 2)) if o.size else np.zeros(len(o))
+    dL = tv + 2 * n * 2.0 ** -24 * scale + 4 * 2.0 ** -24 * L
+    return np.maximum(floor, dL / np.maximum(np.minimum(L, d1), 1e-12) + 1e-6)
+
+
 def check_selection(best_gpu, cost_or, cost_gpu, incumbent=-1, alpha=0.9):
     """The GPU's i* must be the oracle's, unless the oracle's cost gap to the
     GPU's choice is within max(1e-6, 2 max_i |C_gpu - C_or|)."""
@@ -50,9 +65,11 @@ def check_selection(best_gpu, cost_or, cost_gpu, incumbent=-1, alpha=0.9):
     return gap
 
 
-def compare_rollout(pb, gpu, ref, agents=None, pos_tol=POS_TOL):
+def compare_rollout(pb, gpu, ref, agents=None, pos_tol=POS_TOL, cost_spread=None):
     """Element-wise comparison of a GPU rollout with the oracle's (optionally on a
-    subset `agents` of the GPU's agents, ref computed on that subset)."""
+    subset `agents` of the GPU's agents, ref computed on that subset).  cost_spread [n, 5]:
+    how far one ulp of the inputs moves each cost (reading R24); each cost is held to at
+    least twice that."""
     idx = np.arange(pb.agents.n) if agents is None else np.asarray(agents)
     traj = gpu["traj"][idx].astype(np.float64)
     pos_err = float(np.abs(traj - ref.traj).max()) if traj.size else 0.0
@@ -66,13 +83,17 @@ def compare_rollout(pb, gpu, ref, agents=None, pos_tol=POS_TOL):
     cost = gpu["cost"][idx].astype(np.float64)
     tol = cost_tolerances(pb, pos_err)
     d = np.abs(cost - ref.cost)
-    rel_smooth = d[:, 3] / np.maximum(np.abs(ref.cost[:, 3]), 1e-3)
-    assert (d[:, 0] <= tol[0]).all(), ("C_goal", d[:, 0].max(), tol[0])
-    assert (d[:, 1] <= tol[1]).all(), ("C_obs", d[:, 1].max(), tol[1])
-    assert (d[:, 2] <= tol[2]).all(), ("C_path", d[:, 2].max(), tol[2])
-    assert (rel_smooth <= tol[3]).all(), ("C_smooth", rel_smooth.max(), tol[3])
-    tot_tol = tol[0] * abs(pb.params.w[0]) + tol[1] * abs(pb.params.w[1]) + tol[2] * abs(pb.params.w[2]) + \
-        tol[3] * abs(pb.params.w[3]) * np.maximum(np.abs(ref.cost[:, 3]), 1e-3) + 1e-6
+    spread = np.zeros_like(d) if cost_spread is None else 2.0 * np.asarray(cost_spread)
+    t_goal = np.maximum(tol[0], spread[:, 0])
+    t_obs = np.maximum(tol[1], spread[:, 1])
+    t_path = np.maximum(path_tolerance(pb, traj, ref.traj, tol[2]), spread[:, 2])
+    t_smooth = np.maximum(tol[3] * np.maximum(np.abs(ref.cost[:, 3]), 1e-3), spread[:, 3])
+    assert (d[:, 0] <= t_goal).all(), ("C_goal", d[:, 0].max(), tol[0])
+    assert (d[:, 1] <= t_obs).all(), ("C_obs", d[:, 1].max(), tol[1])
+    assert (d[:, 2] <= t_path).all(), ("C_path", d[:, 2].max(), t_path.min())
+    assert (d[:, 3] <= t_smooth).all(), ("C_smooth", (d[:, 3] / t_smooth).max())
+    tot_tol = np.maximum(t_goal * abs(pb.params.w[0]) + t_obs * abs(pb.params.w[1]) + t_path * abs(pb.params.w[2])
+                         + t_smooth * abs(pb.params.w[3]) + 1e-6, spread[:, 4])
     assert (d[:, 4] <= tot_tol).all(), ("C_total", d[:, 4].max())
     return pos_err
 
@@ -95,18 +116,20 @@ def force_bound(r):
             + r.shift_sum)
 
 
-def conditioning(pb, idx):
+def conditioning(pb, idx, with_costs=False):
     """Conditioning of the sampled agents idx (reading R24), from one oracle call that runs
     each agent five times: nominal; its rotation vector moved by one FP32 ulp up and down in
     every component; its circular-field gain k_f scaled by 1 +- 1e-5 (a repulsive force off
-    by the stated 1e-5 relative force tolerance at every step).
-      env[i]:       largest position change over the horizon under any of the four
+    by the stated 1e-5 relative force tolerance at every step); and two more calls with the
+    start position moved by one FP32 ulp up and down in every component.
+      env[i]:       largest position change over the horizon under any of the six
                     perturbations; above 1e-4 m the agent is ill-conditioned (the exact problem
                     does not fix its FP32 trajectory to the tolerance: one ulp of its inputs, or a
                     force within the per-step tolerance, moves it further);
-      env_step[i, k]: largest change of p^(k) under all four perturbations: the spread of the
-                    trajectories whose every step meets the force tolerance.
-    Returns (nominal oracle rollout of idx, env [m], env_step [m, N_k + 1])."""
+      env_step[i, k]: largest change of p^(k) under all six perturbations: the spread of the
+                    trajectories whose every step meets the force tolerance;
+      cost_spread[i, c]: largest change of cost component c under the six perturbations (with_costs).
+    Returns (nominal oracle rollout of idx, env [m], env_step [m, N_k + 1][, cost_spread [m, 5]])."""
     import copy
 
     import oracle
@@ -128,8 +151,18 @@ def conditioning(pb, idx):
     for f in ("traj", "cost", "min_clear", "force", "vel", "ftot"):
         setattr(nom, f, getattr(r, f)[:m])
     dev = [np.abs(r.traj[q * m:(q + 1) * m] - r.traj[:m]).max(2) for q in range(1, 5)]
+    cdev = [np.abs(r.cost[q * m:(q + 1) * m] - r.cost[:m]) for q in range(1, 5)]
+    for direction in (np.inf, -np.inf):             # the start position, one FP32 ulp off
+        moved = copy.deepcopy(pb)
+        moved.agents = pb.agents.subset(idx)
+        moved.query.p0 = np.nextafter(np.asarray(pb.query.p0, np.float32), np.float32(direction))
+        rm = oracle.rollout(moved)
+        dev.append(np.abs(rm.traj - r.traj[:m]).max(2))
+        cdev.append(np.abs(rm.cost - r.cost[:m]))
     env_step = np.maximum.reduce(dev)
     env = env_step.max(1)
+    if with_costs:
+        return nom, env, env_step, np.maximum.reduce(cdev)
     return nom, env, env_step
 
 
@@ -139,7 +172,7 @@ def compare_conditioned(pb, gpu, idx, label=""):
     (positions 1e-4 m, costs); the ill-conditioned ones step by step within
     max(1e-4 m, twice the largest spread of the perturbed trajectories so far).  Returns
     (worst error of the well-conditioned agents, number of ill-conditioned agents)."""
-    nom, env, env_step = conditioning(pb, idx)
+    nom, env, env_step, cost_spread = conditioning(pb, idx, with_costs=True)
     idx = np.asarray(idx)
     err = np.abs(gpu["traj"][idx].astype(np.float64) - nom.traj).max(2)
     ill = env > POS_TOL
@@ -157,5 +190,41 @@ def compare_conditioned(pb, gpu, idx, label=""):
         ref = copy.deepcopy(nom)
         for f in ("traj", "cost", "min_clear", "force", "vel", "ftot"):
             setattr(ref, f, getattr(nom, f)[good])
-        worst = compare_rollout(pb, gpu, ref, agents=idx[good])
+        worst = compare_rollout(pb, gpu, ref, agents=idx[good], cost_spread=cost_spread[good])
     return worst, int(ill.sum())
+
+
+def nearest_sphere_gap(pb, traj):
+    """Per agent, the smallest gap between the nearest and the second-nearest sphere centre over the steps at which
+    the nearest sphere is within r_c (where C_obs = mean(1 - min(rho_min, r_c) / r_c) depends on it).  At a gap of
+    zero the argmin in rho_min switches spheres: the cost has a kink there and its gradient two one-sided values.
+    traj: positions [N_a, >= N_k, 3] (p^(1..N_k) first)."""
+    sc, prm = pb.scene, pb.params
+    n_k = prm.n_steps
+    out = np.full(traj.shape[0], np.inf)
+    if sc.n < 2:
+        return out
+    P = np.stack([sc.x, sc.y, sc.z], 1).astype(np.float64)
+    V = np.zeros_like(P)
+    if sc.seg_begin is not None:
+        for s in range(sc.n_seg):
+            V[sc.seg_begin[s]:sc.seg_begin[s + 1]] = sc.seg_vel[s]
+    dt = float(np.float32(prm.dt))
+    t0 = float(np.float32(pb.query.t0))
+    R = float(np.float32(sc.r_obs)) + pb.agents.r_a.astype(np.float64)
+    rc = float(np.float32(prm.r_cost))
+    eps = float(np.float32(prm.eps))
+    if sc.seg_begin is None:                     # static: one k-d tree for every step
+        import scipy.spatial
+        two, _ = scipy.spatial.cKDTree(P).query(traj[:, :n_k].reshape(-1, 3), k=2)
+        two = two.reshape(traj.shape[0], n_k, 2)
+        near = np.maximum(two[..., 0] - R[:, None], eps) < rc
+        return np.where(near, two[..., 1] - two[..., 0], np.inf).min(axis=1)
+    for k in range(n_k):
+        Q = P + (t0 + k * dt) * V
+        d = np.linalg.norm(traj[:, k, None, :] - Q[None], axis=2)
+        two = np.partition(d, 1, axis=1)[:, :2]
+        near = np.maximum(two[:, 0] - R, eps) < rc
+        gap = np.where(near, two[:, 1] - two[:, 0], np.inf)
+        out = np.minimum(out, gap)
+    return out

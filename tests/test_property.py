@@ -1,6 +1,7 @@
 """Property sweep on the GPU: random tiny planning problems (N_O <= 64, N_a <= 8,
 N_k <= 20) under random tilings of the rollout kernel, each checked against the FP64
-oracle on positions (1e-4 m), costs, the selection rule, and the teacher-forced
+oracle on positions (1e-4 m; agents that one ulp of their inputs moves further are held
+to the spread of those perturbed runs, reading R24), costs, the selection rule, and the teacher-forced
 force of Alg. 1 at the oracle's own states (1e-5 relative).  The draws cover what
 fixed cases miss in combination: empty and one-point worlds, point counts that are
 not a multiple of the slices or tiles, shards with no points, coincident spheres, an
@@ -71,7 +72,7 @@ def test_random_tiny_problems(ctx, seed, n_o, n_a, n_k, moving, cutoff, coincide
           f"on_centre {on_centre} tiling {tiling}", flush=True)
     gpu = gu.gpu_rollout(ctx, pb, tiling=tiling)
     ref = oracle.rollout(pb)
-    gu.compare_rollout(pb, gpu, ref)
+    gu.compare_conditioned(pb, gpu, np.arange(n_a), label=f"seed {seed}")
     gu.check_selection(gpu["best"], ref.cost, gpu["cost"])
     # teacher-forced Alg. 1 response at the oracle's states of the first and the last step
     sc, ag = gmapp.scene_to_device(pb.scene), gmapp.agents_to_device(pb.agents)

@@ -7,6 +7,7 @@ import pytest
 
 import oracle
 from paper_2606_12579_amd import scenes
+from tests import gpu_util as gu
 
 pytestmark = pytest.mark.gpu
 
@@ -36,12 +37,12 @@ def _gpu_grads(ctx, pb, w, ckpt=50):
                            g["k_f"].cpu().numpy()[:, None], g["omega"].cpu().numpy()], 1).astype(np.float64)
 
 
-def _check(pb, gpu, ref, w, rel=5e-3, label=""):
+def _check(pb, gpu, ref, w, rel=5e-3, label="", fwd=None):
     """Per parameter column: |g_gpu - g_or| <= rel * max(|g_or|, 1e-3 max_i |g_or_i|) + 16 * 2^-24 |w_i C_i| / theta:
     FP32 reverse-mode rounding grows with the horizon, the first floor covers near-zero entries, the second
     entries whose response to a relative change of the parameter theta (k_a, d_a, k_f; 1 for the unit vector
     omega) lies below 16 FP32 roundings of the weighted cost, which an FP32 evaluation of the cost cannot
-    resolve."""
+    resolve.  fwd: the device's forward trajectories of the same agents, which place the kinks of C_obs."""
     exp = ref[:, 1:] * w[:, None]
     scale = np.abs(exp).max(0)
     err = np.abs(gpu - exp)
@@ -49,9 +50,20 @@ def _check(pb, gpu, ref, w, rel=5e-3, label=""):
     theta = np.abs(theta.astype(np.float64))
     resolve = 16 * 2.0 ** -24 * np.abs(w * ref[:, 0])[:, None] / np.maximum(theta, 1e-30)
     bound = rel * np.maximum(np.abs(exp), 1e-3 * scale[None, :]) + resolve + 1e-9
+    # an agent whose nearest two spheres are tied, at some step, to within what separates the device's
+    # trajectory from the oracle's sits on a kink of C_obs (the argmin of rho_min may switch there): its
+    # gradient has two one-sided values and either trajectory may take either; such agents are counted,
+    # not compared
+    kink = np.zeros(pb.agents.n, bool)
+    if fwd is not None:
+        orc = oracle.rollout(pb).traj
+        sep = np.abs(fwd.astype(np.float64) - orc).max(axis=(1, 2))
+        kink = gu.nearest_sphere_gap(pb, orc) <= 2 * sep + 1e-8
+    bound[kink] = np.inf
     worst = (err / bound).max(0)
-    print(f"{label} adjoint worst err/bound per column " + ", ".join(f"{n} {v:.2e}" for n, v in zip(NAMES, worst)),
-          flush=True)
+    print(f"{label} adjoint worst err/bound per column " + ", ".join(f"{n} {v:.2e}" for n, v in zip(NAMES, worst))
+          + f"; agents at a kink of C_obs: {int(kink.sum())} of {len(kink)}", flush=True)
+    assert kink.sum() <= max(1, len(kink) // 4), ("agents at a kink", int(kink.sum()), len(kink))
     assert (err <= bound).all(), (label, worst)
 
 
@@ -71,7 +83,7 @@ def test_adjoint_small(ctx, case):
     w = np.random.default_rng(0).uniform(0.5, 1.5, pb.agents.n).astype(np.float32)
     gpu = _gpu_grads(ctx, pb, w, ckpt)
     ref = oracle.rollout_grad(pb)
-    _check(pb, gpu, ref, w.astype(np.float64), label=case)
+    _check(pb, gpu, ref, w.astype(np.float64), label=case, fwd=gu.gpu_rollout(ctx, pb)["traj"])
 
 
 def test_adjoint_config4_sampled(ctx):
@@ -85,7 +97,7 @@ def test_adjoint_config4_sampled(ctx):
     sub = copy.deepcopy(pb)
     sub.agents = pb.agents.subset(idx)
     ref = oracle.rollout_grad(sub)
-    _check(sub, gpu[idx], ref, w[idx].astype(np.float64), label="config4")
+    _check(sub, gpu[idx], ref, w[idx].astype(np.float64), label="config4", fwd=gu.gpu_rollout(ctx, pb)["traj"][idx])
 
 
 def test_autograd_function(ctx):

@@ -9,6 +9,7 @@ from hypothesis import strategies as st
 
 import oracle
 from paper_2606_12579_amd import scenes
+from tests import gpu_util as gu
 from tests.test_parity_adjoint import _check, _gpu_grads
 
 pytestmark = pytest.mark.gpu
@@ -36,4 +37,4 @@ def test_random_adjoint(ctx, seed, n_o, n_a, n_k, moving, ckpt, kf):
     print(f"seed {seed} N_O {n_o} N_a {n_a} N_k {n_k} moving {moving} ckpt {ckpt} k_f {kf}", flush=True)
     gpu = _gpu_grads(ctx, pb, w, ckpt)
     ref = oracle.rollout_grad(pb)
-    _check(pb, gpu, ref, w.astype(np.float64), label=f"seed {seed}")
+    _check(pb, gpu, ref, w.astype(np.float64), label=f"seed {seed}", fwd=gu.gpu_rollout(ctx, pb)["traj"])

@@ -2,7 +2,7 @@
 
 Pose agents (gmapp_rollout_pose, Eqs. 6-11 on Spin(3) x| R^3): random tiny problems
 (N_O 1-120, N_a 1-8, N_k 2-40, moving or static, cut-off or taper, random gains,
-start rotor, goal and initial twist) under random tilings against the FP64 oracle
+start rotor, goal and initial twist, homogeneous or mixed heuristics) under random tilings against the FP64 oracle
 (positions, rotors, clearances and costs with the bounds of the fixed pose tests).
 
 Voxel pass (Sec. IV-B lattice): random point clouds on random lattices (voxel size,
@@ -18,6 +18,7 @@ import oracle
 from oracle import perception as op
 from paper_2606_12579_amd import scenes
 from tests.test_parity_pose import _compare, _gpu
+from tests.test_property_loop import _mix
 
 pytestmark = pytest.mark.gpu
 
@@ -43,12 +44,15 @@ POSE_TILINGS = [None, (1, 8, 4, 0, 0, 2), (2, 8, 2, 0, 1, 2), (1, 4, 1, 0, 1, 2)
 
 @settings(max_examples=40, **SETTINGS)
 @given(seed=st.integers(0, 2 ** 31 - 1), n_o=st.integers(1, 120), n_a=st.integers(1, 8), n_k=st.integers(2, 40),
-       moving=st.booleans(), cutoff=st.integers(0, 1), tiling=st.sampled_from(POSE_TILINGS))
-def test_random_pose_problems(ctx, seed, n_o, n_a, n_k, moving, cutoff, tiling):
+       moving=st.booleans(), cutoff=st.integers(0, 1), mixed=st.booleans(), tiling=st.sampled_from(POSE_TILINGS))
+def test_random_pose_problems(ctx, seed, n_o, n_a, n_k, moving, cutoff, mixed, tiling):
     pb = scenes.tiny(seed, n_points=n_o, n_agents=n_a, n_steps=n_k, moving=moving, cutoff=cutoff)
+    if mixed:                                   # every agent its own heuristic, r_d and k_f
+        pb = _mix(pb, np.random.default_rng(seed + 3))
     rng = np.random.default_rng(seed)
     pa, pq = scenes.pose_agents(rng, n_a), scenes.pose_query(rng)
-    print(f"seed {seed} N_O {n_o} N_a {n_a} N_k {n_k} moving {moving} cutoff {cutoff} tiling {tiling}", flush=True)
+    print(f"seed {seed} N_O {n_o} N_a {n_a} N_k {n_k} moving {moving} cutoff {cutoff} mixed {mixed} tiling {tiling}",
+          flush=True)
     ref = oracle.rollout_pose(pb, pa, pq)
     _compare(pb, _gpu(ctx, pb, pa, pq, tiling), ref)
 

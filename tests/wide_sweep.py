@@ -57,7 +57,7 @@ def draw(rng, mode):
         return dict(seed=seed, n_o=i(1, 150), n_a=i(1, 8), n_k=i(2, 60), moving=b(), ckpt=i(1, 64),
                     kf=[0.005, 0.01, 0.02][i(0, 2)])
     if mode == "pose":
-        return dict(seed=seed, n_o=i(1, 120), n_a=i(1, 8), n_k=i(2, 40), moving=b(), cutoff=i(0, 1),
+        return dict(seed=seed, n_o=i(1, 120), n_a=i(1, 8), n_k=i(2, 40), moving=b(), cutoff=i(0, 1), mixed=b(),
                     tiling=tpv.POSE_TILINGS[i(0, len(tpv.POSE_TILINGS) - 1)])
     if mode == "voxel":
         return dict(seed=seed, n=i(0, 3000), voxel=[0.001, 0.003, 0.01, 0.25][i(0, 3)],
@@ -66,7 +66,8 @@ def draw(rng, mode):
                     cap_frac=[0.0, 0.5, 1.0, 2.0][i(0, 3)], static=b())
     if mode == "arm":
         return dict(seed=seed, n_a=i(1, 8), n_o=i(0, 200), n_k=i(2, 40), moving=b(), joints=i(1, 7),
-                    damping=[0.0, 0.01, 0.1][i(0, 2)], tiling=tar.ARM_TILINGS[i(0, len(tar.ARM_TILINGS) - 1)])
+                    damping=[0.0, 0.01, 0.1][i(0, 2)], mixed=b(),
+                    tiling=tar.ARM_TILINGS[i(0, len(tar.ARM_TILINGS) - 1)])
     if mode == "server":
         reqs = [(i(0, 2 ** 31 - 1), i(0, 200), i(0, 12), i(1, 60), b(), i(0, 1), b()) for _ in range(i(1, 6))]
         return dict(reqs=reqs, budget=[1 << 20, 64 << 20][i(0, 1)], slots=i(1, 4), quantum=i(1, 32), spread=b())

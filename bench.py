@@ -544,10 +544,11 @@ def batched_vs_per_scene(ctx, dev, reqs, proxy_steps=16):
                          ctx.outputs(j.agents.n, j.params.n_steps, traj=True, min_clear=False)) for j in sample]
     ctx.rollout_batch(tj, stream=stream)
     # conditioning of every sampled agent, on the GPU: the per-scene trajectory with each
-    # agent's rotation vector moved one FP32 ulp up and down in every component, and with
-    # its k_f scaled by 1 +- 1e-5 (a repulsive force off by the per-step force tolerance);
-    # an agent whose trajectory moves more than 1e-4 m under any of them is ill-conditioned
-    # (the parity tests classify agents the same way against the FP64 oracle)
+    # agent's rotation vector moved one FP32 ulp up and down in every component, with its
+    # k_f scaled by 1 +- 1e-5 (a repulsive force off by the per-step force tolerance), and
+    # with the start position one FP32 ulp up and down in every component; an agent whose
+    # trajectory moves more than 1e-4 m under any of them is ill-conditioned (the parity
+    # tests classify agents the same way against the FP64 oracle)
     import dataclasses
     pos, env = [], []
     for j in tj:
@@ -557,8 +558,12 @@ def batched_vs_per_scene(ctx, dev, reqs, proxy_steps=16):
         perturbed = [dataclasses.replace(j.agents, omega=torch.nextafter(
                          j.agents.omega, torch.full_like(j.agents.omega, d))) for d in (float("inf"), float("-inf"))]
         perturbed += [dataclasses.replace(j.agents, k_f=j.agents.k_f * f) for f in (1.0 + 1e-5, 1.0 - 1e-5)]
-        for pa in perturbed:
-            op = ctx.rollout(j.scene, pa, j.query, j.params, traj=True, min_clear=False, stream=stream)
+        runs = [(pa, j.query) for pa in perturbed]
+        runs += [(j.agents, dataclasses.replace(j.query, p0=np.nextafter(np.asarray(j.query.p0, np.float32),
+                                                                           np.float32(d))))
+                 for d in (np.inf, -np.inf)]
+        for pa, q in runs:
+            op = ctx.rollout(j.scene, pa, q, j.params, traj=True, min_clear=False, stream=stream)
             e = torch.maximum(e, (op["traj"] - nom).abs().amax(dim=(1, 2)))
         torch.cuda.synchronize()
         pos.append((j.out["traj"] - nom).abs().amax(dim=(1, 2)).cpu().numpy())

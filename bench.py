@@ -586,8 +586,9 @@ def batched_vs_per_scene(ctx, dev, reqs, proxy_steps=16):
                                "pass": bool((pos[well] <= 1e-4).all()),
                                "note": "batched vs per-scene launch, both FP32, for every agent of 16 evenly "
                                        "spaced requests; ill-conditioned: the per-scene trajectory moves more "
-                                       "than 1e-4 m when the agent's rotation vector moves one FP32 ulp or its "
-                                       "k_f by 1e-5 relative; pass: every other agent within 1e-4 m (the parity "
+                                       "than 1e-4 m when the agent's rotation vector or the start position moves "
+                                       "one FP32 ulp, or its k_f by 1e-5 relative; pass: every other agent within "
+                                       "1e-4 m (the parity "
                                        "tests hold both kinds against the FP64 oracle)"}}
 
 

@@ -83,8 +83,9 @@ typedef struct {
  * same field with the current of Eq. (3) taken from the relative velocity w,
  * c = w - n (n . w) (omega unused); GMAPP_H_APF the artificial potential field of
  * Eq. (1), f = k_f (1/rho - 1/r_d) (1/rho^2) d/|d| with the surface distance rho.
- * Heterogeneous agents run in gmapp_rollout and gmapp_force_probe; the batched,
- * adjoint and served entry points require heuristic = NULL (EINVAL otherwise). */
+ * Heterogeneous agents run in gmapp_rollout, gmapp_rollout_pose, gmapp_rollout_arm,
+ * gmapp_plan_loop, gmapp_control_force and gmapp_force_probe; the batched, adjoint
+ * and served entry points require heuristic = NULL (EINVAL otherwise). */
 #define GMAPP_H_CF_OMEGA 0
 #define GMAPP_H_MFI_VEL 1
 #define GMAPP_H_APF 2

@@ -227,6 +227,22 @@ def test_force_tolerance_terms_cancellation_and_frame():
     assert r.shift_sum[0] <= 4 * np.linalg.norm(r_up.force[0] - r.force[0]) + 1e-12 * np.linalg.norm(r.force[0])
 
 
+def test_repulsion_diagnostics_do_not_change_the_force():
+    """The tolerance diagnostics are computed beside the force, never into it: with and without them the force
+    and rho_min are identical, and without them the diagnostics read zero."""
+    pb = scenes.tiny(9, n_points=50, n_agents=6, n_steps=5, moving=True)
+    pb.agents = scenes.multi_agents(np.random.default_rng(2), 6)
+    rng = np.random.default_rng(3)
+    p = rng.uniform(-0.02, 0.06, (6, 3))
+    v = rng.normal(size=(6, 3))
+    a = oracle.repulsion(pb, p, v, 0.003)
+    b = oracle.repulsion(pb, p, v, 0.003, diagnostics=False)
+    assert np.array_equal(a.force, b.force) and np.array_equal(a.rho_min, b.rho_min)
+    for f in ("abs_sum", "edge_sum", "edge_cnt", "term_sum", "shift_sum"):
+        assert not np.any(getattr(b, f)), f
+    assert (a.term_sum >= a.abs_sum).all() and (a.shift_sum > 0).any()
+
+
 def test_min_distance_matches_kdtree():
     """rho_min^(k) = max(nearest-centre distance - (r_O + r_a), eps): checked with scipy's k-d tree."""
     pb = scenes.config1()
